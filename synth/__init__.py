@@ -1,0 +1,7 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+Holds meshes, bases, EQ sets and evaluation points only; none of the
+method's arithmetic lives here.
+"""
+from .mesh import Mesh, structured_mesh  # noqa: F401
+from .inputs import Workload, tiny_burgers, euler_p2, with_eq, orthonormal_columns  # noqa: F401
