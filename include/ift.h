@@ -1,0 +1,186 @@
+/*
+ * ift.h -- C ABI of the EQ-hyperreduced implicit-feature-tracking assembly
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for a DG discretisation of a 2-D conservation law
+ * posed on a reference domain deformed by a mapping x = X + Psi tau, the
+ * element residuals R_e and mesh-distortion residuals N_e, their Jacobians,
+ * and the empirical-quadrature (EQ) weighted reduced quantities of
+ * Mirhoseini & Zahr, "Accelerated solutions of convection-dominated partial
+ * differential equations using implicit feature tracking and empirical
+ * quadrature":
+ *   - the full-order element loop of eq. (hdm_elem) / (hdm_elem_jac1)
+ *     (hdm_assemble);
+ *   - the hyperreduced objective J~ of eq. (ift-opt-eqp2) and the stacked
+ *     residual F~ of eq. (ift-eqp-res) (eq_assemble_residual);
+ *   - the hyperreduced residuals [S~; T~] = J~_z^T F~ of eq. (ift-eqp-res0)
+ *     and the Gauss-Newton matrix J~_z^T J~_z of eq. (levmarq-elem)
+ *     (eq_assemble_jacobian);
+ *   - one Levenberg-Marquardt step of eq. (levmarq-step)/(lmstep) with a
+ *     sufficient-decrease line search (rom_gauss_newton_step).
+ *
+ * Conventions (all arrays row-major, FP64 at the boundary):
+ *   - element nodes: 3 vertices (counter-clockwise), then for degree 2 the
+ *     mid-edge nodes of edges 0,1,2; edge f joins vertex f and vertex f+1;
+ *     face f of an element is edge f.  The mapping has the degree of the
+ *     solution (q = p), so geometry nodes and solution nodes coincide per
+ *     element.
+ *   - state U[(e*nn + i)*nc + c] (element-major; DG blocks are disjoint);
+ *     mapping coefficients x[2*gnode + d].
+ *   - element DoFs U_e (nue = nn*nc), neighbour face-trace DoFs U_e'
+ *     (nun = 3*(p+1)*nc: for face f and edge node k ordered from vertex f to
+ *     vertex f+1, the neighbour's DoFs at that node; zero on boundary faces),
+ *     element mapping DoFs x_e (nxe = 2*nn).
+ *   - mu: host pointer; Burgers: mu[0] (inflow u_b = 1 + bc_mu_scale*mu[0]),
+ *     Euler: mu[0] = free-stream Mach number, mu[1] = inflow angle (deg).
+ *   - unless stated otherwise, every array argument is a DEVICE pointer
+ *     owned by the caller; the library never frees caller memory.
+ *   - every call runs on the caller's stream and returns after enqueueing
+ *     the work, except where it says it synchronises.
+ *
+ * Errors: calls return an ift_status.  Negative values are hard errors
+ * (arguments rejected before any work was enqueued, or a HIP failure);
+ * outputs are then unspecified.  Invalid geometry (mapping Jacobian
+ * determinant g <= eps_g at a volume quadrature point) or a non-physical
+ * Euler state (rho <= 0 or p <= 0 at a flux evaluation point) at an
+ * evaluation point is a soft outcome: the objective is +inf and the element
+ * is counted in n_bad; a line search then rejects the point.
+ *
+ * Handles are not thread-safe: use one handle on one stream at a time.
+ */
+#ifndef IFT_H
+#define IFT_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IFT_OK = 0,
+  IFT_EINVAL = -1,      /* bad argument (null pointer, size, index, mesh)  */
+  IFT_ENOMEM = -2,      /* device allocation failed                        */
+  IFT_EDEVICE = -3,     /* HIP runtime error                               */
+  IFT_EBADMESH = -4,    /* invalid geometry at the evaluation point        */
+  IFT_ENONPHYS = -5,    /* non-physical state at the evaluation point      */
+  IFT_ESINGULAR = -6,   /* Gauss-Newton matrix not positive definite        */
+  IFT_ELINESEARCH = -7, /* no sufficient decrease within max_backtrack      */
+  IFT_ENOTCONV = -8     /* iteration limit reached                          */
+} ift_status;
+
+typedef enum { IFT_BURGERS2D = 0, IFT_EULER2D = 1 } ift_pde;
+
+/* Element arithmetic precision (the boundary is always FP64). */
+typedef enum { IFT_FP64 = 0, IFT_FP32_ELEM = 1 } ift_precision;
+
+typedef struct ift_problem ift_problem;
+typedef struct ift_rom ift_rom;
+
+/* Mesh and discretisation.  All pointers are HOST pointers, copied at
+ * creation.  elem_nbr[e*3+f] is the element across face f or -tag with tag
+ * 1 (left), 2 (right), 3 (bottom), 4 (top); interior neighbours must be
+ * mutual.  Boundary states (Section 4 reading): Burgers tags 1,3 inflow
+ * u+ = 1 + bc_mu_scale*mu[0], tags 2,4 outflow u+ = u-; Euler tag 1
+ * supersonic inflow u+ = U_inf(mu), tag 2 supersonic outflow, tags 3,4 slip
+ * walls; all_farfield != 0 makes every Euler tag an inflow. */
+typedef struct {
+  ift_pde pde;
+  int p;                   /* DG degree = mapping degree, 1 or 2          */
+  int n_elem;
+  int n_gnode;
+  const double* X;         /* [n_gnode][2] reference node coordinates      */
+  const int* elem_gnodes;  /* [n_elem][nn] geometry node ids               */
+  const int* elem_nbr;     /* [n_elem][3]                                  */
+  double gamma;            /* ratio of specific heats (Euler)              */
+  double kappa;            /* distortion weight, eq. (dist_elem0)          */
+  double eps_g;            /* eps of eq. (dist_elem1); also validity bound */
+  double bc_mu_scale;      /* Burgers inflow scale                         */
+  int all_farfield;
+} ift_problem_desc;
+
+ift_status ift_problem_create(const ift_problem_desc* desc, ift_problem** out);
+void ift_problem_destroy(ift_problem* prob);
+/* Sizes of the problem: nue, nun, nxe, N_u, N_x (any may be NULL). */
+ift_status ift_problem_sizes(const ift_problem* prob, int* nue, int* nun, int* nxe,
+                             long long* N_u, long long* N_x);
+
+/* Full-order element loop over all n_elem elements (eq. (hdm_elem) and
+ * eq. (hdm_elem_jac1), distortion eq. (dist_elem0)-(dist_elem1)).
+ * In: U [N_u], x [N_x].  Out (each may be NULL to skip):
+ *   R [N_u] global residual (element blocks are disjoint, P_e^T P_E = delta),
+ *   N [n_elem], dRdU [n_elem][nue][nue], dRdUn [n_elem][nue][nun],
+ *   dRdx [n_elem][nue][nxe], dNdx [n_elem][nxe],
+ *   n_bad [1] (int): elements with invalid geometry or state.
+ * The Jacobian blocks are computed only if at least one of them is
+ * requested. */
+ift_status hdm_assemble(ift_problem* prob, const double* mu, const double* U, const double* x,
+                        double* R, double* N, double* dRdU, double* dRdUn, double* dRdx,
+                        double* dNdx, int* n_bad, hipStream_t stream);
+
+/* Reduced-order model with EQ set {(e_k, rho_k)}, k < n_s.  Phi [N_u][n]
+ * and Psi [N_x][m] are DEVICE pointers, only read during creation;
+ * eq_elem [n_s] and eq_rho [n_s] are HOST pointers (rho_k >= 0).  Creation
+ * gathers Phi_e = P_e^T Phi, Phi_e' = P_e'^T Phi, Psi_e = Q_e^T Psi and
+ * X_e = Q_e^T X for every sampled element (end of Section 3.0) into
+ * library-owned device memory and allocates all workspaces; no later call
+ * allocates.  Limits: 1 <= n, 0 <= m, n + m <= 64, n_s >= 1.
+ * Synchronises the stream of the default device context. */
+ift_status ift_rom_create(ift_problem* prob, int n, int m, const double* Phi, const double* Psi,
+                          int n_s, const int* eq_elem, const double* eq_rho,
+                          ift_precision precision, ift_rom** out);
+void ift_rom_destroy(ift_rom* rom);
+/* Copies of the gathered operands (device outputs, bit-exact copies of the
+ * rows of Phi, Psi, X): Phi_s [n_s][nue][n], Phin_s [n_s][nun][n] (zero rows on
+ * boundary faces), Psi_s [n_s][nxe][m], X_s [n_s][nxe]; any may be NULL. */
+ift_status ift_rom_get_gathers(ift_rom* rom, double* Phi_s, double* Phin_s, double* Psi_s,
+                               double* X_s, hipStream_t stream);
+
+/* Hyperreduced residual at z = (w [n], tau [m]) (device inputs):
+ *   Jobj [1]  = sum_k rho_k/2 (|R_e|^2 + N_e^2), +inf if invalid,
+ *   Ft [n_s*nue + n_s] = [sqrt(rho_k) R_e (k-major) ; sqrt(rho_k) N_e] or NULL,
+ *   PhiT_r [n] = sum_k rho_k Phi_e^T R_e or NULL,
+ *   n_bad [1] (int) or NULL. */
+ift_status eq_assemble_residual(ift_rom* rom, const double* mu, const double* w, const double* tau,
+                                double* Jobj, double* Ft, double* PhiT_r, int* n_bad,
+                                hipStream_t stream);
+
+/* Hyperreduced gradient and Gauss-Newton matrix at z = (w, tau):
+ *   Jobj [1] as above,
+ *   g [n+m] = [S~; T~] (eq. (ift-eqp-res0)),
+ *   H [n+m][n+m] = J~_z^T J~_z (eq. (levmarq-elem)),
+ *   Jt [n_s*nue + n_s][n+m] = rows sqrt(rho_k)[A_e B_e] then sqrt(rho_k)[0 a_e]
+ *     with A_e = dR_e/dU_e Phi_e + dR_e/dU_e' Phi_e', B_e = dR_e/dx_e Psi_e,
+ *     a_e = dN_e/dx_e Psi_e, or NULL,
+ *   n_bad [1] or NULL. */
+ift_status eq_assemble_jacobian(ift_rom* rom, const double* mu, const double* w, const double* tau,
+                                double* Jobj, double* g, double* H, double* Jt, int* n_bad,
+                                hipStream_t stream);
+
+typedef struct {
+  double lambda;       /* LM weight on the tau block (0 = Gauss-Newton)     */
+  double c1;           /* sufficient-decrease constant (1e-4)               */
+  int max_backtrack;   /* step halvings (30)                                */
+  double tol;          /* |S~| <= tol and |T~| <= tol (1e-8)                */
+} ift_gn_params;
+
+typedef struct {
+  double J_old, J_new, alpha, norm_S, norm_T; /* norms at the input point  */
+  int n_backtrack;
+  int converged;       /* input point meets tol; no step taken              */
+  int status;          /* an ift_status                                     */
+} ift_gn_info;
+
+/* One Levenberg-Marquardt step from z_n = (w, tau) (device, in/out):
+ * assemble at z_n; if |S~| <= tol and |T~| <= tol report convergence;
+ * otherwise solve (H + lambda diag(0, I)) dz = -g (FP64 Cholesky) and
+ * backtrack alpha = 1, 1/2, ... until J~(z + alpha dz) <= J~(z) +
+ * c1 alpha g.dz, then overwrite (w, tau).  info is a HOST pointer.
+ * Synchronises the stream. */
+ift_status rom_gauss_newton_step(ift_rom* rom, const double* mu, double* w, double* tau,
+                                 const ift_gn_params* params, ift_gn_info* info, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IFT_H */

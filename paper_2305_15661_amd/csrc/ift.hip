@@ -1,0 +1,683 @@
+// Host side of the C ABI declared in include/ift.h: argument validation,
+// mesh preprocessing (face pairing and gather maps), reference-element
+// tables, workspace management and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ift.h"
+#include "kernels.hpp"
+
+namespace ift {
+__constant__ RefTab c_tab[2];
+}
+
+using namespace ift;
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return IFT_EDEVICE;           \
+  } while (0)
+
+struct ift_problem {
+  int pde = 0, p = 1, n_elem = 0, n_gnode = 0;
+  int nn = 3, nc = 1, nue = 3, nun = 6, nxe = 6;
+  long long N_u = 0, N_x = 0;
+  double gamma = 1.4, kappa = 0.0, eps_g = 1e-8, bc_mu_scale = 0.5;
+  int all_farfield = 0;
+  std::vector<int> h_gn, h_face;
+  std::vector<long long> h_Pn;
+  std::vector<double> h_X;
+  int* d_gn = nullptr;
+  int* d_face = nullptr;
+  int* d_Pn = nullptr;
+  double* d_X = nullptr;
+  int* d_flags = nullptr;
+};
+
+struct ift_rom {
+  ift_problem* prob = nullptr;
+  int n = 0, m = 0, D = 0, n_s = 0;
+  ift_precision precision = IFT_FP64;
+  int* d_eq = nullptr;
+  double* d_rho = nullptr;
+  double* d_srho = nullptr;
+  double* d_Phi_s = nullptr;
+  double* d_Phin_s = nullptr;
+  double* d_Psi_s = nullptr;
+  double* d_X_s = nullptr;
+  // workspaces
+  long long nrows = 0;
+  int n_gram_blk = 0;
+  double* d_Jt = nullptr;
+  double* d_Ft = nullptr;
+  double* d_Jpart = nullptr;
+  int* d_flags = nullptr;
+  double* d_PTR = nullptr;
+  double* d_gram_part = nullptr;
+  // Gauss-Newton state
+  double* d_H = nullptr;
+  double* d_g = nullptr;
+  double* d_J = nullptr;
+  double* d_Jtrial = nullptr;
+  double* d_dz = nullptr;
+  double* d_solve_out = nullptr;
+  double* d_wt = nullptr;
+  double* d_tt = nullptr;
+  int* d_nbad = nullptr;
+  int* d_flag_or = nullptr;
+};
+
+// --------------------------------------------------------- reference tables
+// Closed forms: barycentric Lagrange bases of degree 1 and 2; the 3-point
+// degree-2 rule; the 6-point degree-4 rule of Dunavant (1985) in its
+// closed form; Gauss-Legendre with p+1 points on [0, 1].
+static void build_tables(int p, RefTab& t) {
+  std::memset(&t, 0, sizeof(t));
+  const int nn = (p + 1) * (p + 2) / 2;
+  std::vector<double> qx, qy, qw;
+  if (p == 1) {
+    const double a = 1.0 / 6.0, b = 2.0 / 3.0;
+    qx = {a, b, a};
+    qy = {a, a, b};
+    qw = {1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+  } else {
+    const double s10 = std::sqrt(10.0);
+    const double r = std::sqrt(38.0 - 44.0 * std::sqrt(0.4));
+    const double a1 = (8.0 - s10 + r) / 18.0, a2 = (8.0 - s10 - r) / 18.0;
+    const double rw = std::sqrt(213125.0 - 53320.0 * s10);
+    const double w1 = 0.5 * (620.0 + rw) / 3720.0, w2 = 0.5 * (620.0 - rw) / 3720.0;
+    for (double a : {a1, a2}) {
+      const double w = (a == a1) ? w1 : w2;
+      const double c = 1.0 - 2.0 * a;
+      qx.insert(qx.end(), {a, c, a});
+      qy.insert(qy.end(), {a, a, c});
+      qw.insert(qw.end(), {w, w, w});
+    }
+  }
+  const int nq = (int)qw.size();
+  for (int q = 0; q < nq; ++q) {
+    const double xi = qx[q], eta = qy[q];
+    const double l[3] = {1.0 - xi - eta, xi, eta};
+    const double dl[3][2] = {{-1.0, -1.0}, {1.0, 0.0}, {0.0, 1.0}};
+    t.wv[q] = qw[q];
+    for (int i = 0; i < 3; ++i) {
+      if (p == 1) {
+        t.phiv[q][i] = l[i];
+        t.dphiv[q][i][0] = dl[i][0];
+        t.dphiv[q][i][1] = dl[i][1];
+      } else {
+        t.phiv[q][i] = l[i] * (2.0 * l[i] - 1.0);
+        t.dphiv[q][i][0] = (4.0 * l[i] - 1.0) * dl[i][0];
+        t.dphiv[q][i][1] = (4.0 * l[i] - 1.0) * dl[i][1];
+      }
+    }
+    if (p == 2) {
+      for (int f = 0; f < 3; ++f) {
+        const int a = f, b = (f + 1) % 3;
+        t.phiv[q][3 + f] = 4.0 * l[a] * l[b];
+        t.dphiv[q][3 + f][0] = 4.0 * (l[b] * dl[a][0] + l[a] * dl[b][0]);
+        t.dphiv[q][3 + f][1] = 4.0 * (l[b] * dl[a][1] + l[a] * dl[b][1]);
+      }
+    }
+  }
+  std::vector<double> s, ws;
+  if (p == 1) {
+    const double h = 0.5 / std::sqrt(3.0);
+    s = {0.5 - h, 0.5 + h};
+    ws = {0.5, 0.5};
+  } else {
+    const double h = 0.5 * std::sqrt(0.6);
+    s = {0.5 - h, 0.5, 0.5 + h};
+    ws = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  }
+  for (int q = 0; q <= p; ++q) {
+    const double x = s[q];
+    t.wf[q] = ws[q];
+    if (p == 1) {
+      t.L[q][0] = 1.0 - x;
+      t.L[q][1] = x;
+      t.dL[q][0] = -1.0;
+      t.dL[q][1] = 1.0;
+    } else {
+      t.L[q][0] = 2.0 * (x - 0.5) * (x - 1.0);
+      t.L[q][1] = -4.0 * x * (x - 1.0);
+      t.L[q][2] = 2.0 * x * (x - 0.5);
+      t.dL[q][0] = 4.0 * x - 3.0;
+      t.dL[q][1] = -8.0 * x + 4.0;
+      t.dL[q][2] = 4.0 * x - 1.0;
+    }
+  }
+  for (int f = 0; f < 3; ++f) {
+    t.en[f][0] = f;
+    if (p == 1) {
+      t.en[f][1] = (f + 1) % 3;
+    } else {
+      t.en[f][1] = 3 + f;
+      t.en[f][2] = (f + 1) % 3;
+    }
+  }
+  for (int i = 0; i < 6; ++i)
+    for (int f = 0; f < 3; ++f) {
+      t.nfk[i][f] = -1;
+      if (i < nn)
+        for (int k = 0; k <= p; ++k)
+          if (t.en[f][k] == i) t.nfk[i][f] = k;
+    }
+}
+
+static bool g_tables_ready = false;
+
+static ift_status ensure_tables() {
+  if (g_tables_ready) return IFT_OK;
+  RefTab t[2];
+  build_tables(1, t[0]);
+  build_tables(2, t[1]);
+  HIP_TRY(hipMemcpyToSymbol(HIP_SYMBOL(c_tab), t, sizeof(t)));
+  g_tables_ready = true;
+  return IFT_OK;
+}
+
+template <class T>
+static ift_status dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc((void**)p, count * sizeof(T)) != hipSuccess) return IFT_ENOMEM;
+  return IFT_OK;
+}
+
+template <class T>
+static void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+static PhysConst phys_const(const ift_problem* pr, const double* mu) {
+  PhysConst pc;
+  std::memset(&pc, 0, sizeof(pc));
+  pc.gamma = pr->gamma;
+  pc.all_farfield = pr->all_farfield;
+  if (pr->pde == IFT_BURGERS2D) {
+    pc.uinf[0] = 1.0 + pr->bc_mu_scale * mu[0];
+  } else {
+    const double M = mu[0];
+    const double a = mu[1] * (M_PI / 180.0);
+    const double c = std::sqrt(pr->gamma);
+    pc.uinf[0] = 1.0;
+    pc.uinf[1] = M * c * std::cos(a);
+    pc.uinf[2] = M * c * std::sin(a);
+    pc.uinf[3] = 1.0 / (pr->gamma - 1.0) + 0.5 * pr->gamma * M * M;
+  }
+  return pc;
+}
+
+static bool finite_mu(const ift_problem* pr, const double* mu) {
+  if (!mu) return false;
+  const int nmu = pr->pde == IFT_BURGERS2D ? 1 : 2;
+  for (int i = 0; i < nmu; ++i)
+    if (!std::isfinite(mu[i])) return false;
+  if (pr->pde == IFT_EULER2D && !(mu[0] > 0.0)) return false;
+  return true;
+}
+
+// ------------------------------------------------------------------- problem
+extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem** out) {
+  if (!d || !out) return IFT_EINVAL;
+  *out = nullptr;
+  if (d->pde != IFT_BURGERS2D && d->pde != IFT_EULER2D) return IFT_EINVAL;
+  if (d->p != 1 && d->p != 2) return IFT_EINVAL;
+  if (d->n_elem <= 0 || d->n_gnode <= 0 || !d->X || !d->elem_gnodes || !d->elem_nbr) return IFT_EINVAL;
+  if (!(d->eps_g > 0.0) || !(d->kappa >= 0.0) || !std::isfinite(d->kappa)) return IFT_EINVAL;
+  if (d->pde == IFT_EULER2D && !(d->gamma > 1.0)) return IFT_EINVAL;
+  ift_status st;
+  ift_problem* pr = new ift_problem();
+  pr->pde = d->pde;
+  pr->p = d->p;
+  pr->n_elem = d->n_elem;
+  pr->n_gnode = d->n_gnode;
+  pr->nn = (d->p + 1) * (d->p + 2) / 2;
+  pr->nc = d->pde == IFT_BURGERS2D ? 1 : 4;
+  pr->nue = pr->nn * pr->nc;
+  pr->nun = 3 * (d->p + 1) * pr->nc;
+  pr->nxe = 2 * pr->nn;
+  pr->N_u = (long long)d->n_elem * pr->nue;
+  pr->N_x = 2LL * d->n_gnode;
+  pr->gamma = d->gamma;
+  pr->kappa = d->kappa;
+  pr->eps_g = d->eps_g;
+  pr->bc_mu_scale = d->bc_mu_scale;
+  pr->all_farfield = d->all_farfield;
+  const int Ne = d->n_elem, nn = pr->nn;
+  pr->h_gn.assign(d->elem_gnodes, d->elem_gnodes + (size_t)Ne * nn);
+  pr->h_face.assign(d->elem_nbr, d->elem_nbr + (size_t)Ne * 3);
+  pr->h_X.assign(d->X, d->X + (size_t)2 * d->n_gnode);
+  for (double v : pr->h_X)
+    if (!std::isfinite(v)) { delete pr; return IFT_EINVAL; }
+  for (int g : pr->h_gn)
+    if (g < 0 || g >= d->n_gnode) { delete pr; return IFT_EINVAL; }
+  // face pairing: the neighbour E across face f of e must list e exactly once;
+  // the shared edge is traversed in opposite directions.
+  const int P = d->p, NC = pr->nc, NE = P + 1;
+  pr->h_Pn.assign((size_t)Ne * pr->nun, -1);
+  for (int e = 0; e < Ne; ++e) {
+    for (int f = 0; f < 3; ++f) {
+      const int E = pr->h_face[e * 3 + f];
+      if (E < 0) {
+        if (E < -4) { delete pr; return IFT_EINVAL; }
+        continue;
+      }
+      if (E >= Ne || E == e) { delete pr; return IFT_EINVAL; }
+      int g = -1, cnt = 0;
+      for (int h = 0; h < 3; ++h)
+        if (pr->h_face[E * 3 + h] == e) { g = h; ++cnt; }
+      if (cnt != 1) { delete pr; return IFT_EINVAL; }
+      if (pr->h_gn[e * nn + f] != pr->h_gn[E * nn + (g + 1) % 3] ||
+          pr->h_gn[e * nn + (f + 1) % 3] != pr->h_gn[E * nn + g]) {
+        delete pr;
+        return IFT_EINVAL;
+      }
+      for (int k = 0; k < NE; ++k) {
+        // neighbour's edge node p-k of face g sits at e's edge node k
+        const int kk = P - k;
+        int node;
+        if (kk == 0) node = g;
+        else if (kk == P) node = (g + 1) % 3;
+        else node = 3 + g;
+        for (int c = 0; c < NC; ++c)
+          pr->h_Pn[((size_t)e * 3 + f) * NE * NC + k * NC + c] = ((long long)E * nn + node) * NC + c;
+      }
+    }
+  }
+  std::vector<int> pn32(pr->h_Pn.size());
+  if (pr->N_u > 0x7fffffffLL) { delete pr; return IFT_EINVAL; }
+  // all host-side checks passed: from here on the device is touched
+  if ((st = ensure_tables()) != IFT_OK) { delete pr; return st; }
+  for (size_t i = 0; i < pn32.size(); ++i) pn32[i] = (int)pr->h_Pn[i];
+  if ((st = dalloc(&pr->d_gn, pr->h_gn.size())) != IFT_OK ||
+      (st = dalloc(&pr->d_face, pr->h_face.size())) != IFT_OK ||
+      (st = dalloc(&pr->d_Pn, pn32.size())) != IFT_OK ||
+      (st = dalloc(&pr->d_X, pr->h_X.size())) != IFT_OK ||
+      (st = dalloc(&pr->d_flags, (size_t)Ne)) != IFT_OK) {
+    ift_problem_destroy(pr);
+    return st;
+  }
+  if (hipMemcpy(pr->d_gn, pr->h_gn.data(), pr->h_gn.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pr->d_face, pr->h_face.data(), pr->h_face.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pr->d_Pn, pn32.data(), pn32.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(pr->d_X, pr->h_X.data(), pr->h_X.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    ift_problem_destroy(pr);
+    return IFT_EDEVICE;
+  }
+  *out = pr;
+  return IFT_OK;
+}
+
+extern "C" void ift_problem_destroy(ift_problem* pr) {
+  if (!pr) return;
+  dfree(pr->d_gn);
+  dfree(pr->d_face);
+  dfree(pr->d_Pn);
+  dfree(pr->d_X);
+  dfree(pr->d_flags);
+  delete pr;
+}
+
+extern "C" ift_status ift_problem_sizes(const ift_problem* pr, int* nue, int* nun, int* nxe, long long* N_u,
+                                        long long* N_x) {
+  if (!pr) return IFT_EINVAL;
+  if (nue) *nue = pr->nue;
+  if (nun) *nun = pr->nun;
+  if (nxe) *nxe = pr->nxe;
+  if (N_u) *N_u = pr->N_u;
+  if (N_x) *N_x = pr->N_x;
+  return IFT_OK;
+}
+
+// --------------------------------------------------------------- dispatch
+template <class D, class R>
+static ift_status launch_hdm(const HdmArgs& a, bool jac, hipStream_t st) {
+  if (jac)
+    hipLaunchKernelGGL((k_hdm<D, R, true>), dim3(a.n_elem), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_hdm<D, R, false>), dim3(a.n_elem), dim3(64), 0, st, a);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+template <class R>
+static ift_status dispatch_hdm(const ift_problem* pr, const HdmArgs& a, bool jac, hipStream_t st) {
+  if (pr->pde == IFT_BURGERS2D)
+    return pr->p == 1 ? launch_hdm<Disc<PDE_BURGERS, 1>, R>(a, jac, st) : launch_hdm<Disc<PDE_BURGERS, 2>, R>(a, jac, st);
+  return pr->p == 1 ? launch_hdm<Disc<PDE_EULER, 1>, R>(a, jac, st) : launch_hdm<Disc<PDE_EULER, 2>, R>(a, jac, st);
+}
+
+extern "C" ift_status hdm_assemble(ift_problem* pr, const double* mu, const double* U, const double* x, double* R,
+                                   double* N, double* dRdU, double* dRdUn, double* dRdx, double* dNdx, int* n_bad,
+                                   hipStream_t stream) {
+  if (!pr || !U || !x || !finite_mu(pr, mu)) return IFT_EINVAL;
+  HdmArgs a;
+  a.U = U;
+  a.x = x;
+  a.gn = pr->d_gn;
+  a.face = pr->d_face;
+  a.Pn = pr->d_Pn;
+  a.X = pr->d_X;
+  a.R = R;
+  a.N = N;
+  a.dRdU = dRdU;
+  a.dRdUn = dRdUn;
+  a.dRdx = dRdx;
+  a.dNdx = dNdx;
+  a.flags = pr->d_flags;
+  a.pc = phys_const(pr, mu);
+  a.kappa = pr->kappa;
+  a.eps = pr->eps_g;
+  a.n_elem = pr->n_elem;
+  const bool jac = dRdU || dRdUn || dRdx || dNdx;
+  ift_status s = dispatch_hdm<double>(pr, a, jac, stream);
+  if (s != IFT_OK) return s;
+  if (n_bad) {
+    hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, stream, (const double*)nullptr, (const int*)pr->d_flags,
+                       pr->n_elem, (double*)nullptr, n_bad, (int*)nullptr);
+    if (hipGetLastError() != hipSuccess) return IFT_EDEVICE;
+  }
+  return IFT_OK;
+}
+
+// -------------------------------------------------------------------- ROM
+extern "C" void ift_rom_destroy(ift_rom* r) {
+  if (!r) return;
+  dfree(r->d_eq);
+  dfree(r->d_rho);
+  dfree(r->d_srho);
+  dfree(r->d_Phi_s);
+  dfree(r->d_Phin_s);
+  dfree(r->d_Psi_s);
+  dfree(r->d_X_s);
+  dfree(r->d_Jt);
+  dfree(r->d_Ft);
+  dfree(r->d_Jpart);
+  dfree(r->d_flags);
+  dfree(r->d_PTR);
+  dfree(r->d_gram_part);
+  dfree(r->d_H);
+  dfree(r->d_g);
+  dfree(r->d_J);
+  dfree(r->d_Jtrial);
+  dfree(r->d_dz);
+  dfree(r->d_solve_out);
+  dfree(r->d_wt);
+  dfree(r->d_tt);
+  dfree(r->d_nbad);
+  dfree(r->d_flag_or);
+  delete r;
+}
+
+extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double* Phi, const double* Psi, int n_s,
+                                     const int* eq_elem, const double* eq_rho, ift_precision precision,
+                                     ift_rom** out) {
+  if (!pr || !out || !Phi || (m > 0 && !Psi) || !eq_elem || !eq_rho) return IFT_EINVAL;
+  *out = nullptr;
+  if (n < 1 || m < 0 || n + m > 64 || n_s < 1) return IFT_EINVAL;
+  if (precision != IFT_FP64 && precision != IFT_FP32_ELEM) return IFT_EINVAL;
+  for (int k = 0; k < n_s; ++k) {
+    if (eq_elem[k] < 0 || eq_elem[k] >= pr->n_elem) return IFT_EINVAL;
+    if (!(eq_rho[k] >= 0.0) || !std::isfinite(eq_rho[k])) return IFT_EINVAL;
+  }
+  ift_rom* r = new ift_rom();
+  r->prob = pr;
+  r->n = n;
+  r->m = m;
+  r->D = n + m;
+  r->n_s = n_s;
+  r->precision = precision;
+  const int nue = pr->nue, nun = pr->nun, nxe = pr->nxe, nn = pr->nn;
+  r->nrows = (long long)n_s * nue + n_s;
+  r->n_gram_blk = (int)((r->nrows + GRAM_ROWS - 1) / GRAM_ROWS);
+  const int npair = r->D * (r->D + 1) / 2;
+  std::vector<long long> rows_u((size_t)n_s * nue), rows_n((size_t)n_s * nun), rows_x((size_t)n_s * nxe);
+  std::vector<double> hXs((size_t)n_s * nxe), hsr(n_s);
+  for (int k = 0; k < n_s; ++k) {
+    const int e = eq_elem[k];
+    for (int i = 0; i < nue; ++i) rows_u[(size_t)k * nue + i] = (long long)e * nue + i;
+    for (int i = 0; i < nun; ++i) rows_n[(size_t)k * nun + i] = pr->h_Pn[(size_t)e * nun + i];
+    for (int i = 0; i < nxe; ++i) {
+      const long long gi = 2LL * pr->h_gn[(size_t)e * nn + i / 2] + (i & 1);
+      rows_x[(size_t)k * nxe + i] = gi;
+      hXs[(size_t)k * nxe + i] = pr->h_X[gi];
+    }
+    hsr[k] = std::sqrt(eq_rho[k]);
+  }
+  ift_status st;
+  long long* d_rows = nullptr;
+  const size_t maxrows = std::max({rows_u.size(), rows_n.size(), rows_x.size()});
+#define ALLOC(ptr, cnt)                                       \
+  if ((st = dalloc(&(ptr), (size_t)(cnt))) != IFT_OK) {       \
+    dfree(d_rows);                                            \
+    ift_rom_destroy(r);                                       \
+    return st;                                                \
+  }
+  ALLOC(d_rows, maxrows);
+  ALLOC(r->d_eq, n_s);
+  ALLOC(r->d_rho, n_s);
+  ALLOC(r->d_srho, n_s);
+  ALLOC(r->d_Phi_s, (size_t)n_s * nue * n);
+  ALLOC(r->d_Phin_s, (size_t)n_s * nun * n);
+  ALLOC(r->d_Psi_s, (size_t)n_s * nxe * std::max(m, 1));
+  ALLOC(r->d_X_s, (size_t)n_s * nxe);
+  ALLOC(r->d_Jt, (size_t)r->nrows * r->D);
+  ALLOC(r->d_Ft, (size_t)r->nrows);
+  ALLOC(r->d_Jpart, n_s);
+  ALLOC(r->d_flags, n_s);
+  ALLOC(r->d_PTR, (size_t)n_s * n);
+  ALLOC(r->d_gram_part, (size_t)r->n_gram_blk * (npair + r->D));
+  ALLOC(r->d_H, (size_t)r->D * r->D);
+  ALLOC(r->d_g, r->D);
+  ALLOC(r->d_J, 1);
+  ALLOC(r->d_Jtrial, 1);
+  ALLOC(r->d_dz, r->D);
+  ALLOC(r->d_solve_out, 8);
+  ALLOC(r->d_wt, n);
+  ALLOC(r->d_tt, std::max(m, 1));
+  ALLOC(r->d_nbad, 1);
+  ALLOC(r->d_flag_or, 1);
+#undef ALLOC
+  bool ok = hipMemcpy(r->d_eq, eq_elem, n_s * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(r->d_rho, eq_rho, n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(r->d_srho, hsr.data(), n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(r->d_X_s, hXs.data(), hXs.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+  auto gather = [&](const double* src, int ncol, const std::vector<long long>& rows, double* dst) {
+    if (!ok || ncol == 0) return;
+    ok = hipMemcpy(d_rows, rows.data(), rows.size() * sizeof(long long), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) return;
+    const long long tot = (long long)rows.size() * ncol;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, 0, src, ncol,
+                       (const long long*)d_rows, (long long)rows.size(), dst);
+    ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  };
+  gather(Phi, n, rows_u, r->d_Phi_s);
+  gather(Phi, n, rows_n, r->d_Phin_s);
+  gather(Psi, m, rows_x, r->d_Psi_s);
+  dfree(d_rows);
+  if (!ok) {
+    ift_rom_destroy(r);
+    return IFT_EDEVICE;
+  }
+  *out = r;
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_rom_get_gathers(ift_rom* r, double* Phi_s, double* Phin_s, double* Psi_s, double* X_s,
+                                          hipStream_t stream) {
+  if (!r) return IFT_EINVAL;
+  const ift_problem* pr = r->prob;
+  const size_t ns = r->n_s;
+  if (Phi_s) HIP_TRY(hipMemcpyAsync(Phi_s, r->d_Phi_s, ns * pr->nue * r->n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  if (Phin_s) HIP_TRY(hipMemcpyAsync(Phin_s, r->d_Phin_s, ns * pr->nun * r->n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  if (Psi_s && r->m > 0) HIP_TRY(hipMemcpyAsync(Psi_s, r->d_Psi_s, ns * pr->nxe * r->m * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  if (X_s) HIP_TRY(hipMemcpyAsync(X_s, r->d_X_s, ns * pr->nxe * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return IFT_OK;
+}
+
+static EqArgs eq_args(ift_rom* r, const double* mu, const double* w, const double* tau) {
+  const ift_problem* pr = r->prob;
+  EqArgs a;
+  a.n_s = r->n_s;
+  a.n = r->n;
+  a.m = r->m;
+  a.D = r->D;
+  a.eq_elem = r->d_eq;
+  a.face = pr->d_face;
+  a.rho = r->d_rho;
+  a.srho = r->d_srho;
+  a.Phi_s = r->d_Phi_s;
+  a.Phin_s = r->d_Phin_s;
+  a.Psi_s = r->d_Psi_s;
+  a.X_s = r->d_X_s;
+  a.w = w;
+  a.tau = tau;
+  a.Jt = r->d_Jt;
+  a.Ft = r->d_Ft;
+  a.Jpart = r->d_Jpart;
+  a.flags = r->d_flags;
+  a.PTR = nullptr;
+  a.pc = phys_const(pr, mu);
+  a.kappa = pr->kappa;
+  a.eps = pr->eps_g;
+  return a;
+}
+
+template <class D, class R>
+static void launch_eq(const EqArgs& a, bool jac, hipStream_t st) {
+  if (jac)
+    hipLaunchKernelGGL((k_eq_jac<D, R>), dim3(a.n_s), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_eq_res<D, R>), dim3(a.n_s), dim3(64), 0, st, a);
+}
+
+template <class R>
+static void dispatch_eq_r(const ift_problem* pr, const EqArgs& a, bool jac, hipStream_t st) {
+  if (pr->pde == IFT_BURGERS2D) {
+    if (pr->p == 1) launch_eq<Disc<PDE_BURGERS, 1>, R>(a, jac, st);
+    else launch_eq<Disc<PDE_BURGERS, 2>, R>(a, jac, st);
+  } else {
+    if (pr->p == 1) launch_eq<Disc<PDE_EULER, 1>, R>(a, jac, st);
+    else launch_eq<Disc<PDE_EULER, 2>, R>(a, jac, st);
+  }
+}
+
+static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, hipStream_t st) {
+  if (r->precision == IFT_FP32_ELEM) dispatch_eq_r<float>(r->prob, a, jac, st);
+  else dispatch_eq_r<double>(r->prob, a, jac, st);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+extern "C" ift_status eq_assemble_residual(ift_rom* r, const double* mu, const double* w, const double* tau,
+                                           double* Jobj, double* Ft, double* PhiT_r, int* n_bad,
+                                           hipStream_t stream) {
+  if (!r || !w || (r->m > 0 && !tau) || !finite_mu(r->prob, mu)) return IFT_EINVAL;
+  EqArgs a = eq_args(r, mu, w, tau);
+  a.Ft = Ft;
+  a.PTR = PhiT_r ? r->d_PTR : nullptr;
+  ift_status s = dispatch_eq(r, a, false, stream);
+  if (s != IFT_OK) return s;
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, stream, (const double*)r->d_Jpart, (const int*)r->d_flags,
+                     r->n_s, Jobj, n_bad, r->d_flag_or);
+  if (PhiT_r)
+    hipLaunchKernelGGL(k_sum_rows, dim3((r->n + 63) / 64), dim3(64), 0, stream, (const double*)r->d_PTR, r->n_s,
+                       r->n, PhiT_r);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+static ift_status gram(ift_rom* r, double* H, double* g, hipStream_t stream) {
+  const int D = r->D;
+  const size_t shm = (size_t)(GRAM_TILE * D + GRAM_TILE) * sizeof(double);
+  hipLaunchKernelGGL(k_gram_partial, dim3(r->n_gram_blk), dim3(256), shm, stream, (const double*)r->d_Jt,
+                     (const double*)r->d_Ft, r->nrows, D, r->d_gram_part);
+  const int nent = D * (D + 1) / 2 + D;
+  hipLaunchKernelGGL(k_gram_final, dim3((nent + 255) / 256), dim3(256), 0, stream, (const double*)r->d_gram_part,
+                     r->n_gram_blk, D, H, g);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+extern "C" ift_status eq_assemble_jacobian(ift_rom* r, const double* mu, const double* w, const double* tau,
+                                           double* Jobj, double* g, double* H, double* Jt, int* n_bad,
+                                           hipStream_t stream) {
+  if (!r || !w || (r->m > 0 && !tau) || !finite_mu(r->prob, mu)) return IFT_EINVAL;
+  EqArgs a = eq_args(r, mu, w, tau);
+  ift_status s = dispatch_eq(r, a, true, stream);
+  if (s != IFT_OK) return s;
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, stream, (const double*)r->d_Jpart, (const int*)r->d_flags,
+                     r->n_s, Jobj, n_bad, r->d_flag_or);
+  s = gram(r, H ? H : r->d_H, g ? g : r->d_g, stream);
+  if (s != IFT_OK) return s;
+  if (Jt) HIP_TRY(hipMemcpyAsync(Jt, r->d_Jt, (size_t)r->nrows * r->D * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return IFT_OK;
+}
+
+extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double* w, double* tau,
+                                            const ift_gn_params* prm, ift_gn_info* info, hipStream_t stream) {
+  if (!r || !w || (r->m > 0 && !tau) || !prm || !info || !finite_mu(r->prob, mu)) return IFT_EINVAL;
+  if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
+    return IFT_EINVAL;
+  std::memset(info, 0, sizeof(*info));
+  const int n = r->n, m = r->m, D = r->D;
+  ift_status s = eq_assemble_jacobian(r, mu, w, tau, r->d_J, r->d_g, r->d_H, nullptr, r->d_nbad, stream);
+  if (s != IFT_OK) return s;
+  hipLaunchKernelGGL(k_lm_solve, dim3(1), dim3(64), 0, stream, (const double*)r->d_H, (const double*)r->d_g, D, n,
+                     prm->lambda, r->d_dz, r->d_solve_out);
+  HIP_TRY(hipGetLastError());
+  double so[4], J0;
+  int fo;
+  HIP_TRY(hipMemcpyAsync(so, r->d_solve_out, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&J0, r->d_J, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(&fo, r->d_flag_or, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  info->J_old = J0;
+  info->J_new = J0;
+  info->norm_S = so[1];
+  info->norm_T = so[2];
+  if (!std::isfinite(J0)) {
+    info->status = (fo & BAD_GEOM) ? IFT_EBADMESH : IFT_ENONPHYS;
+    return (ift_status)info->status;
+  }
+  if (so[1] <= prm->tol && so[2] <= prm->tol) {
+    info->converged = 1;
+    info->status = IFT_OK;
+    return IFT_OK;
+  }
+  if (so[0] != 0.0) {
+    info->status = IFT_ESINGULAR;
+    return IFT_ESINGULAR;
+  }
+  const double slope = so[3];
+  double alpha = 1.0;
+  for (int bt = 0; bt <= prm->max_backtrack; ++bt) {
+    hipLaunchKernelGGL(k_axpy2, dim3((D + 63) / 64), dim3(64), 0, stream, (const double*)w, (const double*)tau,
+                       (const double*)r->d_dz, alpha, n, m, r->d_wt, r->d_tt);
+    HIP_TRY(hipGetLastError());
+    s = eq_assemble_residual(r, mu, r->d_wt, r->d_tt, r->d_Jtrial, nullptr, nullptr, nullptr, stream);
+    if (s != IFT_OK) return s;
+    double Jt;
+    HIP_TRY(hipMemcpyAsync(&Jt, r->d_Jtrial, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (Jt <= J0 + prm->c1 * alpha * slope) {
+      HIP_TRY(hipMemcpyAsync(w, r->d_wt, n * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      if (m > 0) HIP_TRY(hipMemcpyAsync(tau, r->d_tt, m * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      info->J_new = Jt;
+      info->alpha = alpha;
+      info->n_backtrack = bt;
+      info->status = IFT_OK;
+      return IFT_OK;
+    }
+    alpha *= 0.5;
+  }
+  info->n_backtrack = prm->max_backtrack + 1;
+  info->status = IFT_ELINESEARCH;
+  return IFT_ELINESEARCH;
+}

@@ -1,0 +1,249 @@
+"""Thin ctypes binding of the C ABI in include/ift.h (argument marshalling only).
+
+Every function here forwards to ``libift.so``; all element, reduction and
+solver arithmetic runs in the library's HIP kernels.  Device arrays are
+torch tensors on the current CUDA/HIP device (float64, contiguous); the
+stream is torch's current stream unless one is given.  If the library has
+not been built this module raises at first use instead of falling back to
+any CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libift.so")
+
+IFT_OK, IFT_EINVAL, IFT_ENOMEM, IFT_EDEVICE = 0, -1, -2, -3
+IFT_EBADMESH, IFT_ENONPHYS, IFT_ESINGULAR, IFT_ELINESEARCH, IFT_ENOTCONV = -4, -5, -6, -7, -8
+STATUS_NAMES = {0: "IFT_OK", -1: "IFT_EINVAL", -2: "IFT_ENOMEM", -3: "IFT_EDEVICE", -4: "IFT_EBADMESH",
+                -5: "IFT_ENONPHYS", -6: "IFT_ESINGULAR", -7: "IFT_ELINESEARCH", -8: "IFT_ENOTCONV"}
+PDE = {"burgers": 0, "euler": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+
+class IftError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}")
+        self.status = status
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("pde", ctypes.c_int), ("p", ctypes.c_int), ("n_elem", ctypes.c_int), ("n_gnode", ctypes.c_int),
+                ("X", ctypes.POINTER(ctypes.c_double)), ("elem_gnodes", ctypes.POINTER(ctypes.c_int)),
+                ("elem_nbr", ctypes.POINTER(ctypes.c_int)), ("gamma", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("eps_g", ctypes.c_double), ("bc_mu_scale", ctypes.c_double), ("all_farfield", ctypes.c_int)]
+
+
+class GNParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("c1", ctypes.c_double), ("max_backtrack", ctypes.c_int),
+                ("tol", ctypes.c_double)]
+
+
+class GNInfo(ctypes.Structure):
+    _fields_ = [("J_old", ctypes.c_double), ("J_new", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("norm_S", ctypes.c_double), ("norm_T", ctypes.c_double), ("n_backtrack", ctypes.c_int),
+                ("converged", ctypes.c_int), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+EXPORTS = {
+    "ift_problem_create": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), ctypes.POINTER(_P)]),
+    "ift_problem_destroy": (None, [_P]),
+    "ift_problem_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(ctypes.c_longlong)]),
+    "hdm_assemble": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ift_rom_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), _D, ctypes.c_int, ctypes.POINTER(_P)]),
+    "ift_rom_destroy": (None, [_P]),
+    "ift_rom_get_gathers": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "eq_assemble_residual": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P]),
+    "eq_assemble_jacobian": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "rom_gauss_newton_step": (ctypes.c_int, [_P, _D, _P, _P, ctypes.POINTER(GNParams), ctypes.POINTER(GNInfo), _P]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2305_15661_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, where: str):
+    if st != IFT_OK:
+        raise IftError(st, where)
+
+
+def _ptr(t, n=None, dtype=None):
+    """Device pointer of a contiguous torch tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _mu(mu):
+    a = (ctypes.c_double * 2)()
+    mu = np.atleast_1d(np.asarray(mu, dtype=np.float64))
+    for i in range(min(2, mu.size)):
+        a[i] = mu[i]
+    return a
+
+
+class Problem:
+    def __init__(self, pde: str, p: int, X, elem_gnodes, elem_nbr, gamma=1.4, kappa=0.1, eps_g=1e-8,
+                 bc_mu_scale=0.5, all_farfield=False):
+        L = lib()
+        self._X = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(-1))
+        self._gn = np.ascontiguousarray(elem_gnodes, dtype=np.int32)
+        self._nb = np.ascontiguousarray(elem_nbr, dtype=np.int32)
+        d = ProblemDesc(PDE[pde], int(p), int(self._gn.shape[0]), int(self._X.size // 2),
+                        self._X.ctypes.data_as(_D), self._gn.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                        self._nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(gamma), float(kappa),
+                        float(eps_g), float(bc_mu_scale), int(bool(all_farfield)))
+        h = _P()
+        _check(L.ift_problem_create(ctypes.byref(d), ctypes.byref(h)), "ift_problem_create")
+        self.handle = h
+        a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        nu, nx = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(L.ift_problem_sizes(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(nu),
+                                   ctypes.byref(nx)), "ift_problem_sizes")
+        self.nue, self.nun, self.nxe, self.N_u, self.N_x = a.value, b.value, c.value, nu.value, nx.value
+        self.n_elem = int(self._gn.shape[0])
+        self.pde = pde
+
+    @classmethod
+    def from_workload(cls, wl):
+        return cls(wl.pde, wl.p, wl.mesh.X, wl.mesh.elem_gnodes, wl.mesh.elem_nbr, gamma=wl.gamma,
+                   kappa=wl.kappa, eps_g=wl.eps_g, bc_mu_scale=wl.bc_mu_scale, all_farfield=wl.all_farfield)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.ift_problem_destroy(h)
+            self.handle = None
+
+    def hdm_assemble(self, mu, U, x, R=None, N=None, dRdU=None, dRdUn=None, dRdx=None, dNdx=None, n_bad=None,
+                     stream=None):
+        import torch
+        f64 = torch.float64
+        Ne, nue, nun, nxe = self.n_elem, self.nue, self.nun, self.nxe
+        st = lib().hdm_assemble(self.handle, _mu(mu), _ptr(U, self.N_u, f64), _ptr(x, self.N_x, f64),
+                                _ptr(R, self.N_u, f64), _ptr(N, Ne, f64), _ptr(dRdU, Ne * nue * nue, f64),
+                                _ptr(dRdUn, Ne * nue * nun, f64), _ptr(dRdx, Ne * nue * nxe, f64),
+                                _ptr(dNdx, Ne * nxe, f64), _ptr(n_bad, 1, torch.int32), _stream(stream))
+        _check(st, "hdm_assemble")
+
+
+class ROM:
+    def __init__(self, prob: Problem, Phi, Psi, eq_elem, eq_rho, precision="fp64"):
+        import torch
+        self.prob = prob
+        self.n = int(Phi.shape[1])
+        self.m = int(Psi.shape[1])
+        self.D = self.n + self.m
+        el = np.ascontiguousarray(eq_elem, dtype=np.int32)
+        rho = np.ascontiguousarray(eq_rho, dtype=np.float64)
+        self.n_s = int(el.size)
+        h = _P()
+        st = lib().ift_rom_create(prob.handle, self.n, self.m, _ptr(Phi, prob.N_u * self.n, torch.float64),
+                                  _ptr(Psi, prob.N_x * self.m, torch.float64) if self.m else None, self.n_s,
+                                  el.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), rho.ctypes.data_as(_D),
+                                  PRECISION[precision], ctypes.byref(h))
+        _check(st, "ift_rom_create")
+        self.handle = h
+        self.nrows = self.n_s * prob.nue + self.n_s
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.ift_rom_destroy(h)
+            self.handle = None
+
+    def get_gathers(self, Phi_s=None, Phin_s=None, Psi_s=None, X_s=None, stream=None):
+        import torch
+        f64, p = torch.float64, self.prob
+        _check(lib().ift_rom_get_gathers(self.handle, _ptr(Phi_s, self.n_s * p.nue * self.n, f64),
+                                         _ptr(Phin_s, self.n_s * p.nun * self.n, f64),
+                                         _ptr(Psi_s, self.n_s * p.nxe * self.m, f64),
+                                         _ptr(X_s, self.n_s * p.nxe, f64), _stream(stream)), "ift_rom_get_gathers")
+
+    def eq_assemble_residual(self, mu, w, tau, Jobj, Ft=None, PhiT_r=None, n_bad=None, stream=None):
+        import torch
+        f64 = torch.float64
+        st = lib().eq_assemble_residual(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
+                                        _ptr(Jobj, 1, f64), _ptr(Ft, self.nrows, f64), _ptr(PhiT_r, self.n, f64),
+                                        _ptr(n_bad, 1, torch.int32), _stream(stream))
+        _check(st, "eq_assemble_residual")
+
+    def eq_assemble_jacobian(self, mu, w, tau, Jobj, g, H, Jt=None, n_bad=None, stream=None):
+        import torch
+        f64 = torch.float64
+        st = lib().eq_assemble_jacobian(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
+                                        _ptr(Jobj, 1, f64), _ptr(g, self.D, f64), _ptr(H, self.D * self.D, f64),
+                                        _ptr(Jt, self.nrows * self.D, f64), _ptr(n_bad, 1, torch.int32),
+                                        _stream(stream))
+        _check(st, "eq_assemble_jacobian")
+
+    def gauss_newton_step(self, mu, w, tau, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, stream=None):
+        """rom_gauss_newton_step; returns (status, info dict).  Soft outcomes
+        (converged / line-search failure / invalid point) are reported in the
+        status instead of raising."""
+        import torch
+        f64 = torch.float64
+        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol))
+        info = GNInfo()
+        st = lib().rom_gauss_newton_step(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
+                                         ctypes.byref(prm), ctypes.byref(info), _stream(stream))
+        if st in (IFT_EINVAL, IFT_ENOMEM, IFT_EDEVICE):
+            raise IftError(st, "rom_gauss_newton_step")
+        return st, info.as_dict()
+
+
+# backwards-compatible names matching the C ABI
+def hdm_assemble(prob: Problem, *a, **k):
+    return prob.hdm_assemble(*a, **k)
+
+
+def eq_assemble_residual(rom: ROM, *a, **k):
+    return rom.eq_assemble_residual(*a, **k)
+
+
+def eq_assemble_jacobian(rom: ROM, *a, **k):
+    return rom.eq_assemble_jacobian(*a, **k)
+
+
+def rom_gauss_newton_step(rom: ROM, *a, **k):
+    return rom.gauss_newton_step(*a, **k)

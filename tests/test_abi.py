@@ -1,0 +1,81 @@
+"""The C-ABI library loads, exports every symbol of include/ift.h, and
+rejects bad arguments on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2305_15661_amd import ift
+    if not os.path.exists(ift.LIB_PATH):
+        pytest.fail("libift.so not built: run __graft_entry__.build()")
+    return ift, ift.lib()
+
+
+def test_every_declared_symbol_is_exported():
+    ift, L = _lib()
+    hdr = open(os.path.join(ROOT, "include", "ift.h")).read()
+    names = set(re.findall(r"^(?:ift_status|void)\s+(\w+)\s*\(", hdr, flags=re.M))
+    assert names == set(ift.EXPORTS), names ^ set(ift.EXPORTS)
+    for n in names:
+        assert hasattr(L, n)
+
+
+def _desc(ift, wl, **over):
+    X = np.ascontiguousarray(wl.mesh.X.reshape(-1))
+    gn = np.ascontiguousarray(wl.mesh.elem_gnodes, dtype=np.int32)
+    nb = np.ascontiguousarray(wl.mesh.elem_nbr, dtype=np.int32)
+    kw = dict(pde=ift.PDE[wl.pde], p=wl.p, n_elem=gn.shape[0], n_gnode=X.size // 2, gamma=1.4, kappa=0.1,
+              eps_g=1e-8, bc_mu_scale=0.5, all_farfield=0)
+    kw.update(over)
+    d = ift.ProblemDesc(kw["pde"], kw["p"], kw["n_elem"], kw["n_gnode"], X.ctypes.data_as(ift._D),
+                        gn.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                        kw["gamma"], kw["kappa"], kw["eps_g"], kw["bc_mu_scale"], kw["all_farfield"])
+    return d, (X, gn, nb)
+
+
+@pytest.mark.parametrize("over", [dict(p=3), dict(pde=7), dict(n_elem=0), dict(eps_g=0.0), dict(kappa=-1.0),
+                                  dict(gamma=1.0, pde=1)])
+def test_bad_descriptor_rejected(over):
+    ift, L = _lib()
+    wl = synth.tiny_burgers()
+    d, keep = _desc(ift, wl, **over)
+    h = ctypes.c_void_p()
+    assert L.ift_problem_create(ctypes.byref(d), ctypes.byref(h)) == ift.IFT_EINVAL
+    assert not h.value
+
+
+def test_bad_mesh_rejected():
+    ift, L = _lib()
+    wl = synth.tiny_burgers()
+    for mut in ("nonmutual", "range", "tag", "orientation"):
+        d, (X, gn, nb) = _desc(ift, wl)
+        if mut == "nonmutual":
+            nb[0, 2] = 5
+        elif mut == "range":
+            gn[3, 1] = 10 ** 6
+        elif mut == "tag":
+            nb[0, 0] = -9
+        else:
+            gn[1, [0, 1]] = gn[1, [1, 0]]
+        h = ctypes.c_void_p()
+        assert L.ift_problem_create(ctypes.byref(d), ctypes.byref(h)) == ift.IFT_EINVAL, mut
+
+
+def test_null_handles_rejected():
+    ift, L = _lib()
+    mu = (ctypes.c_double * 2)(0.3, 0.0)
+    assert L.hdm_assemble(None, mu, None, None, None, None, None, None, None, None, None, None) == ift.IFT_EINVAL
+    assert L.eq_assemble_residual(None, mu, None, None, None, None, None, None, None) == ift.IFT_EINVAL
+    assert L.eq_assemble_jacobian(None, mu, None, None, None, None, None, None, None, None) == ift.IFT_EINVAL
+    assert L.rom_gauss_newton_step(None, mu, None, None, None, None, None) == ift.IFT_EINVAL
+    assert L.ift_rom_get_gathers(None, None, None, None, None, None) == ift.IFT_EINVAL
+    L.ift_problem_destroy(None)
+    L.ift_rom_destroy(None)

@@ -1,0 +1,244 @@
+"""GPU parity: every output of the HIP path against the CPU oracle on the
+same seeded inputs, through the C ABI.
+
+Tolerances (FP64): normwise relative error <= 1e-12 for residuals,
+Jacobians, gradients and Gauss-Newton matrices (both sides compute the same
+sums of O(10^2) terms in a different order; the observed error is ~1e-15);
+gathers are bit-exact; a Gauss-Newton step is compared given the same z_n
+with a bound of 1e-13 * cond(H) (the two sides factor H independently)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_15661_amd import ift
+    ift.lib()            # fails loudly if the HIP library is missing
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+
+
+def _z(n, dev, dtype=None):
+    import torch
+    return torch.zeros(n, dtype=dtype or torch.float64, device=dev)
+
+
+class Case:
+    def __init__(self, wl, dev, eq_elem=None, eq_rho=None, precision="fp64"):
+        from oracle import eq as oeq
+        from oracle import residual as ors
+        from paper_2305_15661_amd import ift
+        self.wl = wl
+        self.dev = dev
+        self.eq_elem = wl.eq_elem if eq_elem is None else np.asarray(eq_elem, dtype=np.int32)
+        self.eq_rho = wl.eq_rho if eq_rho is None else np.asarray(eq_rho)
+        self.prob = ift.Problem.from_workload(wl)
+        self.rom = ift.ROM(self.prob, _t(wl.Phi, dev), _t(wl.Psi, dev), self.eq_elem, self.eq_rho, precision)
+        self.oprob = ors.Problem(wl)
+        self.orom = oeq.ROM(self.oprob, wl.Phi, wl.Psi, self.eq_elem, self.eq_rho)
+
+
+@pytest.fixture(scope="module")
+def tiny_case(dev):
+    return Case(synth.tiny_burgers(), dev)
+
+
+@pytest.fixture(scope="module")
+def euler_case(dev):
+    # 16x8 cells (256 P2 elements), 64 EQ elements: several tiles and a ragged tail
+    return Case(synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=64), dev)
+
+
+def _hdm_gpu(case, mu, U, x, jac=True):
+    import torch
+    p, d = case.prob, case.dev
+    Ne = p.n_elem
+    out = {"R": _z(p.N_u, d), "N": _z(Ne, d), "n_bad": _z(1, d, torch.int32)}
+    if jac:
+        out.update(dRdU=_z(Ne * p.nue * p.nue, d), dRdUn=_z(Ne * p.nue * p.nun, d),
+                   dRdx=_z(Ne * p.nue * p.nxe, d), dNdx=_z(Ne * p.nxe, d))
+    p.hdm_assemble(mu, _t(U, d), _t(x, d), **out)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+def test_hdm_assemble_parity(which, request):
+    from oracle import residual as ors
+    case = request.getfixturevalue(which)
+    wl = case.wl
+    for k in (0, 7):
+        _say(f"hdm_assemble parity {wl.name} eval point {k}")
+        mu = wl.mus[k]
+        U = wl.Phi @ wl.w_eval[k]
+        x = wl.X + wl.Psi @ wl.tau_eval[k]
+        g = _hdm_gpu(case, mu, U, x)
+        o = ors.hdm_assemble(case.oprob, mu, U, x, jac=True)
+        assert rel(g["R"], o["R"]) < 1e-12
+        assert rel(g["N"], o["N"]) < 1e-12
+        for key in ("dRdU", "dRdUn", "dRdx", "dNdx"):
+            assert rel(g[key], o[key].ravel()) < 1e-12, key
+        assert int(g["n_bad"][0]) == o["n_bad"] == 0
+
+
+def test_hdm_residual_only_matches_jacobian_path(euler_case):
+    wl = euler_case.wl
+    U = wl.Phi @ wl.w_eval[3]
+    x = wl.X + wl.Psi @ wl.tau_eval[3]
+    a = _hdm_gpu(euler_case, wl.mus[3], U, x, jac=False)
+    b = _hdm_gpu(euler_case, wl.mus[3], U, x, jac=True)
+    assert np.array_equal(a["R"], b["R"]) and np.array_equal(a["N"], b["N"])
+
+
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+def test_gathers_bit_exact(which, request):
+    case = request.getfixturevalue(which)
+    _say(f"gathers {case.wl.name}")
+    p, r, d = case.prob, case.rom, case.dev
+    bufs = [_z(r.n_s * p.nue * r.n, d), _z(r.n_s * p.nun * r.n, d), _z(r.n_s * p.nxe * r.m, d), _z(r.n_s * p.nxe, d)]
+    r.get_gathers(*bufs)
+    o = case.orom
+    for b, ref in zip(bufs, (o.Phi_s, o.Phin_s, o.Psi_s, o.X_s)):
+        assert np.array_equal(b.cpu().numpy(), ref.ravel())
+
+
+def _eq_gpu(case, mu, w, tau):
+    import torch
+    r, d = case.rom, case.dev
+    J, g, H, Jt = _z(1, d), _z(r.D, d), _z(r.D * r.D, d), _z(r.nrows * r.D, d)
+    nb = _z(1, d, torch.int32)
+    r.eq_assemble_jacobian(mu, _t(w, d), _t(tau, d), J, g, H, Jt, nb)
+    Jr, Ft, ptr, nb2 = _z(1, d), _z(r.nrows, d), _z(r.n, d), _z(1, d, torch.int32)
+    r.eq_assemble_residual(mu, _t(w, d), _t(tau, d), Jr, Ft, ptr, nb2)
+    torch.cuda.synchronize()
+    f = lambda t: t.cpu().numpy()
+    return dict(J=f(J)[0], g=f(g), H=f(H).reshape(r.D, r.D), Jt=f(Jt).reshape(r.nrows, r.D), Jr=f(Jr)[0],
+                Ft=f(Ft), PhiT_r=f(ptr), n_bad=int(f(nb)[0]))
+
+
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+def test_eq_assembly_parity(which, request):
+    case = request.getfixturevalue(which)
+    wl = case.wl
+    for k in range(0, 16, 5):
+        _say(f"eq assembly parity {wl.name} eval point {k}")
+        mu, w, tau = wl.mus[k], wl.w_eval[k], wl.tau_eval[k]
+        g = _eq_gpu(case, mu, w, tau)
+        oj = case.orom.jacobian(mu, w, tau)
+        orr = case.orom.residual(mu, w, tau)
+        assert abs(g["J"] - oj["J"]) <= 1e-12 * oj["J"]
+        assert abs(g["Jr"] - oj["J"]) <= 1e-12 * oj["J"]
+        assert rel(g["g"], oj["g"]) < 1e-12
+        assert rel(g["H"], oj["H"]) < 1e-12
+        assert rel(g["Jt"], oj["Jt"]) < 1e-12
+        assert rel(g["Ft"], orr["Ft"]) < 1e-12
+        assert rel(g["PhiT_r"], orr["PhiT_r"]) < 1e-12
+        assert g["n_bad"] == 0
+
+
+def test_eq_assembly_is_deterministic(euler_case):
+    wl = euler_case.wl
+    a = _eq_gpu(euler_case, wl.mus[1], wl.w_eval[1], wl.tau_eval[1])
+    b = _eq_gpu(euler_case, wl.mus[1], wl.w_eval[1], wl.tau_eval[1])
+    for k in ("g", "H", "Jt", "Ft"):
+        assert np.array_equal(a[k], b[k])
+    assert a["J"] == b["J"]
+
+
+def test_invalid_point_reported(tiny_case):
+    wl = tiny_case.wl
+    _say("invalid evaluation point")
+    g = _eq_gpu(tiny_case, wl.mus[0], wl.w_eval[0], 80.0 * wl.tau_eval[0])
+    o = tiny_case.orom.residual(wl.mus[0], wl.w_eval[0], 80.0 * wl.tau_eval[0])
+    assert np.isinf(g["J"]) and np.isinf(g["Jr"]) and o["invalid"]
+    assert g["n_bad"] == o["n_bad"] > 0
+
+
+def test_single_element_and_boundary_only_eq_sets(dev):
+    wl = synth.euler_p2(nx=8, ny=4, n=20, m=10, n_s=12)
+    for el in ([5], np.nonzero((wl.mesh.elem_nbr < 0).any(axis=1))[0]):
+        _say(f"eq set of size {len(el)}")
+        case = Case(wl, dev, eq_elem=el, eq_rho=np.linspace(0.5, 1.5, len(el)))
+        mu, w, tau = wl.mus[2], wl.w_eval[2], wl.tau_eval[2]
+        g = _eq_gpu(case, mu, w, tau)
+        oj = case.orom.jacobian(mu, w, tau)
+        assert rel(g["g"], oj["g"]) < 1e-12 and rel(g["H"], oj["H"]) < 1e-12
+
+
+def test_gauss_newton_steps_parity(tiny_case):
+    """Twenty steps from the plain start; each GPU step is compared with the
+    oracle's step from the same z_n (normal equations, Armijo backtracking)."""
+    import torch
+    from oracle import eq as oeq
+    from oracle import gn as ogn
+    case = tiny_case
+    wl, d = case.wl, case.dev
+    mu = wl.mus[0]
+    w0, t0 = oeq.plain_start(wl, mu)
+    z = np.r_[w0, t0]
+    n = wl.n
+    for it in range(20):
+        _say(f"gauss-newton step {it}")
+        w, tau = _t(z[:n], d), _t(z[n:], d)
+        st, info = case.rom.gauss_newton_step(mu, w, tau)
+        z_gpu = np.r_[w.cpu().numpy(), tau.cpu().numpy()]
+        wo, to, oinfo = ogn.gn_step(case.orom, mu, z[:n], z[n:])
+        assert st == 0 and oinfo["status"] in ("ok", "converged")
+        assert info["n_backtrack"] == oinfo["n_backtrack"]
+        H = case.orom.jacobian(mu, z[:n], z[n:])["H"]
+        bound = max(1e-12, 1e-13 * np.linalg.cond(H))
+        step_o = np.r_[wo, to] - z
+        assert np.linalg.norm(z_gpu - np.r_[wo, to]) <= bound * max(np.linalg.norm(step_o), 1e-300) + 1e-14 * np.linalg.norm(z)
+        assert abs(info["J_new"] - oinfo["J_new"]) <= 1e-10 * oinfo["J_old"]
+        z = np.r_[wo, to]
+
+
+def test_full_size_euler_samples(dev):
+    """16384 P2 elements, 819 EQ elements, n = 20, m = 10 (the benchmark
+    shape): full EQ assembly against the oracle, and the full-order residual
+    on a sample of elements (every 97th plus all boundary-adjacent ones of
+    the first rows) computed element by element by the oracle."""
+    import torch
+    wl = synth.euler_p2()
+    case = Case(wl, dev)
+    k = 4
+    mu, w, tau = wl.mus[k], wl.w_eval[k], wl.tau_eval[k]
+    _say("full size: eq assembly")
+    g = _eq_gpu(case, mu, w, tau)
+    oj = case.orom.jacobian(mu, w, tau)
+    assert rel(g["g"], oj["g"]) < 1e-12 and rel(g["H"], oj["H"]) < 1e-12
+    assert abs(g["J"] - oj["J"]) <= 1e-12 * oj["J"]
+    _say("full size: hdm_assemble residual + jacobians on sampled elements")
+    U = wl.Phi @ w
+    x = wl.X + wl.Psi @ tau
+    gg = _hdm_gpu(case, mu, U, x, jac=True)
+    Ne = wl.mesh.n_elem
+    el = np.unique(np.r_[np.arange(0, Ne, 97), np.arange(0, 256), np.arange(Ne - 256, Ne)])
+    o = case.oprob.evaluate(el, *case.oprob.gather_state(el, U, x), mu, jac=True)
+    p = case.prob
+    assert rel(gg["R"].reshape(Ne, -1)[el], o["R"]) < 1e-12
+    assert rel(gg["N"][el], o["N"]) < 1e-12
+    assert rel(gg["dRdU"].reshape(Ne, p.nue, p.nue)[el], o["dRdU"]) < 1e-12
+    assert rel(gg["dRdUn"].reshape(Ne, p.nue, p.nun)[el], o["dRdUn"]) < 1e-12
+    assert rel(gg["dRdx"].reshape(Ne, p.nue, p.nxe)[el], o["dRdx"]) < 1e-12
+    del gg
+    torch.cuda.empty_cache()
