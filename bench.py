@@ -1,0 +1,231 @@
+"""Benchmark of the EQ-hyperreduced assembly on one MI355X.
+
+Workload: P2 compressible Euler on a 128x64-cell mesh of [0,2]x[0,1]
+(16384 elements), reduced bases n = 20 (state) and m = 10 (mapping), 819
+EQ-sampled elements with lognormal(0, 0.5) weights, FP64.  Inputs are
+seeded synthetic data (see synth/); they stay resident in HBM.
+
+A step is one eq_assemble_jacobian call at one of 16 seeded evaluation
+points (lift, mapped geometry, DG volume and face terms with exact point
+Jacobians, projection onto [Phi Psi], rho-weighting and the Gram
+reduction to the Gauss-Newton matrix and gradient).  value = sampled
+element-evals per second (n_s per step).  The line also carries:
+  solves_per_s   Gauss-Newton solves to |S~|,|T~| <= 1e-8 from the 16
+                 seeded evaluation points (each a full rom_gauss_newton_step
+                 loop including line searches);
+  hdm_assemble   the full-order element loop over all 16384 elements with
+                 all Jacobian blocks (evals/s);
+  roofline       for the dominant kernel (the EQ element kernel), timed with
+                 HIP events bracketing its launches on the caller's stream;
+  cpu_baseline   the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "EQ residual+Jacobian element-evals/s; ROM Gauss-Newton solves/s to ||r||<=1e-8"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+
+# Algorithmic work per sampled element of the EQ Jacobian assembly at
+# nue = 24, nun = 36, nxe = 12, n = 20, m = 10 (FP64):
+#   bytes: gathered operands read (Phi_e 24x20, Phi_e' 36x20, Psi_e 12x10,
+#   X_e 12 doubles, rho and index 12 B) plus the Jacobian rows written
+#   (25 x 30 doubles) and residual rows (25 doubles).
+#   flops: the projection and reduction of the method, A_e = J^U Phi_e +
+#   J^U' Phi_e' (2*24*60*20), B_e = J^x Psi_e (2*24*12*10), H (2*25*30*30 / 2
+#   + diag), g (2*25*30), lift (2*(60*20 + 12*10)); physics not counted.
+EQ_BYTES_PER_ELEM = 8 * (24 * 20 + 36 * 20 + 12 * 10 + 12) + 12 + 8 * (25 * 30 + 25)
+EQ_FLOPS_PER_ELEM = 2 * 24 * 60 * 20 + 2 * 24 * 12 * 10 + 25 * 30 * 31 + 2 * 25 * 30 + 2 * (60 * 20 + 12 * 10)
+# Full-order loop with Jacobians: reads U_e, the neighbour traces, x_e, X_e
+# and connectivity; writes R_e, N_e, dR/dU_e, dR/dU_e', dR/dx_e, dN/dx_e.
+HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, budget_s: float):
+    """The oracle's EQ Jacobian assembly on the host (single thread)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import eq as oeq
+    from oracle import residual as ors
+    with threadpool_limits(1):
+        orom = oeq.ROM(ors.Problem(wl), wl.Phi, wl.Psi, wl.eq_elem, wl.eq_rho)
+        orom.jacobian(wl.mus[0], wl.w_eval[0], wl.tau_eval[0])   # warm-up
+        t0 = time.perf_counter()
+        calls = 0
+        while True:
+            k = calls % wl.mus.shape[0]
+            orom.jacobian(wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
+            calls += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    return {"value": calls * wl.n_s / dt, "unit": "element-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{calls} oracle eq_assemble_jacobian calls x {wl.n_s} EQ elements "
+                      f"(same 16384-element Euler P2 workload), {dt:.1f} s, one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-solve", action="store_true", help="skip the solves/s leg")
+    ap.add_argument("--no-hdm", action="store_true", help="skip the full-order leg")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device copy of this size (traffic-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 8 * n, "launches": 5}))
+        return
+
+    import synth
+    from paper_2305_15661_amd import ift
+
+    t_setup = time.perf_counter()
+    wl = synth.euler_p2()
+    prob = ift.Problem.from_workload(wl)
+    Phi = torch.tensor(wl.Phi, device=dev)
+    Psi = torch.tensor(wl.Psi, device=dev)
+    rom = ift.ROM(prob, Phi, Psi, wl.eq_elem, wl.eq_rho)
+    del Phi, Psi
+    D, n = rom.D, rom.n
+    W = torch.tensor(wl.w_eval, device=dev)
+    T = torch.tensor(wl.tau_eval, device=dev)
+    J = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(D, dtype=torch.float64, device=dev)
+    H = torch.zeros(D * D, dtype=torch.float64, device=dev)
+    n_eval = wl.mus.shape[0]
+    log(f"setup {time.perf_counter() - t_setup:.1f}s: {wl.mesh.n_elem} elements, n_s={wl.n_s}, n={n}, m={rom.m}")
+
+    # ---------------------------------------------------------- timed steps
+    for s in range(args.warmup):
+        k = s % n_eval
+        rom.eq_assemble_jacobian(wl.mus[k], W[k], T[k], J, g, H)
+    torch.cuda.synchronize()
+    ift.profile_enable(True)
+    ift.profile_reset()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        k = s % n_eval
+        rom.eq_assemble_jacobian(wl.mus[k], W[k], T[k], J, g, H)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ift.profile_enable(False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = max(gpu_ms, 1e3 * wall) / args.steps
+    value = wl.n_s / (ms_per_step * 1e-3)
+    cnt, kern_ms = ift.profile_read("eq_jac")
+    cnt_g, gram_ms = ift.profile_read("gram")
+    k_avg_s = kern_ms / cnt * 1e-3
+    log(f"eq_assemble_jacobian: {ms_per_step * 1e3:.1f} us/step, element kernel {k_avg_s * 1e6:.1f} us, "
+        f"gram {gram_ms / max(cnt_g, 1) * 1e3:.1f} us")
+    flops = EQ_FLOPS_PER_ELEM * wl.n_s
+    achieved = flops / k_avg_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "kernel": "k_eq_jac<Euler P2, fp64>", "launch_avg_us": k_avg_s * 1e6,
+                "algorithmic_flops_per_launch": flops,
+                "hbm_achieved_GBs": EQ_BYTES_PER_ELEM * wl.n_s / k_avg_s / 1e9}
+    out = {"metric": METRIC, "value": value, "unit": "element-evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "euler_p2 128x64 cells (16384 P2 elements), n=20, m=10, 819 EQ elements",
+                      "n_s": int(wl.n_s), "n": n, "m": int(rom.m), "n_elem": int(wl.mesh.n_elem)},
+           "roofline": roofline}
+
+    # ------------------------------------------------------------- solves/s
+    if not args.no_solve:
+        from oracle import eq as oeq  # noqa: F401  (only for the start points' shape check)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        conv, iters = 0, []
+        for k in range(n_eval):
+            w = W[k].clone()
+            tau = T[k].clone()
+            for it in range(60):
+                st, info = rom.gauss_newton_step(wl.mus[k], w, tau)
+                if info["converged"] or st != 0:
+                    break
+            conv += int(info["converged"] == 1)
+            iters.append(it)
+        dt = time.perf_counter() - t0
+        out["solves_per_s"] = conv / dt
+        out["solves"] = {"converged": conv, "attempted": n_eval, "mean_gn_iterations": float(np.mean(iters)),
+                         "tol": 1e-8, "seconds": dt}
+        log(f"solves: {conv}/{n_eval} converged, {conv / dt:.1f} solves/s, mean iterations {np.mean(iters):.1f}")
+
+    # ---------------------------------------------------------- full order
+    if not args.no_hdm:
+        p = prob
+        Ne = p.n_elem
+        U = torch.tensor(wl.Phi @ wl.w_eval[0], device=dev)
+        x = torch.tensor(wl.X + wl.Psi @ wl.tau_eval[0], device=dev)
+        R = torch.empty(p.N_u, dtype=torch.float64, device=dev)
+        Nn = torch.empty(Ne, dtype=torch.float64, device=dev)
+        dRdU = torch.empty(Ne * p.nue * p.nue, dtype=torch.float64, device=dev)
+        dRdUn = torch.empty(Ne * p.nue * p.nun, dtype=torch.float64, device=dev)
+        dRdx = torch.empty(Ne * p.nue * p.nxe, dtype=torch.float64, device=dev)
+        dNdx = torch.empty(Ne * p.nxe, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            p.hdm_assemble(wl.mus[0], U, x, R, Nn, dRdU, dRdUn, dRdx, dNdx)
+        torch.cuda.synchronize()
+        ift.profile_enable(True)
+        ift.profile_reset()
+        reps = 10
+        for _ in range(reps):
+            p.hdm_assemble(wl.mus[0], U, x, R, Nn, dRdU, dRdUn, dRdx, dNdx)
+        torch.cuda.synchronize()
+        ift.profile_enable(False)
+        c, ms = ift.profile_read("hdm")
+        t_avg = ms / c * 1e-3
+        gbs = HDM_BYTES_PER_ELEM * Ne / t_avg / 1e9
+        out["hdm_assemble"] = {"evals_per_s": Ne / t_avg, "launch_avg_us": t_avg * 1e6, "bound": "hbm",
+                               "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS}
+        log(f"hdm_assemble: {t_avg * 1e6:.1f} us, {Ne / t_avg:.3e} evals/s, {gbs:.0f} GB/s")
+        del dRdU, dRdUn, dRdx
+
+    # ------------------------------------------------------------ CPU leg
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.1f} evals/s")
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

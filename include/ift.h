@@ -180,6 +180,17 @@ typedef struct {
 ift_status rom_gauss_newton_step(ift_rom* rom, const double* mu, double* w, double* tau,
                                  const ift_gn_params* params, ift_gn_info* info, hipStream_t stream);
 
+/* Kernel timing.  While enabled, every launch of the library's element
+ * kernels and reductions is bracketed by HIP events on the caller's stream
+ * (events are created on first use and reused).  ift_profile_read
+ * synchronises on the recorded events and returns, for kernel class
+ * `which` (IFT_PROF_*), the number of launches and their summed duration in
+ * milliseconds since the last reset.  Not thread-safe. */
+enum { IFT_PROF_HDM = 0, IFT_PROF_EQ_RES = 1, IFT_PROF_EQ_JAC = 2, IFT_PROF_GRAM = 3, IFT_PROF_NKIND = 4 };
+ift_status ift_profile_enable(int on);
+ift_status ift_profile_reset(void);
+ift_status ift_profile_read(int which, int* count, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

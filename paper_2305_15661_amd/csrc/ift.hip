@@ -73,6 +73,83 @@ struct ift_rom {
   int* d_flag_or = nullptr;
 };
 
+// ---------------------------------------------------------------- profiling
+namespace {
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_live;     // recorded, not yet read
+std::vector<hipEvent_t> g_prof_pool;  // idle events
+int g_prof_count[IFT_PROF_NKIND] = {0, 0, 0, 0};
+double g_prof_ms[IFT_PROF_NKIND] = {0, 0, 0, 0};
+
+hipEvent_t prof_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch: call begin before and end after enqueueing it.
+struct ProfScope {
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(int k, hipStream_t s) : kind(k), st(s) {
+    if (!g_prof_on) return;
+    a = prof_event();
+    b = prof_event();
+    if (a) (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!g_prof_on || !a || !b) return;
+    (void)hipEventRecord(b, st);
+    g_prof_live.push_back({kind, a, b});
+  }
+};
+
+void prof_drain() {
+  for (auto& r : g_prof_live) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      g_prof_count[r.kind] += 1;
+      g_prof_ms[r.kind] += ms;
+    }
+    g_prof_pool.push_back(r.a);
+    g_prof_pool.push_back(r.b);
+  }
+  g_prof_live.clear();
+}
+}  // namespace
+
+extern "C" ift_status ift_profile_enable(int on) {
+  g_prof_on = on != 0;
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_profile_reset(void) {
+  prof_drain();
+  for (int k = 0; k < IFT_PROF_NKIND; ++k) {
+    g_prof_count[k] = 0;
+    g_prof_ms[k] = 0.0;
+  }
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_profile_read(int which, int* count, double* total_ms) {
+  if (which < 0 || which >= IFT_PROF_NKIND) return IFT_EINVAL;
+  prof_drain();
+  if (count) *count = g_prof_count[which];
+  if (total_ms) *total_ms = g_prof_ms[which];
+  return IFT_OK;
+}
+
 // --------------------------------------------------------- reference tables
 // Closed forms: barycentric Lagrange bases of degree 1 and 2; the 3-point
 // degree-2 rule; the 6-point degree-4 rule of Dunavant (1985) in its
@@ -378,7 +455,11 @@ extern "C" ift_status hdm_assemble(ift_problem* pr, const double* mu, const doub
   a.eps = pr->eps_g;
   a.n_elem = pr->n_elem;
   const bool jac = dRdU || dRdUn || dRdx || dNdx;
-  ift_status s = dispatch_hdm<double>(pr, a, jac, stream);
+  ift_status s;
+  {
+    ProfScope ps(IFT_PROF_HDM, stream);
+    s = dispatch_hdm<double>(pr, a, jac, stream);
+  }
   if (s != IFT_OK) return s;
   if (n_bad) {
     hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, stream, (const double*)nullptr, (const int*)pr->d_flags,
@@ -571,6 +652,7 @@ static void dispatch_eq_r(const ift_problem* pr, const EqArgs& a, bool jac, hipS
 }
 
 static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, hipStream_t st) {
+  ProfScope ps(jac ? IFT_PROF_EQ_JAC : IFT_PROF_EQ_RES, st);
   if (r->precision == IFT_FP32_ELEM) dispatch_eq_r<float>(r->prob, a, jac, st);
   else dispatch_eq_r<double>(r->prob, a, jac, st);
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
@@ -596,6 +678,7 @@ extern "C" ift_status eq_assemble_residual(ift_rom* r, const double* mu, const d
 static ift_status gram(ift_rom* r, double* H, double* g, hipStream_t stream) {
   const int D = r->D;
   const size_t shm = (size_t)(GRAM_TILE * D + GRAM_TILE) * sizeof(double);
+  ProfScope ps(IFT_PROF_GRAM, stream);
   hipLaunchKernelGGL(k_gram_partial, dim3(r->n_gram_blk), dim3(256), shm, stream, (const double*)r->d_Jt,
                      (const double*)r->d_Ft, r->nrows, D, r->d_gram_part);
   const int nent = D * (D + 1) / 2 + D;

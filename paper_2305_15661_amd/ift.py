@@ -68,7 +68,11 @@ EXPORTS = {
     "eq_assemble_residual": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P]),
     "eq_assemble_jacobian": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rom_gauss_newton_step": (ctypes.c_int, [_P, _D, _P, _P, ctypes.POINTER(GNParams), ctypes.POINTER(GNInfo), _P]),
+    "ift_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "ift_profile_reset": (ctypes.c_int, []),
+    "ift_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
 }
+PROF = {"hdm": 0, "eq_res": 1, "eq_jac": 2, "gram": 3}
 
 _lib = None
 
@@ -232,7 +236,22 @@ class ROM:
         return st, info.as_dict()
 
 
-# backwards-compatible names matching the C ABI
+def profile_enable(on: bool = True):
+    _check(lib().ift_profile_enable(int(bool(on))), "ift_profile_enable")
+
+
+def profile_reset():
+    _check(lib().ift_profile_reset(), "ift_profile_reset")
+
+
+def profile_read(which: str):
+    """(launch count, total milliseconds) of one kernel class since the last reset."""
+    c, ms = ctypes.c_int(), ctypes.c_double()
+    _check(lib().ift_profile_read(PROF[which], ctypes.byref(c), ctypes.byref(ms)), "ift_profile_read")
+    return c.value, ms.value
+
+
+# names matching the C ABI
 def hdm_assemble(prob: Problem, *a, **k):
     return prob.hdm_assemble(*a, **k)
 
