@@ -5,18 +5,21 @@ Workload: P2 compressible Euler on a 128x64-cell mesh of [0,2]x[0,1]
 EQ-sampled elements with lognormal(0, 0.5) weights, FP64.  Inputs are
 seeded synthetic data (see synth/); they stay resident in HBM.
 
-A step is one eq_assemble_jacobian call at one of 16 seeded evaluation
-points (lift, mapped geometry, DG volume and face terms with exact point
-Jacobians, projection onto [Phi Psi], rho-weighting and the Gram
-reduction to the Gauss-Newton matrix and gradient).  value = sampled
-element-evals per second (n_s per step).  The line also carries:
+A step is one batched eq_assemble_jacobian call over the 16 seeded
+evaluation points (mu, w, tau) of the workload: per sampled element and
+point, the lift, mapped geometry, DG volume and face terms with exact point
+Jacobians, the projection onto [Phi_e; Phi_e'] and Psi_e, and the
+rho-weighted Gram reduction to the Gauss-Newton matrix and gradient.
+value = sampled element-evals per second (16 x n_s per step).  The line
+also carries:
   solves_per_s   Gauss-Newton solves to |S~|,|T~| <= 1e-8 from the 16
-                 seeded evaluation points (each a full rom_gauss_newton_step
+                 seeded evaluation points (each a rom_gauss_newton_step
                  loop including line searches);
   hdm_assemble   the full-order element loop over all 16384 elements with
                  all Jacobian blocks (evals/s);
-  roofline       for the dominant kernel (the EQ element kernel), timed with
-                 HIP events bracketing its launches on the caller's stream;
+  roofline       for the kernel with the largest share of the step time,
+                 timed with HIP events bracketing its launches on the
+                 caller's stream;
   cpu_baseline   the CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -36,16 +39,24 @@ METRIC = "EQ residual+Jacobian element-evals/s; ROM Gauss-Newton solves/s to ||r
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
-# Algorithmic work per sampled element of the EQ Jacobian assembly at
-# nue = 24, nun = 36, nxe = 12, n = 20, m = 10 (FP64):
-#   bytes: gathered operands read (Phi_e 24x20, Phi_e' 36x20, Psi_e 12x10,
-#   X_e 12 doubles, rho and index 12 B) plus the Jacobian rows written
-#   (25 x 30 doubles) and residual rows (25 doubles).
-#   flops: the projection and reduction of the method, A_e = J^U Phi_e +
-#   J^U' Phi_e' (2*24*60*20), B_e = J^x Psi_e (2*24*12*10), H (2*25*30*30 / 2
-#   + diag), g (2*25*30), lift (2*(60*20 + 12*10)); physics not counted.
-EQ_BYTES_PER_ELEM = 8 * (24 * 20 + 36 * 20 + 12 * 10 + 12) + 12 + 8 * (25 * 30 + 25)
-EQ_FLOPS_PER_ELEM = 2 * 24 * 60 * 20 + 2 * 24 * 12 * 10 + 25 * 30 * 31 + 2 * 25 * 30 + 2 * (60 * 20 + 12 * 10)
+# Algorithmic work per sampled element-eval at nue = 24, nun = 36, nxe = 12,
+# n = 20, m = 10 (FP64), per kernel of the Jacobian path:
+#  points  (point physics): reads the gathered operands it lifts
+#          (Phi_e 24x20, Phi_e' 36x20, Psi_e 12x10, X_e 12 doubles);
+#  eq_jac  (assembly + projection): reads Phi_e, Phi_e', Psi_e and writes
+#          the 25 Jacobian rows (25 x 30) and residual rows (25); its dense
+#          contraction A_e = J^U Phi_e + J^U' Phi_e' (2*24*60*20 flops) and
+#          B_e = J^x Psi_e (2*24*12*10), distortion row (2*12*10);
+#  gram    reads the rows (25 x 31 doubles) and forms J~^T J~ and J~^T F~
+#          (2*25*30*30 + 2*25*30 flops).
+KBYTES = {"points": 8 * (24 * 20 + 36 * 20 + 12 * 10 + 12),
+          "eq_jac": 8 * (24 * 20 + 36 * 20 + 12 * 10) + 8 * (25 * 30 + 25),
+          "gram": 8 * 25 * 31}
+KFLOPS = {"points": None,
+          "eq_jac": 2 * 24 * 60 * 20 + 2 * 24 * 12 * 10 + 2 * 12 * 10,
+          "gram": 2 * 25 * 30 * 30 + 2 * 25 * 30}
+KNAMES = {"points": "k_points_eq<Euler P2, fp64>", "eq_jac": "k_eq_asm<Euler P2, fp64>",
+          "gram": "k_gram_part + k_gram_final"}
 # Full-order loop with Jacobians: reads U_e, the neighbour traces, x_e, X_e
 # and connectivity; writes R_e, N_e, dR/dU_e, dR/dU_e', dR/dx_e, dN/dx_e.
 HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)
@@ -129,9 +140,16 @@ def main():
     log(f"setup {time.perf_counter() - t_setup:.1f}s: {wl.mesh.n_elem} elements, n_s={wl.n_s}, n={n}, m={rom.m}")
 
     # ---------------------------------------------------------- timed steps
+    P = n_eval
+    rom.reserve(P)
+    mu2 = np.zeros((P, 2))
+    mu2[:, :wl.mus.shape[1]] = wl.mus
+    MU = torch.tensor(mu2, device=dev)
+    JB = torch.zeros(P, dtype=torch.float64, device=dev)
+    GB = torch.zeros(P * D, dtype=torch.float64, device=dev)
+    HB = torch.zeros(P * D * D, dtype=torch.float64, device=dev)
     for s in range(args.warmup):
-        k = s % n_eval
-        rom.eq_assemble_jacobian(wl.mus[k], W[k], T[k], J, g, H)
+        rom.eq_assemble_jacobian_batch(MU, W, T, JB, GB, HB)
     torch.cuda.synchronize()
     ift.profile_enable(True)
     ift.profile_reset()
@@ -140,32 +158,37 @@ def main():
     ev0.record()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        k = s % n_eval
-        rom.eq_assemble_jacobian(wl.mus[k], W[k], T[k], J, g, H)
+        rom.eq_assemble_jacobian_batch(MU, W, T, JB, GB, HB)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ift.profile_enable(False)
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = max(gpu_ms, 1e3 * wall) / args.steps
-    value = wl.n_s / (ms_per_step * 1e-3)
-    cnt, kern_ms = ift.profile_read("eq_jac")
-    cnt_g, gram_ms = ift.profile_read("gram")
-    k_avg_s = kern_ms / cnt * 1e-3
-    log(f"eq_assemble_jacobian: {ms_per_step * 1e3:.1f} us/step, element kernel {k_avg_s * 1e6:.1f} us, "
-        f"gram {gram_ms / max(cnt_g, 1) * 1e3:.1f} us")
-    flops = EQ_FLOPS_PER_ELEM * wl.n_s
-    achieved = flops / k_avg_s / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "kernel": "k_eq_jac<Euler P2, fp64>", "launch_avg_us": k_avg_s * 1e6,
-                "algorithmic_flops_per_launch": flops,
-                "hbm_achieved_GBs": EQ_BYTES_PER_ELEM * wl.n_s / k_avg_s / 1e9}
+    evals_per_step = P * wl.n_s
+    value = evals_per_step / (ms_per_step * 1e-3)
+    kt = {k: ift.profile_read(k) for k in ("points", "eq_jac", "gram")}
+    avg = {k: (ms / c * 1e-3 if c else 0.0) for k, (c, ms) in kt.items()}
+    log("step %.1f us: " % (ms_per_step * 1e3) + ", ".join(f"{k} {v * 1e6:.1f} us" for k, v in avg.items()))
+    dom = max(avg, key=avg.get)
+    t_dom = avg[dom]
+    gbs = KBYTES[dom] * evals_per_step / t_dom / 1e9
+    if dom == "points" or gbs / PEAK_HBM_GBS >= (KFLOPS[dom] or 0) * evals_per_step / t_dom / 1e12 / PEAK_FP64_TFLOPS:
+        roofline = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
+    else:
+        tf = KFLOPS[dom] * evals_per_step / t_dom / 1e12
+        roofline = {"bound": "mfma" if dom == "eq_jac" else "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS,
+                    "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS}
+    roofline.update({"traffic": None, "kernel": KNAMES[dom], "launch_avg_us": t_dom * 1e6,
+                     "algorithmic_bytes_per_launch": KBYTES[dom] * evals_per_step,
+                     "algorithmic_flops_per_launch": (KFLOPS[dom] or 0) * evals_per_step,
+                     "kernels_us": {k: v * 1e6 for k, v in avg.items()}})
     out = {"metric": METRIC, "value": value, "unit": "element-evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "euler_p2 128x64 cells (16384 P2 elements), n=20, m=10, 819 EQ elements",
-                      "n_s": int(wl.n_s), "n": n, "m": int(rom.m), "n_elem": int(wl.mesh.n_elem)},
+           "config": {"workload": "euler_p2 128x64 cells (16384 P2 elements), n=20, m=10, 819 EQ elements, "
+                                  "16 evaluation points per step",
+                      "n_s": int(wl.n_s), "n": n, "m": int(rom.m), "n_elem": int(wl.mesh.n_elem), "points": P},
            "roofline": roofline}
 
     # ------------------------------------------------------------- solves/s
@@ -212,10 +235,12 @@ def main():
         torch.cuda.synchronize()
         ift.profile_enable(False)
         c, ms = ift.profile_read("hdm")
-        t_avg = ms / c * 1e-3
+        c2, ms2 = ift.profile_read("points")
+        t_avg = (ms + ms2) / c * 1e-3
         gbs = HDM_BYTES_PER_ELEM * Ne / t_avg / 1e9
         out["hdm_assemble"] = {"evals_per_s": Ne / t_avg, "launch_avg_us": t_avg * 1e6, "bound": "hbm",
-                               "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS}
+                               "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS,
+                               "points_us": ms2 / c2 * 1e3, "assembly_us": ms / c * 1e3}
         log(f"hdm_assemble: {t_avg * 1e6:.1f} us, {Ne / t_avg:.3e} evals/s, {gbs:.0f} GB/s")
         del dRdU, dRdUn, dRdx
 

@@ -157,6 +157,21 @@ ift_status eq_assemble_jacobian(ift_rom* rom, const double* mu, const double* w,
                                 double* Jobj, double* g, double* H, double* Jt, int* n_bad,
                                 hipStream_t stream);
 
+/* Batched evaluation: n_pts evaluation points (mu_p, w_p, tau_p) of the same
+ * ROM in one launch (e.g. many parameters, or several line-search trial
+ * points).  ift_rom_reserve sizes the per-point workspaces for up to
+ * max_pts points (it allocates, and synchronises the device); the batched
+ * calls then allocate nothing and require n_pts <= max_pts.
+ * mu [n_pts][2] (DEVICE; Burgers uses mu[p][0]), w [n_pts][n],
+ * tau [n_pts][m]; outputs Jobj [n_pts], g [n_pts][n+m], H [n_pts][n+m][n+m],
+ * n_bad [n_pts] or NULL, each with the meaning of the single-point call. */
+ift_status ift_rom_reserve(ift_rom* rom, int max_pts);
+ift_status eq_assemble_residual_batch(ift_rom* rom, int n_pts, const double* mu, const double* w,
+                                      const double* tau, double* Jobj, int* n_bad, hipStream_t stream);
+ift_status eq_assemble_jacobian_batch(ift_rom* rom, int n_pts, const double* mu, const double* w,
+                                      const double* tau, double* Jobj, double* g, double* H, int* n_bad,
+                                      hipStream_t stream);
+
 typedef struct {
   double lambda;       /* LM weight on the tau block (0 = Gauss-Newton)     */
   double c1;           /* sufficient-decrease constant (1e-4)               */
@@ -186,7 +201,14 @@ ift_status rom_gauss_newton_step(ift_rom* rom, const double* mu, double* w, doub
  * synchronises on the recorded events and returns, for kernel class
  * `which` (IFT_PROF_*), the number of launches and their summed duration in
  * milliseconds since the last reset.  Not thread-safe. */
-enum { IFT_PROF_HDM = 0, IFT_PROF_EQ_RES = 1, IFT_PROF_EQ_JAC = 2, IFT_PROF_GRAM = 3, IFT_PROF_NKIND = 4 };
+enum {
+  IFT_PROF_HDM = 0,     /* full-order assembly / values kernels              */
+  IFT_PROF_EQ_RES = 1,  /* EQ residual kernel                                */
+  IFT_PROF_EQ_JAC = 2,  /* EQ Jacobian assembly + projection kernel          */
+  IFT_PROF_GRAM = 3,    /* Gram reduction (both stages)                      */
+  IFT_PROF_POINTS = 4,  /* point-physics kernels of the Jacobian paths       */
+  IFT_PROF_NKIND = 5
+};
 ift_status ift_profile_enable(int on);
 ift_status ift_profile_reset(void);
 ift_status ift_profile_read(int which, int* count, double* total_ms);

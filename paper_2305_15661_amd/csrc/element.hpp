@@ -1,4 +1,4 @@
-// One DG element on one 64-lane wavefront.
+// One DG element per 256-thread workgroup (four 64-lane waves).
 //
 // Discretisation (Section 2.3 of the paper, readings where it is silent):
 //   R_e[i,c] = sum_faces int phi_i H_c(u-, u+, n~) ds - int grad_0 phi_i . F_c dX,
@@ -10,14 +10,14 @@
 // mapping validity test uses g = det J / det J0, and the distortion of
 // eq. (dist_elem1) uses G = J J0^{-1}.
 //
-// Work split inside the wave (all data of one element staged in LDS):
+// Work split inside the workgroup (all data of one element staged in LDS):
 //   A  load / lift the element DoFs U_e, U_e', x_e, X_e;
-//   B  point physics: each lane evaluates one quadrature point, or one
+//   B  point physics: each thread evaluates one quadrature point, or one
 //      (point, input direction) pair in tangent arithmetic, giving the point
-//      fluxes and their exact Jacobians;
-//   C  residual R_e: one lane per (node, component);
-//   D  Jacobian columns: one lane per input direction (a reduced basis
-//      vector, or a unit vector for the full-order blocks).
+//      fluxes and their exact point Jacobians;
+//   C  residual R_e (one thread per (node, component)) and the explicit
+//      element Jacobian [dR/dU_e | dR/dU_e' | dR/dx_e] (one thread per
+//      entry), assembled from the point Jacobians and the basis tables.
 #pragma once
 #include "physics.hpp"
 
@@ -44,33 +44,56 @@ struct Disc {
   static constexpr int NN = (P_ + 1) * (P_ + 2) / 2;
   static constexpr int NQV = P_ == 1 ? 3 : 6;
   static constexpr int NQF = P_ + 1;
+  static constexpr int NE = P_ + 1;          // nodes per edge
   static constexpr int NUE = NN * NC;
   static constexpr int NUN = 3 * (P_ + 1) * NC;
   static constexpr int NXE = 2 * NN;
-  static constexpr int NDIR_HDM = NUE + NUN + NXE;
+  static constexpr int NDIR = NUE + NUN + NXE;  // columns of the explicit Jacobian
 };
+
+constexpr int NTHR = 256;
 
 enum { BAD_GEOM = 1, BAD_STATE = 2 };
 
+// Point data of one element: fluxes and exact point Jacobians at the
+// volume and face quadrature points, the distortion and its gradient, and
+// the validity flags.  This is what the point-physics kernel hands to the
+// assembly kernel (a plain copy through global memory).
+template <class D, class R>
+struct Pts {
+  R fv[D::NQV][D::NC][2];          // f(u_q)
+  R Af[D::NQV][D::NC][2][D::NC];   // df/du at volume points: [q][c][dim][c']
+  R gp[D::NQV][D::NN][2];          // cof(J) grad_xi phi_i
+  R H[3][D::NQF][D::NC];           // numerical flux at face points
+  R dHm[3][D::NQF][D::NC][D::NC];  // dH/du- (boundary state dependence included)
+  R dHp[3][D::NQF][D::NC][D::NC];  // dH/du+ (interior faces)
+  R dHn[3][D::NQF][D::NC][2];      // dH/dn~ (wall state dependence included)
+  R dN[D::NXE];                    // dN_e/dx_e
+  R N;
+  int bad;
+  int pad_;
+};
+
 template <class D, class R>
 struct ElemLDS {
+  RefTab tab;
   R U[D::NUE];
   R Un[D::NUN];
   R x[D::NXE];
   R X[D::NXE];
-  R fv[D::NQV][D::NC][2];
-  R Af[D::NQV][D::NC][2][D::NC];
-  R gp[D::NQV][D::NN][2];
-  R H[3][D::NQF][D::NC];
-  R dHm[3][D::NQF][D::NC][D::NC];
-  R dHp[3][D::NQF][D::NC][D::NC];
-  R dHn[3][D::NQF][D::NC][2];
-  R Re[D::NUE];
-  R N;
-  R dN[D::NXE];
   int face[3];
-  int bad;
+  Pts<D, R> p;
+  R Re[D::NUE];
+  R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
 };
+
+template <class D, class R>
+IFT_DEV void load_tab(ElemLDS<D, R>& s, int tid, int nthr) {
+  const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
+  int* dst = reinterpret_cast<int*>(&s.tab);
+  constexpr int nw = sizeof(RefTab) / sizeof(int);
+  for (int i = tid; i < nw; i += nthr) dst[i] = src[i];
+}
 
 // ----------------------------------------------------------------- phase B
 template <class D, class T, class R>
@@ -86,34 +109,65 @@ IFT_DEV void jac2(const RefTab& t, int q, const T* x, T& J00, T& J01, T& J10, T&
   }
 }
 
-// Distortion eta_e = sum_q w_q det J0 (|G|_F^2 / max(g, eps))^2 with
-// G = J J0^{-1}, g = det J / det J0 (eq. (dist_elem1), 2/d = 1).
+// Distortion integrand at volume point q, eq. (dist_elem1) with 2/d = 1:
+// w_q det J0 (|G|_F^2 / max(g, eps))^2 with G = J J0^{-1}, g = det J / det J0.
 template <class D, class T, class R>
-IFT_DEV T eta_elem(const RefTab& t, const T* x, const R* X, R eps) {
-  T eta = mk<T, R>(R(0));
-#pragma unroll
+IFT_DEV T eta_point(const RefTab& t, int q, T J00, T J01, T J10, T J11, const R* X, R eps) {
+  R K00, K01, K10, K11;
+  jac2<D, R, R>(t, q, X, K00, K01, K10, K11);
+  R dK = K00 * K11 - K01 * K10;
+  R i00 = K11 / dK, i01 = -K01 / dK, i10 = -K10 / dK, i11 = K00 / dK;
+  T G00 = J00 * i00 + J01 * i10, G01 = J00 * i01 + J01 * i11;
+  T G10 = J10 * i00 + J11 * i10, G11 = J10 * i01 + J11 * i11;
+  T nG2 = G00 * G00 + G01 * G01 + G10 * G10 + G11 * G11;
+  T g = (J00 * J11 - J01 * J10) / dK;
+  T mx = val(g) >= eps ? g : mk<T, R>(eps);
+  T r = nG2 / mx;
+  return (R(t.wv[q]) * dK) * (r * r);
+}
+
+// eta_e and, for seed >= 0, its derivative along mapping coordinate `seed`
+// of x_e (node seed/2, component seed%2): only J carries a tangent, and it
+// is sparse: dJ[a][b] = d phi_node / d xi_b for the seeded component a.
+template <class D, class R>
+IFT_DEV Tan<R> eta_elem(const RefTab& t, const R* x, const R* X, R eps, int seed) {
+  using TT = Tan<R>;
+  TT eta = {R(0), R(0)};
+  const int kn = seed >> 1, ka = seed & 1;
+#pragma unroll 1
   for (int q = 0; q < D::NQV; ++q) {
-    T J00, J01, J10, J11;
-    jac2<D, T, R>(t, q, x, J00, J01, J10, J11);
-    R K00, K01, K10, K11;
-    jac2<D, R, R>(t, q, X, K00, K01, K10, K11);
-    R dK = K00 * K11 - K01 * K10;
-    R i00 = K11 / dK, i01 = -K01 / dK, i10 = -K10 / dK, i11 = K00 / dK;
-    T G00 = J00 * i00 + J01 * i10, G01 = J00 * i01 + J01 * i11;
-    T G10 = J10 * i00 + J11 * i10, G11 = J10 * i01 + J11 * i11;
-    T nG2 = G00 * G00 + G01 * G01 + G10 * G10 + G11 * G11;
-    T g = (J00 * J11 - J01 * J10) / dK;
-    T mx = val(g) >= eps ? g : mk<T, R>(eps);
-    T r = nG2 / mx;
-    eta = eta + (R(t.wv[q]) * dK) * (r * r);
+    R J00, J01, J10, J11;
+    jac2<D, R, R>(t, q, x, J00, J01, J10, J11);
+    R d0 = R(0), d1 = R(0);
+    if (seed >= 0) {
+      d0 = R(t.dphiv[q][kn][0]);
+      d1 = R(t.dphiv[q][kn][1]);
+    }
+    TT a00 = {J00, ka == 0 ? d0 : R(0)}, a01 = {J01, ka == 0 ? d1 : R(0)};
+    TT a10 = {J10, ka == 1 ? d0 : R(0)}, a11 = {J11, ka == 1 ? d1 : R(0)};
+    eta = eta + eta_point<D, TT, R>(t, q, a00, a01, a10, a11, X, eps);
   }
   return eta;
+}
+
+template <class D, class R>
+IFT_DEV R eta_reference(const RefTab& t, const R* X) {
+  // at x = X: G = I, |G|_F^2 = 2, g = 1, so the integrand is 4
+  R a = R(0);
+#pragma unroll
+  for (int q = 0; q < D::NQV; ++q) {
+    R K00, K01, K10, K11;
+    jac2<D, R, R>(t, q, X, K00, K01, K10, K11);
+    a += R(t.wv[q]) * (K00 * K11 - K01 * K10);
+  }
+  return R(4) * a;
 }
 
 // Volume point q: state, flux, cof(J) grad phi; seed = component seeded in
 // tangent mode (-1: none).  Returns the flux Jacobian column in Af.
 template <class D, class T, class R>
-IFT_DEV void vol_point(ElemLDS<D, R>& s, const RefTab& t, int q, int seed, const PhysConst& pc, R eps) {
+IFT_DEV void vol_point(ElemLDS<D, R>& s, int q, int seed, const PhysConst& pc, R eps) {
+  const RefTab& t = s.tab;
   T u[D::NC];
 #pragma unroll
   for (int c = 0; c < D::NC; ++c) {
@@ -127,8 +181,8 @@ IFT_DEV void vol_point(ElemLDS<D, R>& s, const RefTab& t, int q, int seed, const
   if (seed <= 0) {
 #pragma unroll
     for (int c = 0; c < D::NC; ++c) {
-      s.fv[q][c][0] = val(f[c][0]);
-      s.fv[q][c][1] = val(f[c][1]);
+      s.p.fv[q][c][0] = val(f[c][0]);
+      s.p.fv[q][c][1] = val(f[c][1]);
     }
     R J00, J01, J10, J11, K00, K01, K10, K11;
     jac2<D, R, R>(t, q, s.x, J00, J01, J10, J11);
@@ -137,19 +191,19 @@ IFT_DEV void vol_point(ElemLDS<D, R>& s, const RefTab& t, int q, int seed, const
     int bad = 0;
     if (!(g > eps)) bad |= BAD_GEOM;
     if (!physical_state<D::PDE, T, R>(u, R(pc.gamma))) bad |= BAD_STATE;
-    if (bad) atomicOr(&s.bad, bad);
+    if (bad) atomicOr(&s.p.bad, bad);
 #pragma unroll
     for (int i = 0; i < D::NN; ++i) {
       R a = R(t.dphiv[q][i][0]), b = R(t.dphiv[q][i][1]);
-      s.gp[q][i][0] = J11 * a - J10 * b;
-      s.gp[q][i][1] = J00 * b - J01 * a;
+      s.p.gp[q][i][0] = J11 * a - J10 * b;
+      s.p.gp[q][i][1] = J00 * b - J01 * a;
     }
   }
   if (seed >= 0) {
 #pragma unroll
     for (int c = 0; c < D::NC; ++c) {
-      s.Af[q][c][0][seed] = der(f[c][0]);
-      s.Af[q][c][1][seed] = der(f[c][1]);
+      s.p.Af[q][c][0][seed] = der(f[c][0]);
+      s.p.Af[q][c][1][seed] = der(f[c][1]);
     }
   }
 }
@@ -157,13 +211,14 @@ IFT_DEV void vol_point(ElemLDS<D, R>& s, const RefTab& t, int q, int seed, const
 // Face point (f, q).  dir < 0: values only; dir in [0, NC): seed u-;
 // [NC, 2NC): seed u+ (interior faces); [2NC, 2NC+2): seed n~.
 template <class D, class T, class R>
-IFT_DEV void face_point(ElemLDS<D, R>& s, const RefTab& t, int f, int q, int dir, const PhysConst& pc) {
+IFT_DEV void face_point(ElemLDS<D, R>& s, int f, int q, int dir, const PhysConst& pc) {
+  const RefTab& t = s.tab;
   constexpr int NC = D::NC;
-  constexpr int NE = D::P + 1;
+  constexpr int NE = D::NE;
   const int nb = s.face[f];
   if (nb < 0 && dir >= NC && dir < 2 * NC) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s.dHp[f][q][c][dir - NC] = R(0);
+    for (int c = 0; c < NC; ++c) s.p.dHp[f][q][c][dir - NC] = R(0);
     return;
   }
   R tx = R(0), ty = R(0);
@@ -191,73 +246,66 @@ IFT_DEV void face_point(ElemLDS<D, R>& s, const RefTab& t, int f, int q, int dir
   num_flux<D::PDE, T, R>(um, up, ntx, nty, R(pc.gamma), H);
   if (dir <= 0) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s.H[f][q][c] = val(H[c]);
+    for (int c = 0; c < NC; ++c) s.p.H[f][q][c] = val(H[c]);
     if (!physical_state<D::PDE, T, R>(um, R(pc.gamma)) || !physical_state<D::PDE, T, R>(up, R(pc.gamma)))
-      atomicOr(&s.bad, BAD_STATE);
+      atomicOr(&s.p.bad, BAD_STATE);
   }
   if (dir >= 0) {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       R d = der(H[c]);
-      if (dir < NC) s.dHm[f][q][c][dir] = d;
-      else if (dir < 2 * NC) s.dHp[f][q][c][dir - NC] = d;
-      else s.dHn[f][q][c][dir - 2 * NC] = d;
+      if (dir < NC) s.p.dHm[f][q][c][dir] = d;
+      else if (dir < 2 * NC) s.p.dHp[f][q][c][dir - NC] = d;
+      else s.p.dHn[f][q][c][dir - 2 * NC] = d;
     }
   }
 }
 
-// Phase B over the lanes of the wave.  JAC selects tangent tasks.
+// Number of phase-B tasks per element.
+template <class D, bool JAC>
+constexpr int n_point_tasks() {
+  return JAC ? D::NQV * D::NC + 3 * D::NQF * (2 * D::NC + 2) + D::NXE : D::NQV + 3 * D::NQF + 1;
+}
+
+// Phase B: thread `tid` runs task `tid` (every launch has at least as many
+// threads as tasks; a single guarded task, not a loop, keeps the compiler
+// from hoisting the table loads of all task kinds at once).  JAC selects
+// tangent tasks.
 template <class D, class R, bool JAC>
-IFT_DEV void phase_points(ElemLDS<D, R>& s, int lane, const PhysConst& pc, R kappa, R eps) {
-  const RefTab& t = c_tab[D::P - 1];
+IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kappa, R eps) {
   using TT = Tan<R>;
   if (!JAC) {
-    constexpr int ntask = D::NQV + 3 * D::NQF + 1;
-    for (int k = lane; k < ntask; k += 64) {
+    constexpr int ntask = n_point_tasks<D, false>();
+    if (tid < ntask) {
+      const int k = tid;
       if (k < D::NQV) {
-        vol_point<D, R, R>(s, t, k, -1, pc, eps);
+        vol_point<D, R, R>(s, k, -1, pc, eps);
       } else if (k < D::NQV + 3 * D::NQF) {
         int r = k - D::NQV;
-        face_point<D, R, R>(s, t, r / D::NQF, r % D::NQF, -1, pc);
+        face_point<D, R, R>(s, r / D::NQF, r % D::NQF, -1, pc);
       } else {
-        R eta = eta_elem<D, R, R>(t, s.x, s.X, eps);
-        R eta0 = R(0);
-        for (int q = 0; q < D::NQV; ++q) {
-          R K00, K01, K10, K11;
-          jac2<D, R, R>(t, q, s.X, K00, K01, K10, K11);
-          eta0 += R(t.wv[q]) * (K00 * K11 - K01 * K10);
-        }
-        s.N = kappa * (eta - R(4) * eta0);
+        Tan<R> eta = eta_elem<D, R>(s.tab, s.x, s.X, eps, -1);
+        s.p.N = kappa * (eta.v - eta_reference<D, R>(s.tab, s.X));
       }
     }
   } else {
     constexpr int nvol = D::NQV * D::NC;
     constexpr int nface = 3 * D::NQF * (2 * D::NC + 2);
-    constexpr int ntask = nvol + nface + D::NXE;
-    for (int k = lane; k < ntask; k += 64) {
+    constexpr int ntask = n_point_tasks<D, true>();
+    if (tid < ntask) {
+      const int k = tid;
       if (k < nvol) {
-        vol_point<D, TT, R>(s, t, k / D::NC, k % D::NC, pc, eps);
+        vol_point<D, TT, R>(s, k / D::NC, k % D::NC, pc, eps);
       } else if (k < nvol + nface) {
         int r = k - nvol;
         int dir = r % (2 * D::NC + 2);
         int pt = r / (2 * D::NC + 2);
-        face_point<D, TT, R>(s, t, pt / D::NQF, pt % D::NQF, dir, pc);
+        face_point<D, TT, R>(s, pt / D::NQF, pt % D::NQF, dir, pc);
       } else {
         int j = k - nvol - nface;
-        TT xs[D::NXE];
-#pragma unroll
-        for (int i = 0; i < D::NXE; ++i) xs[i] = seedv<TT, R>(s.x[i], i == j);
-        TT eta = eta_elem<D, TT, R>(t, xs, s.X, eps);
-        s.dN[j] = kappa * eta.d;
-        if (j == 0) {
-          R eta0 = R(0);
-          for (int q = 0; q < D::NQV; ++q) {
-            R K00, K01, K10, K11;
-            jac2<D, R, R>(t, q, s.X, K00, K01, K10, K11);
-            eta0 += R(t.wv[q]) * (K00 * K11 - K01 * K10);
-          }
-          s.N = kappa * (eta.v - R(4) * eta0);
-        }
+        TT eta = eta_elem<D, R>(s.tab, s.x, s.X, eps, j);
+        s.p.dN[j] = kappa * eta.d;
+        if (j == 0) s.p.N = kappa * (eta.v - eta_reference<D, R>(s.tab, s.X));
       }
     }
   }
@@ -265,132 +313,81 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int lane, const PhysConst& pc, R kap
 
 // ----------------------------------------------------------------- phase C
 template <class D, class R>
-IFT_DEV void phase_residual(ElemLDS<D, R>& s, int lane) {
-  const RefTab& t = c_tab[D::P - 1];
-  if (lane < D::NUE) {
-    const int i = lane / D::NC, c = lane % D::NC;
-    R r = R(0);
+IFT_DEV R residual_entry(const ElemLDS<D, R>& s, int r) {
+  const RefTab& t = s.tab;
+  const int i = r / D::NC, c = r % D::NC;
+  R v = R(0);
+#pragma unroll
+  for (int q = 0; q < D::NQV; ++q) v -= R(t.wv[q]) * (s.p.fv[q][c][0] * s.p.gp[q][i][0] + s.p.fv[q][c][1] * s.p.gp[q][i][1]);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int k = t.nfk[i][f];
+    if (k < 0) continue;
+#pragma unroll
+    for (int q = 0; q < D::NQF; ++q) v += R(t.wf[q] * t.L[q][k]) * s.p.H[f][q][c];
+  }
+  return v;
+}
+
+// Entry (r, col) of [dR/dU_e | dR/dU_e' | dR/dx_e] from the point Jacobians.
+template <class D, class R>
+IFT_DEV R jacobian_entry(const ElemLDS<D, R>& s, int r, int col) {
+  const RefTab& t = s.tab;
+  constexpr int NC = D::NC;
+  const int i = r / NC, c = r % NC;
+  R v = R(0);
+  if (col < D::NUE) {
+    // d/dU_e[j, c']: volume through the flux Jacobian, faces through dH/du-
+    const int j = col / NC, cc = col % NC;
 #pragma unroll
     for (int q = 0; q < D::NQV; ++q)
-      r -= R(t.wv[q]) * (s.fv[q][c][0] * s.gp[q][i][0] + s.fv[q][c][1] * s.gp[q][i][1]);
+      v -= R(t.wv[q] * t.phiv[q][j]) * (s.p.Af[q][c][0][cc] * s.p.gp[q][i][0] + s.p.Af[q][c][1][cc] * s.p.gp[q][i][1]);
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      const int k = t.nfk[i][f];
-      if (k < 0) continue;
+      const int ki = t.nfk[i][f], kj = t.nfk[j][f];
+      if (ki < 0 || kj < 0) continue;
 #pragma unroll
-      for (int q = 0; q < D::NQF; ++q) r += R(t.wf[q] * t.L[q][k]) * s.H[f][q][c];
+      for (int q = 0; q < D::NQF; ++q) v += R(t.wf[q] * t.L[q][ki] * t.L[q][kj]) * s.p.dHm[f][q][c][cc];
     }
-    s.Re[lane] = r;
+  } else if (col < D::NUE + D::NUN) {
+    // d/dU_e'[f, k, c']: only faces containing node i, through dH/du+
+    const int cn = col - D::NUE;
+    const int f = cn / (D::NE * NC), kn = (cn / NC) % D::NE, cc = cn % NC;
+    const int ki = t.nfk[i][f];
+    if (ki >= 0) {
+#pragma unroll
+      for (int q = 0; q < D::NQF; ++q) v += R(t.wf[q] * t.L[q][ki] * t.L[q][kn]) * s.p.dHp[f][q][c][cc];
+    }
+  } else {
+    // d/dx_e[k, a]: cof(J) grad phi_i is linear in x_e; n~ is linear in x_e
+    const int xx = col - D::NUE - D::NUN;
+    const int k = xx >> 1, a = xx & 1;
+#pragma unroll
+    for (int q = 0; q < D::NQV; ++q) {
+      const R K = R(t.dphiv[q][k][0] * t.dphiv[q][i][1] - t.dphiv[q][k][1] * t.dphiv[q][i][0]);
+      v += (a == 0 ? -s.p.fv[q][c][1] : s.p.fv[q][c][0]) * (R(t.wv[q]) * K);
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const int ki = t.nfk[i][f], kk = t.nfk[k][f];
+      if (ki < 0 || kk < 0) continue;
+#pragma unroll
+      for (int q = 0; q < D::NQF; ++q)
+        v += R(t.wf[q] * t.L[q][ki] * t.dL[q][kk]) * (a == 0 ? -s.p.dHn[f][q][c][1] : s.p.dHn[f][q][c][0]);
+    }
   }
+  return v;
 }
 
-// ----------------------------------------------------------------- phase D
-// Column of dR_e along a state direction (dU on the element's DoFs, dUn on
-// the neighbour face-trace DoFs).
-template <class D, class R>
-IFT_DEV void column_state(const ElemLDS<D, R>& s, const R* dU, const R* dUn, R* dR) {
-  const RefTab& t = c_tab[D::P - 1];
-  constexpr int NC = D::NC;
-  constexpr int NE = D::P + 1;
-#pragma unroll
-  for (int r = 0; r < D::NUE; ++r) dR[r] = R(0);
-#pragma unroll
-  for (int q = 0; q < D::NQV; ++q) {
-    R du[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      R a = R(0);
-#pragma unroll
-      for (int j = 0; j < D::NN; ++j) a += R(t.phiv[q][j]) * dU[j * NC + c];
-      du[c] = a;
-    }
-    R w = R(t.wv[q]);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      R f0 = R(0), f1 = R(0);
-#pragma unroll
-      for (int cc = 0; cc < NC; ++cc) {
-        f0 += s.Af[q][c][0][cc] * du[cc];
-        f1 += s.Af[q][c][1][cc] * du[cc];
-      }
-      f0 *= w;
-      f1 *= w;
-#pragma unroll
-      for (int i = 0; i < D::NN; ++i) dR[i * NC + c] -= f0 * s.gp[q][i][0] + f1 * s.gp[q][i][1];
+template <class D, class R, bool JAC>
+IFT_DEV void phase_assemble(ElemLDS<D, R>& s, int tid) {
+  for (int r = tid; r < D::NUE; r += NTHR) s.Re[r] = residual_entry<D, R>(s, r);
+  if constexpr (JAC) {
+    for (int e = tid; e < D::NUE * D::NDIR; e += NTHR) {
+      const int r = e / D::NDIR, col = e % D::NDIR;
+      s.Jx[r][col] = jacobian_entry<D, R>(s, r, col);
     }
   }
-#pragma unroll
-  for (int f = 0; f < 3; ++f) {
-#pragma unroll
-    for (int q = 0; q < D::NQF; ++q) {
-      R dm[NC], dp[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        R a = R(0), b = R(0);
-#pragma unroll
-        for (int k = 0; k < NE; ++k) {
-          a += R(t.L[q][k]) * dU[t.en[f][k] * NC + c];
-          b += R(t.L[q][k]) * dUn[(f * NE + k) * NC + c];
-        }
-        dm[c] = a;
-        dp[c] = b;
-      }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        R h = R(0);
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) h += s.dHm[f][q][c][cc] * dm[cc] + s.dHp[f][q][c][cc] * dp[cc];
-        h *= R(t.wf[q]);
-#pragma unroll
-        for (int k = 0; k < NE; ++k) dR[t.en[f][k] * NC + c] += R(t.L[q][k]) * h;
-      }
-    }
-  }
-}
-
-// Column of dR_e and dN_e along a mapping direction dx on x_e.
-template <class D, class R>
-IFT_DEV void column_map(const ElemLDS<D, R>& s, const R* dx, R* dR, R& dNv) {
-  const RefTab& t = c_tab[D::P - 1];
-  constexpr int NC = D::NC;
-  constexpr int NE = D::P + 1;
-#pragma unroll
-  for (int r = 0; r < D::NUE; ++r) dR[r] = R(0);
-#pragma unroll
-  for (int q = 0; q < D::NQV; ++q) {
-    R J00, J01, J10, J11;
-    jac2<D, R, R>(t, q, dx, J00, J01, J10, J11);
-    R w = R(t.wv[q]);
-#pragma unroll
-    for (int i = 0; i < D::NN; ++i) {
-      R a = R(t.dphiv[q][i][0]), b = R(t.dphiv[q][i][1]);
-      R g0 = w * (J11 * a - J10 * b), g1 = w * (J00 * b - J01 * a);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) dR[i * NC + c] -= s.fv[q][c][0] * g0 + s.fv[q][c][1] * g1;
-    }
-  }
-#pragma unroll
-  for (int f = 0; f < 3; ++f) {
-#pragma unroll
-    for (int q = 0; q < D::NQF; ++q) {
-      R tx = R(0), ty = R(0);
-#pragma unroll
-      for (int k = 0; k < NE; ++k) {
-        tx += R(t.dL[q][k]) * dx[2 * t.en[f][k]];
-        ty += R(t.dL[q][k]) * dx[2 * t.en[f][k] + 1];
-      }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        R h = R(t.wf[q]) * (s.dHn[f][q][c][0] * ty - s.dHn[f][q][c][1] * tx);
-#pragma unroll
-        for (int k = 0; k < NE; ++k) dR[t.en[f][k] * NC + c] += R(t.L[q][k]) * h;
-      }
-    }
-  }
-  R a = R(0);
-#pragma unroll
-  for (int k = 0; k < D::NXE; ++k) a += s.dN[k] * dx[k];
-  dNv = a;
 }
 
 }  // namespace ift

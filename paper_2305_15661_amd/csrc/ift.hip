@@ -38,6 +38,7 @@ struct ift_problem {
   int* d_Pn = nullptr;
   double* d_X = nullptr;
   int* d_flags = nullptr;
+  void* d_pts = nullptr;   // point-data workspace of the Jacobian path [n_elem]
 };
 
 struct ift_rom {
@@ -54,12 +55,15 @@ struct ift_rom {
   // workspaces
   long long nrows = 0;
   int n_gram_blk = 0;
+  int gram_rows_per = 0;
+  int max_pts = 0;        // evaluation points the per-point workspaces hold
   double* d_Jt = nullptr;
   double* d_Ft = nullptr;
   double* d_Jpart = nullptr;
   int* d_flags = nullptr;
   double* d_PTR = nullptr;
   double* d_gram_part = nullptr;
+  void* d_pts = nullptr;
   // Gauss-Newton state
   double* d_H = nullptr;
   double* d_g = nullptr;
@@ -82,8 +86,8 @@ struct ProfRec {
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof_live;     // recorded, not yet read
 std::vector<hipEvent_t> g_prof_pool;  // idle events
-int g_prof_count[IFT_PROF_NKIND] = {0, 0, 0, 0};
-double g_prof_ms[IFT_PROF_NKIND] = {0, 0, 0, 0};
+int g_prof_count[IFT_PROF_NKIND] = {};
+double g_prof_ms[IFT_PROF_NKIND] = {};
 
 hipEvent_t prof_event() {
   if (!g_prof_pool.empty()) {
@@ -302,6 +306,33 @@ static bool finite_mu(const ift_problem* pr, const double* mu) {
   return true;
 }
 
+static size_t gram_shm_bytes(int D, int rows_per) {
+  const int Dp = (D + 3) & ~3, TD = Dp / 4;
+  const int G = TD * TD <= 64 ? 4 : (TD * TD <= 128 ? 2 : 1);
+  const size_t rows = (size_t)rows_per * (Dp + 1);
+  const size_t red = (size_t)(G - 1) * TD * TD * 20;
+  return sizeof(double) * std::max(rows, red);
+}
+
+// Bytes of one element's point data (the double layout is the larger one).
+static size_t pts_bytes(const ift_problem* pr) {
+  if (pr->pde == IFT_BURGERS2D)
+    return pr->p == 1 ? sizeof(Pts<Disc<PDE_BURGERS, 1>, double>) : sizeof(Pts<Disc<PDE_BURGERS, 2>, double>);
+  return pr->p == 1 ? sizeof(Pts<Disc<PDE_EULER, 1>, double>) : sizeof(Pts<Disc<PDE_EULER, 2>, double>);
+}
+
+// Calls f.template run<Disc<...>>() for the problem's discretisation.
+template <class F>
+static void with_disc(const ift_problem* pr, F&& f) {
+  if (pr->pde == IFT_BURGERS2D) {
+    if (pr->p == 1) f.template run<Disc<PDE_BURGERS, 1>>();
+    else f.template run<Disc<PDE_BURGERS, 2>>();
+  } else {
+    if (pr->p == 1) f.template run<Disc<PDE_EULER, 1>>();
+    else f.template run<Disc<PDE_EULER, 2>>();
+  }
+}
+
 // ------------------------------------------------------------------- problem
 extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem** out) {
   if (!d || !out) return IFT_EINVAL;
@@ -383,6 +414,10 @@ extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem*
     ift_problem_destroy(pr);
     return st;
   }
+  if (hipMalloc(&pr->d_pts, (size_t)Ne * pts_bytes(pr)) != hipSuccess) {
+    ift_problem_destroy(pr);
+    return IFT_ENOMEM;
+  }
   if (hipMemcpy(pr->d_gn, pr->h_gn.data(), pr->h_gn.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(pr->d_face, pr->h_face.data(), pr->h_face.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(pr->d_Pn, pn32.data(), pn32.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
@@ -401,6 +436,7 @@ extern "C" void ift_problem_destroy(ift_problem* pr) {
   dfree(pr->d_Pn);
   dfree(pr->d_X);
   dfree(pr->d_flags);
+  if (pr->d_pts) (void)hipFree(pr->d_pts);
   delete pr;
 }
 
@@ -416,21 +452,25 @@ extern "C" ift_status ift_problem_sizes(const ift_problem* pr, int* nue, int* nu
 }
 
 // --------------------------------------------------------------- dispatch
-template <class D, class R>
-static ift_status launch_hdm(const HdmArgs& a, bool jac, hipStream_t st) {
-  if (jac)
-    hipLaunchKernelGGL((k_hdm<D, R, true>), dim3(a.n_elem), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_hdm<D, R, false>), dim3(a.n_elem), dim3(64), 0, st, a);
-  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
-}
-
-template <class R>
-static ift_status dispatch_hdm(const ift_problem* pr, const HdmArgs& a, bool jac, hipStream_t st) {
-  if (pr->pde == IFT_BURGERS2D)
-    return pr->p == 1 ? launch_hdm<Disc<PDE_BURGERS, 1>, R>(a, jac, st) : launch_hdm<Disc<PDE_BURGERS, 2>, R>(a, jac, st);
-  return pr->p == 1 ? launch_hdm<Disc<PDE_EULER, 1>, R>(a, jac, st) : launch_hdm<Disc<PDE_EULER, 2>, R>(a, jac, st);
-}
+struct HdmLaunch {
+  const HdmArgs& a;
+  bool jac;
+  hipStream_t st;
+  template <class D>
+  void run() {
+    if (jac) {
+      {
+        ProfScope ps(IFT_PROF_POINTS, st);
+        hipLaunchKernelGGL((k_points_hdm<D, double>), dim3(a.n_elem), dim3(NTHR_PTS), 0, st, a);
+      }
+      ProfScope ps(IFT_PROF_HDM, st);
+      hipLaunchKernelGGL((k_hdm_asm<D, double>), dim3(a.n_elem), dim3(NTHR), 0, st, a);
+    } else {
+      ProfScope ps(IFT_PROF_HDM, st);
+      hipLaunchKernelGGL((k_hdm_val<D, double>), dim3(a.n_elem), dim3(NTHR), 0, st, a);
+    }
+  }
+};
 
 extern "C" ift_status hdm_assemble(ift_problem* pr, const double* mu, const double* U, const double* x, double* R,
                                    double* N, double* dRdU, double* dRdUn, double* dRdx, double* dNdx, int* n_bad,
@@ -450,19 +490,18 @@ extern "C" ift_status hdm_assemble(ift_problem* pr, const double* mu, const doub
   a.dRdx = dRdx;
   a.dNdx = dNdx;
   a.flags = pr->d_flags;
+  a.pts = pr->d_pts;
   a.pc = phys_const(pr, mu);
   a.kappa = pr->kappa;
   a.eps = pr->eps_g;
   a.n_elem = pr->n_elem;
   const bool jac = dRdU || dRdUn || dRdx || dNdx;
   ift_status s;
-  {
-    ProfScope ps(IFT_PROF_HDM, stream);
-    s = dispatch_hdm<double>(pr, a, jac, stream);
-  }
+  with_disc(pr, HdmLaunch{a, jac, stream});
+  s = hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
   if (s != IFT_OK) return s;
   if (n_bad) {
-    hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, stream, (const double*)nullptr, (const int*)pr->d_flags,
+    hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(256), 0, stream, (const double*)nullptr, (const int*)pr->d_flags,
                        pr->n_elem, (double*)nullptr, n_bad, (int*)nullptr);
     if (hipGetLastError() != hipSuccess) return IFT_EDEVICE;
   }
@@ -495,7 +534,55 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   dfree(r->d_tt);
   dfree(r->d_nbad);
   dfree(r->d_flag_or);
+  if (r->d_pts) (void)hipFree(r->d_pts);
   delete r;
+}
+
+// (Re)allocates every workspace that scales with the number of evaluation
+// points of one call.
+static ift_status reserve_points(ift_rom* r, int max_pts) {
+  if (max_pts <= r->max_pts) return IFT_OK;
+  const ift_problem* pr = r->prob;
+  const size_t P = (size_t)max_pts, ns = (size_t)r->n_s, D = (size_t)r->D;
+  dfree(r->d_Jt);
+  dfree(r->d_Ft);
+  dfree(r->d_Jpart);
+  dfree(r->d_flags);
+  dfree(r->d_PTR);
+  dfree(r->d_gram_part);
+  if (r->d_pts) (void)hipFree(r->d_pts);
+  r->d_pts = nullptr;
+  dfree(r->d_H);
+  dfree(r->d_g);
+  dfree(r->d_J);
+  dfree(r->d_Jtrial);
+  dfree(r->d_dz);
+  dfree(r->d_solve_out);
+  dfree(r->d_wt);
+  dfree(r->d_tt);
+  dfree(r->d_nbad);
+  dfree(r->d_flag_or);
+  r->max_pts = 0;
+  ift_status st;
+  if ((st = dalloc(&r->d_Jt, P * r->nrows * D)) != IFT_OK || (st = dalloc(&r->d_Ft, P * r->nrows)) != IFT_OK ||
+      (st = dalloc(&r->d_Jpart, P * ns)) != IFT_OK || (st = dalloc(&r->d_flags, P * ns)) != IFT_OK ||
+      (st = dalloc(&r->d_PTR, P * ns * r->n)) != IFT_OK ||
+      (st = dalloc(&r->d_gram_part, P * r->n_gram_blk * (D * D + D))) != IFT_OK ||
+      (st = dalloc(&r->d_H, P * D * D)) != IFT_OK || (st = dalloc(&r->d_g, P * D)) != IFT_OK ||
+      (st = dalloc(&r->d_J, P)) != IFT_OK || (st = dalloc(&r->d_Jtrial, P)) != IFT_OK ||
+      (st = dalloc(&r->d_dz, P * D)) != IFT_OK || (st = dalloc(&r->d_solve_out, P * 8)) != IFT_OK ||
+      (st = dalloc(&r->d_wt, P * r->n)) != IFT_OK || (st = dalloc(&r->d_tt, P * std::max(r->m, 1))) != IFT_OK ||
+      (st = dalloc(&r->d_nbad, P)) != IFT_OK || (st = dalloc(&r->d_flag_or, P)) != IFT_OK)
+    return st;
+  if (hipMalloc(&r->d_pts, P * ns * pts_bytes(pr)) != hipSuccess) return IFT_ENOMEM;
+  r->max_pts = max_pts;
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_rom_reserve(ift_rom* r, int max_pts) {
+  if (!r || max_pts < 1) return IFT_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return IFT_EDEVICE;
+  return reserve_points(r, max_pts);
 }
 
 extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double* Phi, const double* Psi, int n_s,
@@ -518,8 +605,11 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   r->precision = precision;
   const int nue = pr->nue, nun = pr->nun, nxe = pr->nxe, nn = pr->nn;
   r->nrows = (long long)n_s * nue + n_s;
-  r->n_gram_blk = (int)((r->nrows + GRAM_ROWS - 1) / GRAM_ROWS);
-  const int npair = r->D * (r->D + 1) / 2;
+  // Gram row blocks: about one per compute unit, at most GRAM_MAXROWS rows each
+  const int Dp = (r->D + 3) & ~3;
+  const long long cap = std::min<long long>(GRAM_MAXROWS, 6144 / (Dp + 1));   // row buffer <= 48 KB
+  r->gram_rows_per = (int)std::min<long long>(cap, std::max<long long>(4, (r->nrows + 255) / 256));
+  r->n_gram_blk = (int)((r->nrows + r->gram_rows_per - 1) / r->gram_rows_per);
   std::vector<long long> rows_u((size_t)n_s * nue), rows_n((size_t)n_s * nun), rows_x((size_t)n_s * nxe);
   std::vector<double> hXs((size_t)n_s * nxe), hsr(n_s);
   for (int k = 0; k < n_s; ++k) {
@@ -550,23 +640,12 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   ALLOC(r->d_Phin_s, (size_t)n_s * nun * n);
   ALLOC(r->d_Psi_s, (size_t)n_s * nxe * std::max(m, 1));
   ALLOC(r->d_X_s, (size_t)n_s * nxe);
-  ALLOC(r->d_Jt, (size_t)r->nrows * r->D);
-  ALLOC(r->d_Ft, (size_t)r->nrows);
-  ALLOC(r->d_Jpart, n_s);
-  ALLOC(r->d_flags, n_s);
-  ALLOC(r->d_PTR, (size_t)n_s * n);
-  ALLOC(r->d_gram_part, (size_t)r->n_gram_blk * (npair + r->D));
-  ALLOC(r->d_H, (size_t)r->D * r->D);
-  ALLOC(r->d_g, r->D);
-  ALLOC(r->d_J, 1);
-  ALLOC(r->d_Jtrial, 1);
-  ALLOC(r->d_dz, r->D);
-  ALLOC(r->d_solve_out, 8);
-  ALLOC(r->d_wt, n);
-  ALLOC(r->d_tt, std::max(m, 1));
-  ALLOC(r->d_nbad, 1);
-  ALLOC(r->d_flag_or, 1);
 #undef ALLOC
+  if ((st = reserve_points(r, 1)) != IFT_OK) {
+    dfree(d_rows);
+    ift_rom_destroy(r);
+    return st;
+  }
   bool ok = hipMemcpy(r->d_eq, eq_elem, n_s * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(r->d_rho, eq_rho, n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(r->d_srho, hsr.data(), n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
@@ -611,6 +690,8 @@ static EqArgs eq_args(ift_rom* r, const double* mu, const double* w, const doubl
   a.n = r->n;
   a.m = r->m;
   a.D = r->D;
+  a.nrows = r->nrows;
+  a.mu = nullptr;
   a.eq_elem = r->d_eq;
   a.face = pr->d_face;
   a.rho = r->d_rho;
@@ -626,35 +707,40 @@ static EqArgs eq_args(ift_rom* r, const double* mu, const double* w, const doubl
   a.Jpart = r->d_Jpart;
   a.flags = r->d_flags;
   a.PTR = nullptr;
+  a.pts = r->d_pts;
   a.pc = phys_const(pr, mu);
   a.kappa = pr->kappa;
   a.eps = pr->eps_g;
+  a.bc_mu_scale = pr->bc_mu_scale;
   return a;
 }
 
-template <class D, class R>
-static void launch_eq(const EqArgs& a, bool jac, hipStream_t st) {
-  if (jac)
-    hipLaunchKernelGGL((k_eq_jac<D, R>), dim3(a.n_s), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_eq_res<D, R>), dim3(a.n_s), dim3(64), 0, st, a);
-}
-
 template <class R>
-static void dispatch_eq_r(const ift_problem* pr, const EqArgs& a, bool jac, hipStream_t st) {
-  if (pr->pde == IFT_BURGERS2D) {
-    if (pr->p == 1) launch_eq<Disc<PDE_BURGERS, 1>, R>(a, jac, st);
-    else launch_eq<Disc<PDE_BURGERS, 2>, R>(a, jac, st);
-  } else {
-    if (pr->p == 1) launch_eq<Disc<PDE_EULER, 1>, R>(a, jac, st);
-    else launch_eq<Disc<PDE_EULER, 2>, R>(a, jac, st);
+struct EqLaunch {
+  const EqArgs& a;
+  bool jac;
+  int n_pts;
+  hipStream_t st;
+  template <class D>
+  void run() {
+    if (jac) {
+      {
+        ProfScope ps(IFT_PROF_POINTS, st);
+        hipLaunchKernelGGL((k_points_eq<D, R>), dim3(a.n_s, n_pts), dim3(NTHR_PTS), 0, st, a);
+      }
+      const size_t shm = sizeof(double) * ((size_t)(D::NUE + D::NUN) * a.n + (size_t)D::NXE * a.m);
+      ProfScope ps(IFT_PROF_EQ_JAC, st);
+      hipLaunchKernelGGL((k_eq_asm<D, R>), dim3(a.n_s, n_pts), dim3(NTHR), shm, st, a);
+    } else {
+      ProfScope ps(IFT_PROF_EQ_RES, st);
+      hipLaunchKernelGGL((k_eq_res<D, R>), dim3(a.n_s, n_pts), dim3(NTHR), 0, st, a);
+    }
   }
-}
+};
 
-static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, hipStream_t st) {
-  ProfScope ps(jac ? IFT_PROF_EQ_JAC : IFT_PROF_EQ_RES, st);
-  if (r->precision == IFT_FP32_ELEM) dispatch_eq_r<float>(r->prob, a, jac, st);
-  else dispatch_eq_r<double>(r->prob, a, jac, st);
+static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, int n_pts, hipStream_t st) {
+  if (r->precision == IFT_FP32_ELEM) with_disc(r->prob, EqLaunch<float>{a, jac, n_pts, st});
+  else with_disc(r->prob, EqLaunch<double>{a, jac, n_pts, st});
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }
 
@@ -665,9 +751,9 @@ extern "C" ift_status eq_assemble_residual(ift_rom* r, const double* mu, const d
   EqArgs a = eq_args(r, mu, w, tau);
   a.Ft = Ft;
   a.PTR = PhiT_r ? r->d_PTR : nullptr;
-  ift_status s = dispatch_eq(r, a, false, stream);
+  ift_status s = dispatch_eq(r, a, false, 1, stream);
   if (s != IFT_OK) return s;
-  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, stream, (const double*)r->d_Jpart, (const int*)r->d_flags,
+  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(256), 0, stream, (const double*)r->d_Jpart, (const int*)r->d_flags,
                      r->n_s, Jobj, n_bad, r->d_flag_or);
   if (PhiT_r)
     hipLaunchKernelGGL(k_sum_rows, dim3((r->n + 63) / 64), dim3(64), 0, stream, (const double*)r->d_PTR, r->n_s,
@@ -675,15 +761,28 @@ extern "C" ift_status eq_assemble_residual(ift_rom* r, const double* mu, const d
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }
 
-static ift_status gram(ift_rom* r, double* H, double* g, hipStream_t stream) {
+static ift_status gram(ift_rom* r, int n_pts, double* H, double* g, double* Jobj, int* n_bad, hipStream_t stream) {
   const int D = r->D;
-  const size_t shm = (size_t)(GRAM_TILE * D + GRAM_TILE) * sizeof(double);
+  GramArgs ga;
+  ga.Jt = r->d_Jt;
+  ga.Ft = r->d_Ft;
+  ga.Jpart = r->d_Jpart;
+  ga.flags = r->d_flags;
+  ga.nrows = r->nrows;
+  ga.n_s = r->n_s;
+  ga.D = D;
+  ga.nblk = r->n_gram_blk;
+  ga.rows_per = r->gram_rows_per;
+  ga.part = r->d_gram_part;
+  ga.H = H;
+  ga.g = g;
+  ga.Jobj = Jobj ? Jobj : r->d_J;
+  ga.n_bad = n_bad;
+  ga.flag_or = r->d_flag_or;
   ProfScope ps(IFT_PROF_GRAM, stream);
-  hipLaunchKernelGGL(k_gram_partial, dim3(r->n_gram_blk), dim3(256), shm, stream, (const double*)r->d_Jt,
-                     (const double*)r->d_Ft, r->nrows, D, r->d_gram_part);
-  const int nent = D * (D + 1) / 2 + D;
-  hipLaunchKernelGGL(k_gram_final, dim3((nent + 255) / 256), dim3(256), 0, stream, (const double*)r->d_gram_part,
-                     r->n_gram_blk, D, H, g);
+  hipLaunchKernelGGL(k_gram_part, dim3(ga.nblk, n_pts), dim3(256), gram_shm_bytes(D, ga.rows_per), stream, ga);
+  const int nbe = (D * D + D + GF_ENT - 1) / GF_ENT;
+  hipLaunchKernelGGL(k_gram_final, dim3(nbe + 1, n_pts), dim3(256), 0, stream, ga);
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }
 
@@ -692,14 +791,39 @@ extern "C" ift_status eq_assemble_jacobian(ift_rom* r, const double* mu, const d
                                            hipStream_t stream) {
   if (!r || !w || (r->m > 0 && !tau) || !finite_mu(r->prob, mu)) return IFT_EINVAL;
   EqArgs a = eq_args(r, mu, w, tau);
-  ift_status s = dispatch_eq(r, a, true, stream);
+  ift_status s = dispatch_eq(r, a, true, 1, stream);
   if (s != IFT_OK) return s;
-  hipLaunchKernelGGL(k_obj_final, dim3(1), dim3(64), 0, stream, (const double*)r->d_Jpart, (const int*)r->d_flags,
-                     r->n_s, Jobj, n_bad, r->d_flag_or);
-  s = gram(r, H ? H : r->d_H, g ? g : r->d_g, stream);
+  s = gram(r, 1, H ? H : r->d_H, g ? g : r->d_g, Jobj, n_bad, stream);
   if (s != IFT_OK) return s;
   if (Jt) HIP_TRY(hipMemcpyAsync(Jt, r->d_Jt, (size_t)r->nrows * r->D * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return IFT_OK;
+}
+
+extern "C" ift_status eq_assemble_residual_batch(ift_rom* r, int n_pts, const double* mu, const double* w,
+                                                 const double* tau, double* Jobj, int* n_bad, hipStream_t stream) {
+  if (!r || n_pts < 1 || n_pts > r->max_pts || !mu || !w || (r->m > 0 && !tau) || !Jobj) return IFT_EINVAL;
+  double mu0[2] = {1.0, 0.0};
+  EqArgs a = eq_args(r, mu0, w, tau);
+  a.mu = mu;
+  a.Ft = nullptr;
+  ift_status s = dispatch_eq(r, a, false, n_pts, stream);
+  if (s != IFT_OK) return s;
+  hipLaunchKernelGGL(k_obj_final, dim3(n_pts), dim3(256), 0, stream, (const double*)r->d_Jpart, (const int*)r->d_flags,
+                     r->n_s, Jobj, n_bad, r->d_flag_or);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+extern "C" ift_status eq_assemble_jacobian_batch(ift_rom* r, int n_pts, const double* mu, const double* w,
+                                                 const double* tau, double* Jobj, double* g, double* H, int* n_bad,
+                                                 hipStream_t stream) {
+  if (!r || n_pts < 1 || n_pts > r->max_pts || !mu || !w || (r->m > 0 && !tau) || !Jobj || !g || !H)
+    return IFT_EINVAL;
+  double mu0[2] = {1.0, 0.0};
+  EqArgs a = eq_args(r, mu0, w, tau);
+  a.mu = mu;
+  ift_status s = dispatch_eq(r, a, true, n_pts, stream);
+  if (s != IFT_OK) return s;
+  return gram(r, n_pts, H, g, Jobj, n_bad, stream);
 }
 
 extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double* w, double* tau,

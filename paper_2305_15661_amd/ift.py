@@ -68,11 +68,14 @@ EXPORTS = {
     "eq_assemble_residual": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P]),
     "eq_assemble_jacobian": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P]),
     "rom_gauss_newton_step": (ctypes.c_int, [_P, _D, _P, _P, ctypes.POINTER(GNParams), ctypes.POINTER(GNInfo), _P]),
+    "ift_rom_reserve": (ctypes.c_int, [_P, ctypes.c_int]),
+    "eq_assemble_residual_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "eq_assemble_jacobian_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
     "ift_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "ift_profile_reset": (ctypes.c_int, []),
     "ift_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
 }
-PROF = {"hdm": 0, "eq_res": 1, "eq_jac": 2, "gram": 3}
+PROF = {"hdm": 0, "eq_res": 1, "eq_jac": 2, "gram": 3, "points": 4}
 
 _lib = None
 
@@ -220,6 +223,30 @@ class ROM:
                                         _ptr(Jt, self.nrows * self.D, f64), _ptr(n_bad, 1, torch.int32),
                                         _stream(stream))
         _check(st, "eq_assemble_jacobian")
+
+    def reserve(self, max_pts: int):
+        _check(lib().ift_rom_reserve(self.handle, int(max_pts)), "ift_rom_reserve")
+
+    def eq_assemble_residual_batch(self, mu, w, tau, Jobj, n_bad=None, stream=None):
+        """mu [P,2], w [P,n], tau [P,m] device tensors; Jobj [P]."""
+        import torch
+        f64 = torch.float64
+        P = int(w.shape[0])
+        st = lib().eq_assemble_residual_batch(self.handle, P, _ptr(mu, 2 * P, f64), _ptr(w, P * self.n, f64),
+                                              _ptr(tau, P * self.m, f64), _ptr(Jobj, P, f64),
+                                              _ptr(n_bad, P, torch.int32), _stream(stream))
+        _check(st, "eq_assemble_residual_batch")
+
+    def eq_assemble_jacobian_batch(self, mu, w, tau, Jobj, g, H, n_bad=None, stream=None):
+        """mu [P,2], w [P,n], tau [P,m]; Jobj [P], g [P,D], H [P,D,D] device tensors."""
+        import torch
+        f64 = torch.float64
+        P = int(w.shape[0])
+        st = lib().eq_assemble_jacobian_batch(self.handle, P, _ptr(mu, 2 * P, f64), _ptr(w, P * self.n, f64),
+                                              _ptr(tau, P * self.m, f64), _ptr(Jobj, P, f64),
+                                              _ptr(g, P * self.D, f64), _ptr(H, P * self.D * self.D, f64),
+                                              _ptr(n_bad, P, torch.int32), _stream(stream))
+        _check(st, "eq_assemble_jacobian_batch")
 
     def gauss_newton_step(self, mu, w, tau, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, stream=None):
         """rom_gauss_newton_step; returns (status, info dict).  Soft outcomes

@@ -106,7 +106,13 @@ def test_hdm_residual_only_matches_jacobian_path(euler_case):
     x = wl.X + wl.Psi @ wl.tau_eval[3]
     a = _hdm_gpu(euler_case, wl.mus[3], U, x, jac=False)
     b = _hdm_gpu(euler_case, wl.mus[3], U, x, jac=True)
-    assert np.array_equal(a["R"], b["R"]) and np.array_equal(a["N"], b["N"])
+    # the Jacobian path evaluates the point values in tangent arithmetic,
+    # which the compiler may contract differently: equal to rounding.  N_e is
+    # a difference of two integrals of size ~4|Omega_e| kappa, so its
+    # rounding error scales with that size, not with N_e.
+    assert rel(a["R"], b["R"]) < 1e-14
+    eta_scale = wl.kappa * 4.0 * (2.0 / wl.mesh.n_elem)
+    assert np.abs(a["N"] - b["N"]).max() < 1e-14 * eta_scale
 
 
 @pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
@@ -182,6 +188,36 @@ def test_single_element_and_boundary_only_eq_sets(dev):
         g = _eq_gpu(case, mu, w, tau)
         oj = case.orom.jacobian(mu, w, tau)
         assert rel(g["g"], oj["g"]) < 1e-12 and rel(g["H"], oj["H"]) < 1e-12
+
+
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+def test_batched_points_match_single_calls_and_oracle(which, request):
+    """All 16 seeded evaluation points in one batched launch (device mu)."""
+    import torch
+    case = request.getfixturevalue(which)
+    wl, r, d = case.wl, case.rom, case.dev
+    P = wl.mus.shape[0]
+    _say(f"batched eq assembly {wl.name} x{P}")
+    r.reserve(P)
+    mu2 = np.zeros((P, 2))
+    mu2[:, :wl.mus.shape[1]] = wl.mus
+    MU, W, T = _t(mu2, d), _t(wl.w_eval, d), _t(wl.tau_eval, d)
+    J, G, H = _z(P, d), _z(P * r.D, d), _z(P * r.D * r.D, d)
+    nb = _z(P, d, torch.int32)
+    r.eq_assemble_jacobian_batch(MU, W, T, J, G, H, nb)
+    Jr = _z(P, d)
+    r.eq_assemble_residual_batch(MU, W, T, Jr)
+    torch.cuda.synchronize()
+    J, G, H, Jr = J.cpu().numpy(), G.cpu().numpy().reshape(P, r.D), H.cpu().numpy().reshape(P, r.D, r.D), Jr.cpu().numpy()
+    for k in (0, 5, P - 1):
+        single = _eq_gpu(case, wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
+        oj = case.orom.jacobian(wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
+        assert rel(G[k], single["g"]) < 1e-14 and rel(H[k], single["H"]) < 1e-14
+        assert rel(G[k], oj["g"]) < 1e-12 and rel(H[k], oj["H"]) < 1e-12
+        assert abs(J[k] - oj["J"]) <= 1e-12 * oj["J"] and abs(Jr[k] - oj["J"]) <= 1e-12 * oj["J"]
+    nb_o = [case.orom.residual(wl.mus[k], wl.w_eval[k], wl.tau_eval[k])["n_bad"] for k in range(P)]
+    assert list(nb.cpu().numpy()) == nb_o
+    assert all(np.isinf(J[k]) == (nb_o[k] > 0) for k in range(P))
 
 
 def test_gauss_newton_steps_parity(tiny_case):
