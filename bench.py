@@ -40,23 +40,31 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 
 # Algorithmic work per sampled element-eval at nue = 24, nun = 36, nxe = 12,
-# n = 20, m = 10 (FP64), per kernel of the Jacobian path:
-#  points  (point physics): reads the gathered operands it lifts
-#          (Phi_e 24x20, Phi_e' 36x20, Psi_e 12x10, X_e 12 doubles);
-#  eq_jac  (assembly + projection): reads Phi_e, Phi_e', Psi_e and writes
-#          the 25 Jacobian rows (25 x 30) and residual rows (25); its dense
-#          contraction A_e = J^U Phi_e + J^U' Phi_e' (2*24*60*20 flops) and
-#          B_e = J^x Psi_e (2*24*12*10), distortion row (2*12*10);
-#  gram    reads the rows (25 x 31 doubles) and forms J~^T J~ and J~^T F~
-#          (2*25*30*30 + 2*25*30 flops).
-KBYTES = {"points": 8 * (24 * 20 + 36 * 20 + 12 * 10 + 12),
-          "eq_jac": 8 * (24 * 20 + 36 * 20 + 12 * 10) + 8 * (25 * 30 + 25),
+# n = 20, m = 10 (FP64), split over the kernels of the Jacobian path:
+#  points (lift, geometry, DG volume/face terms, distortion with exact point
+#          Jacobians): reads the gathered EQ operands Phi_e 24x20,
+#          Phi_e' 36x20, Psi_e 12x10, X_e 12 and rho/ids (10,680 B);
+#  eq_jac (projection and weighting, fused with the Gram reduction): the
+#          contraction A^U = J^U Phi_e + J^U' Phi_e' (2*24*60*20 = 57,600),
+#          A^x = J^x Psi_e (2*24*12*10 = 5,760), H += A^T A (2*25*30*30 =
+#          45,000 with the distortion row; 43,200 without it) and g
+#          (2*25*30 = 1,500): 108,000 counted as in the path table;
+#  gram   (sum of the per-block partials): bytes of the partials read.
+KBYTES = {"points": 8 * (24 * 20 + 36 * 20 + 12 * 10 + 12) + 24,
+          "eq_jac": 8 * (24 * 20 + 36 * 20 + 12 * 10),
           "gram": 8 * 25 * 31}
 KFLOPS = {"points": None,
-          "eq_jac": 2 * 24 * 60 * 20 + 2 * 24 * 12 * 10 + 2 * 12 * 10,
-          "gram": 2 * 25 * 30 * 30 + 2 * 25 * 30}
-KNAMES = {"points": "k_points_eq<Euler P2, fp64>", "eq_jac": "k_eq_asm<Euler P2, fp64>",
-          "gram": "k_gram_part + k_gram_final"}
+          "eq_jac": 57600 + 5760 + 43200 + 1440,
+          "gram": None}
+KNAMES = {"points": "k_points_eq<Euler P2, fp64>", "eq_jac": "k_eq_fused<Euler P2, fp64, 2>",
+          "gram": "k_fused_final"}
+# HBM traffic per launch of each kernel from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch) on this workload, scaled by what the same
+# counters read for a plain copy kernel of known size (a 512 MiB copy reads
+# back as 256 MiB fetched and 512 MiB written).  An entry is None until the
+# counters have been taken on the kernel as it now stands.
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+TRAFFIC_KIB = {"points": None, "eq_jac": None, "gram": None}
 # Full-order loop with Jacobians: reads U_e, the neighbour traces, x_e, X_e
 # and connectivity; writes R_e, N_e, dR/dU_e, dR/dU_e', dR/dx_e, dN/dx_e.
 HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)
@@ -173,13 +181,15 @@ def main():
     dom = max(avg, key=avg.get)
     t_dom = avg[dom]
     gbs = KBYTES[dom] * evals_per_step / t_dom / 1e9
-    if dom == "points" or gbs / PEAK_HBM_GBS >= (KFLOPS[dom] or 0) * evals_per_step / t_dom / 1e12 / PEAK_FP64_TFLOPS:
+    if KFLOPS[dom] is None:
         roofline = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
     else:
         tf = KFLOPS[dom] * evals_per_step / t_dom / 1e12
-        roofline = {"bound": "mfma" if dom == "eq_jac" else "alu", "achieved": tf, "peak": PEAK_FP64_TFLOPS,
-                    "unit": "TFLOP/s", "frac": tf / PEAK_FP64_TFLOPS}
-    roofline.update({"traffic": None, "kernel": KNAMES[dom], "launch_avg_us": t_dom * 1e6,
+        roofline = {"bound": "mfma", "achieved": tf, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tf / PEAK_FP64_TFLOPS}
+    tr = TRAFFIC_KIB.get(dom)
+    traffic = None if tr is None else FETCH_SCALE * tr[0] * 1024 + WRITE_SCALE * tr[1] * 1024
+    roofline.update({"traffic": traffic, "kernel": KNAMES[dom], "launch_avg_us": t_dom * 1e6,
                      "algorithmic_bytes_per_launch": KBYTES[dom] * evals_per_step,
                      "algorithmic_flops_per_launch": (KFLOPS[dom] or 0) * evals_per_step,
                      "kernels_us": {k: v * 1e6 for k, v in avg.items()}})
@@ -193,7 +203,6 @@ def main():
 
     # ------------------------------------------------------------- solves/s
     if not args.no_solve:
-        from oracle import eq as oeq  # noqa: F401  (only for the start points' shape check)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         conv, iters = 0, []

@@ -32,6 +32,7 @@ struct RefTab {
   double dL[3][3];       // its s-derivative          [q][k]
   int en[3][3];          // element node of edge node k of face f [f][k]
   int nfk[6][3];         // edge-node index of node i on face f, or -1
+  double wl[6][3][3];    // wf[q] * L[q][nfk[i][f]], 0 where node i is not on face f  [i][f][q]
 };
 
 extern __constant__ RefTab c_tab[2];
@@ -294,13 +295,14 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
     constexpr int ntask = n_point_tasks<D, true>();
     if (tid < ntask) {
       const int k = tid;
-      if (k < nvol) {
-        vol_point<D, TT, R>(s, k / D::NC, k % D::NC, pc, eps);
-      } else if (k < nvol + nface) {
-        int r = k - nvol;
-        int dir = r % (2 * D::NC + 2);
-        int pt = r / (2 * D::NC + 2);
+      // face tasks first so that whole waves run the (heavier) face path
+      if (k < nface) {
+        int dir = k % (2 * D::NC + 2);
+        int pt = k / (2 * D::NC + 2);
         face_point<D, TT, R>(s, pt / D::NQF, pt % D::NQF, dir, pc);
+      } else if (k < nface + nvol) {
+        const int r = k - nface;
+        vol_point<D, TT, R>(s, r / D::NC, r % D::NC, pc, eps);
       } else {
         int j = k - nvol - nface;
         TT eta = eta_elem<D, R>(s.tab, s.x, s.X, eps, j);
@@ -313,20 +315,24 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
 
 // ----------------------------------------------------------------- phase C
 template <class D, class R>
-IFT_DEV R residual_entry(const ElemLDS<D, R>& s, int r) {
-  const RefTab& t = s.tab;
+IFT_DEV R residual_entry_p(const Pts<D, R>& p, const RefTab& t, int r) {
   const int i = r / D::NC, c = r % D::NC;
   R v = R(0);
 #pragma unroll
-  for (int q = 0; q < D::NQV; ++q) v -= R(t.wv[q]) * (s.p.fv[q][c][0] * s.p.gp[q][i][0] + s.p.fv[q][c][1] * s.p.gp[q][i][1]);
+  for (int q = 0; q < D::NQV; ++q) v -= R(t.wv[q]) * (p.fv[q][c][0] * p.gp[q][i][0] + p.fv[q][c][1] * p.gp[q][i][1]);
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const int k = t.nfk[i][f];
     if (k < 0) continue;
 #pragma unroll
-    for (int q = 0; q < D::NQF; ++q) v += R(t.wf[q] * t.L[q][k]) * s.p.H[f][q][c];
+    for (int q = 0; q < D::NQF; ++q) v += R(t.wf[q] * t.L[q][k]) * p.H[f][q][c];
   }
   return v;
+}
+
+template <class D, class R>
+IFT_DEV R residual_entry(const ElemLDS<D, R>& s, int r) {
+  return residual_entry_p<D, R>(s.p, s.tab, r);
 }
 
 // Entry (r, col) of [dR/dU_e | dR/dU_e' | dR/dx_e] from the point Jacobians.

@@ -52,6 +52,8 @@ struct ift_rom {
   double* d_Phin_s = nullptr;
   double* d_Psi_s = nullptr;
   double* d_X_s = nullptr;
+  double* d_Bw = nullptr;   // reduced state basis at the quadrature points [n_s][KWP][n]
+  double* d_Bx = nullptr;   // mapping-basis geometry derivatives [n_s][KXP][m]
   // workspaces
   long long nrows = 0;
   int n_gram_blk = 0;
@@ -64,6 +66,9 @@ struct ift_rom {
   double* d_PTR = nullptr;
   double* d_gram_part = nullptr;
   void* d_pts = nullptr;
+  int fused_nt = 0;             // column tiles of the fused assembly + Gram (0: two-kernel path)
+  double* d_fpart = nullptr;    // fused block partials
+  int* d_fbad = nullptr;
   // Gauss-Newton state
   double* d_H = nullptr;
   double* d_g = nullptr;
@@ -249,6 +254,7 @@ static void build_tables(int p, RefTab& t) {
       if (i < nn)
         for (int k = 0; k <= p; ++k)
           if (t.en[f][k] == i) t.nfk[i][f] = k;
+      for (int q = 0; q <= p; ++q) t.wl[i][f][q] = t.nfk[i][f] >= 0 ? t.wf[q] * t.L[q][t.nfk[i][f]] : 0.0;
     }
 }
 
@@ -524,6 +530,8 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   dfree(r->d_flags);
   dfree(r->d_PTR);
   dfree(r->d_gram_part);
+  dfree(r->d_fpart);
+  dfree(r->d_fbad);
   dfree(r->d_H);
   dfree(r->d_g);
   dfree(r->d_J);
@@ -535,7 +543,51 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   dfree(r->d_nbad);
   dfree(r->d_flag_or);
   if (r->d_pts) (void)hipFree(r->d_pts);
+  dfree(r->d_Bw);
+  dfree(r->d_Bx);
   delete r;
+}
+
+// Reduced bases at the quadrature points of every sampled element (they
+// depend only on the ROM): allocated and computed once at creation.
+struct PointBases {
+  ift_rom* r;
+  bool ok;
+  template <class D>
+  void run() {
+    using O = EqOp<D>;
+    if (dalloc(&r->d_Bw, (size_t)r->n_s * O::KWP * (r->n + 1)) != IFT_OK ||
+        dalloc(&r->d_Bx, (size_t)r->n_s * O::KXP * (r->m + 1)) != IFT_OK) {
+      ok = false;
+      return;
+    }
+    hipLaunchKernelGGL((k_point_bases<D>), dim3(r->n_s), dim3(256), 0, 0, (const double*)r->d_Phi_s,
+                       (const double*)r->d_Phin_s, (const double*)r->d_Psi_s, r->n, r->m, r->d_Bw, r->d_Bx);
+    ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  }
+};
+
+static bool build_point_bases(ift_rom* r) {
+  PointBases pb{r, true};
+  with_disc(r->prob, pb);
+  return pb.ok;
+}
+
+// Work split of the fused assembly for n_pts points: E sampled elements per
+// wave, nblk blocks of four waves per point.  About four waves per SIMD in
+// total; nblk is a multiple of 8 so that the blocks of every point that
+// cover the same elements run on the same XCD and share its L2.
+struct FusedLayout {
+  int E, nblk;
+};
+static constexpr long long FUSED_TARGET_WAVES = 4096;
+static FusedLayout fused_layout(const ift_rom* r, int n_pts) {
+  const long long ns = r->n_s;
+  int E = (int)std::max<long long>(1, (ns * n_pts + FUSED_TARGET_WAVES - 1) / FUSED_TARGET_WAVES);
+  int nblk = (int)((ns + 4LL * E - 1) / (4LL * E));
+  if (nblk > 8) nblk = (nblk + 7) / 8 * 8;
+  E = (int)((ns + 4LL * nblk - 1) / (4LL * nblk));
+  return {E, nblk};
 }
 
 // (Re)allocates every workspace that scales with the number of evaluation
@@ -550,6 +602,8 @@ static ift_status reserve_points(ift_rom* r, int max_pts) {
   dfree(r->d_flags);
   dfree(r->d_PTR);
   dfree(r->d_gram_part);
+  dfree(r->d_fpart);
+  dfree(r->d_fbad);
   if (r->d_pts) (void)hipFree(r->d_pts);
   r->d_pts = nullptr;
   dfree(r->d_H);
@@ -575,6 +629,12 @@ static ift_status reserve_points(ift_rom* r, int max_pts) {
       (st = dalloc(&r->d_nbad, P)) != IFT_OK || (st = dalloc(&r->d_flag_or, P)) != IFT_OK)
     return st;
   if (hipMalloc(&r->d_pts, P * ns * pts_bytes(pr)) != hipSuccess) return IFT_ENOMEM;
+  if (r->fused_nt > 0) {
+    size_t nb = 0;
+    for (int q = 1; q <= max_pts; ++q) nb = std::max(nb, (size_t)q * fused_layout(r, q).nblk);
+    const size_t nh = (size_t)r->fused_nt * (r->fused_nt + 1) / 2;
+    if ((st = dalloc(&r->d_fpart, nb * nh * 256)) != IFT_OK || (st = dalloc(&r->d_fbad, nb * 2)) != IFT_OK) return st;
+  }
   r->max_pts = max_pts;
   return IFT_OK;
 }
@@ -610,6 +670,7 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   const long long cap = std::min<long long>(GRAM_MAXROWS, 6144 / (Dp + 1));   // row buffer <= 48 KB
   r->gram_rows_per = (int)std::min<long long>(cap, std::max<long long>(4, (r->nrows + 255) / 256));
   r->n_gram_blk = (int)((r->nrows + r->gram_rows_per - 1) / r->gram_rows_per);
+  r->fused_nt = (r->D + 1 + 15) / 16 <= FUSED_MAXNT ? (r->D + 1 + 15) / 16 : 0;
   std::vector<long long> rows_u((size_t)n_s * nue), rows_n((size_t)n_s * nun), rows_x((size_t)n_s * nxe);
   std::vector<double> hXs((size_t)n_s * nxe), hsr(n_s);
   for (int k = 0; k < n_s; ++k) {
@@ -663,6 +724,7 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   gather(Phi, n, rows_n, r->d_Phin_s);
   gather(Psi, m, rows_x, r->d_Psi_s);
   dfree(d_rows);
+  if (ok) ok = build_point_bases(r);
   if (!ok) {
     ift_rom_destroy(r);
     return IFT_EDEVICE;
@@ -715,32 +777,73 @@ static EqArgs eq_args(ift_rom* r, const double* mu, const double* w, const doubl
   return a;
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin in linear order; padding
+// the element axis of an (element, point) grid to a multiple of 8 keeps
+// every point of one element on the same XCD, so its gathered operands are
+// read from that XCD's L2 after the first point.
+static inline int xcd_pad(int n) { return n > 8 ? (n + 7) / 8 * 8 : n; }
+
 template <class R>
 struct EqLaunch {
   const EqArgs& a;
   bool jac;
   int n_pts;
   hipStream_t st;
+  const double* Bw;
+  const double* Bx;
+  const FusedArgs* fa;   // fused assembly + Gram, or null
+  int nt;
+  template <class D, int NT>
+  void fused() {
+    hipLaunchKernelGGL((k_eq_fused<D, R, NT>), dim3(fa->nblk, n_pts), dim3(NTHR), 0, st, a, Bw, Bx, *fa);
+  }
   template <class D>
   void run() {
     if (jac) {
       {
         ProfScope ps(IFT_PROF_POINTS, st);
-        hipLaunchKernelGGL((k_points_eq<D, R>), dim3(a.n_s, n_pts), dim3(NTHR_PTS), 0, st, a);
+        hipLaunchKernelGGL((k_points_eq<D, R>), dim3(xcd_pad(a.n_s), n_pts), dim3(NTHR_PTS), 0, st, a);
       }
-      const size_t shm = sizeof(double) * ((size_t)(D::NUE + D::NUN) * a.n + (size_t)D::NXE * a.m);
       ProfScope ps(IFT_PROF_EQ_JAC, st);
-      hipLaunchKernelGGL((k_eq_asm<D, R>), dim3(a.n_s, n_pts), dim3(NTHR), shm, st, a);
+      if (!fa) hipLaunchKernelGGL((k_eq_asm<D, R>), dim3(a.n_s, n_pts), dim3(NTHR), 0, st, a, Bw, Bx);
+      else if (nt == 1) fused<D, 1>();
+      else if (nt == 2) fused<D, 2>();
+      else fused<D, 3>();
     } else {
       ProfScope ps(IFT_PROF_EQ_RES, st);
-      hipLaunchKernelGGL((k_eq_res<D, R>), dim3(a.n_s, n_pts), dim3(NTHR), 0, st, a);
+      hipLaunchKernelGGL((k_eq_res<D, R>), dim3(xcd_pad(a.n_s), n_pts), dim3(NTHR), 0, st, a);
     }
   }
 };
 
-static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, int n_pts, hipStream_t st) {
-  if (r->precision == IFT_FP32_ELEM) with_disc(r->prob, EqLaunch<float>{a, jac, n_pts, st});
-  else with_disc(r->prob, EqLaunch<double>{a, jac, n_pts, st});
+static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, int n_pts, hipStream_t st,
+                              const FusedArgs* fa = nullptr) {
+  if (r->precision == IFT_FP32_ELEM)
+    with_disc(r->prob, EqLaunch<float>{a, jac, n_pts, st, r->d_Bw, r->d_Bx, fa, r->fused_nt});
+  else
+    with_disc(r->prob, EqLaunch<double>{a, jac, n_pts, st, r->d_Bw, r->d_Bx, fa, r->fused_nt});
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+// Jacobian path through the fused assembly + Gram; rows: also leave the
+// rows of J~ and F~ in the workspace (d_Jt, d_Ft).
+static ift_status eq_jacobian_fused(ift_rom* r, const EqArgs& a, int n_pts, double* H, double* g, double* Jobj,
+                                    int* n_bad, bool rows, hipStream_t stream) {
+  const FusedLayout L = fused_layout(r, n_pts);
+  FusedArgs fa;
+  fa.E = L.E;
+  fa.nblk = L.nblk;
+  fa.part = r->d_fpart;
+  fa.part_bad = r->d_fbad;
+  fa.rows = rows ? 1 : 0;
+  ift_status s = dispatch_eq(r, a, true, n_pts, stream, &fa);
+  if (s != IFT_OK) return s;
+  const int D1 = r->D + 1;
+  const int nbe = (D1 * (D1 + 1) / 2 + GF_ENT - 1) / GF_ENT;
+  ProfScope ps(IFT_PROF_GRAM, stream);
+  hipLaunchKernelGGL(k_fused_final, dim3(nbe + 1, n_pts), dim3(256), 0, stream, (const double*)r->d_fpart,
+                     (const int*)r->d_fbad, L.nblk, r->fused_nt, r->D, H, g, Jobj ? Jobj : r->d_J, n_bad,
+                     r->d_flag_or);
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }
 
@@ -791,9 +894,13 @@ extern "C" ift_status eq_assemble_jacobian(ift_rom* r, const double* mu, const d
                                            hipStream_t stream) {
   if (!r || !w || (r->m > 0 && !tau) || !finite_mu(r->prob, mu)) return IFT_EINVAL;
   EqArgs a = eq_args(r, mu, w, tau);
-  ift_status s = dispatch_eq(r, a, true, 1, stream);
-  if (s != IFT_OK) return s;
-  s = gram(r, 1, H ? H : r->d_H, g ? g : r->d_g, Jobj, n_bad, stream);
+  ift_status s;
+  if (r->fused_nt > 0) {
+    s = eq_jacobian_fused(r, a, 1, H ? H : r->d_H, g ? g : r->d_g, Jobj, n_bad, Jt != nullptr, stream);
+  } else {
+    s = dispatch_eq(r, a, true, 1, stream);
+    if (s == IFT_OK) s = gram(r, 1, H ? H : r->d_H, g ? g : r->d_g, Jobj, n_bad, stream);
+  }
   if (s != IFT_OK) return s;
   if (Jt) HIP_TRY(hipMemcpyAsync(Jt, r->d_Jt, (size_t)r->nrows * r->D * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return IFT_OK;
@@ -821,6 +928,7 @@ extern "C" ift_status eq_assemble_jacobian_batch(ift_rom* r, int n_pts, const do
   double mu0[2] = {1.0, 0.0};
   EqArgs a = eq_args(r, mu0, w, tau);
   a.mu = mu;
+  if (r->fused_nt > 0) return eq_jacobian_fused(r, a, n_pts, H, g, Jobj, n_bad, false, stream);
   ift_status s = dispatch_eq(r, a, true, n_pts, stream);
   if (s != IFT_OK) return s;
   return gram(r, n_pts, H, g, Jobj, n_bad, stream);

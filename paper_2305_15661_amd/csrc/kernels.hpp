@@ -183,6 +183,7 @@ template <class D, class R>
 __global__ __launch_bounds__(NTHR_PTS) void k_points_eq(EqArgs a) {
   __shared__ ElemLDS<D, R> s;
   const int k = blockIdx.x, pt = blockIdx.y;
+  if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
   const int tid = threadIdx.x;
   load_tab<D, R>(s, tid, NTHR_PTS);
   load_eq<D, R>(s, a, k, pt, tid, NTHR_PTS);
@@ -231,6 +232,7 @@ template <class D, class R>
 __global__ __launch_bounds__(NTHR) void k_eq_res(EqArgs a) {
   __shared__ ElemLDS<D, R> s;
   const int k = blockIdx.x, pt = blockIdx.y;
+  if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
   const int tid = threadIdx.x;
   load_tab<D, R>(s, tid, NTHR);
   load_eq<D, R>(s, a, k, pt, tid, NTHR);
@@ -260,90 +262,596 @@ __global__ __launch_bounds__(NTHR) void k_eq_res(EqArgs a) {
   }
 }
 
-// C[r][j] = sum_{k<K} Jx[r][a0 + k] B[k*ldb + j] for r < nue, j < ncol, on
-// 16x16x4 FP64 matrix-core tiles; 16x16 output tiles are dealt to the waves
-// round-robin.  Lane layout: A[i][k] from lane
-// i + 16k, B[k][j] from lane j + 16k, accumulator register v of lane l
-// holds C[l/16 + 4v][l%16].
-template <class D, class R, class Out>
-IFT_DEV void project_tiles(const ElemLDS<D, R>& s, int a0, int K, const double* B, int ldb, int ncol, int wave,
-                           int lane, Out out) {
+// ------------------------------------------------------------------------
+// EQ assembly in factorized form.  With the point Jacobians of phase B,
+//   A_e = dR/dU_e Phi_e + dR/dU_e' Phi_e' = Aw * Bw,
+//   B_e = dR/dx_e Psi_e                  = Ax * Bx,
+// where the A factors hold quadrature-point quantities of the evaluation
+//   Aw: T [(i,c),(q,c')]   = -w_q sum_d gp[q][i][d] df/du[q][c][d][c'],
+//       S-[(i,c),(f,q,c')] =  wf_q L_q(k_f(i)) dH/du-[f][q][c][c']   (0 if i not on f),
+//       S+[(i,c),(f,q,c')] =  wf_q L_q(k_f(i)) dH/du+[f][q][c][c'],
+//   Ax: [(i,c),(q,ab)]     =  w_q f_c . d(cof(J) grad phi_i)/dJ_ab,
+//       [(i,c),(f,q,d)]    =  wf_q L_q(k_f(i)) dH/dn~ . dn~/dt_d,
+// and the B factors hold the reduced bases at the same points, which depend
+// only on the ROM and are built once at ROM creation (k_point_bases):
+//   Bw: Phi_e at the volume points, the traces of Phi_e and Phi_e' at the
+//       face points;  Bx: dJ_ab/dtau at the volume points and dt/dtau at the
+//       face points (cof(J) and n~ are linear in x_e).
+// Both products run on FP64 matrix cores; each lane generates its A operand
+// from the point data in LDS and reads its B operand from global memory.
+template <class D>
+struct EqOp {
+  static constexpr int KV = D::NQV * D::NC;          // volume block of Aw
+  static constexpr int KF = 3 * D::NQF * D::NC;      // one face block of Aw
+  static constexpr int KW = KV + 2 * KF;
+  static constexpr int KWP = (KW + 3) & ~3;          // padded to the MFMA k-step
+  static constexpr int KXV = 4 * D::NQV;             // volume block of Ax
+  static constexpr int KX = KXV + 3 * D::NQF * 2;
+  static constexpr int KXP = (KX + 3) & ~3;
+};
+
+template <class D, class R>
+struct EqAsmLDS {
+  RefTab tab;
+  Pts<D, R> p;
+  R Re[D::NUE];
+};
+
+// Entries of Aw and Ax.  The *_vol / *_face forms take the quadrature
+// point, face and component directly; aw_entry / ax_entry map a column to
+// them.  They never select between loaded values: every load executes,
+// selects are between constants, and a choice between two loaded values is
+// the exact blend a s + b (1 - s) with s in {0, 1} (finite operands).  The
+// compiler otherwise sinks such loads into divergent branches, and one such
+// lowering was seen to leave the wrong arm in some lanes.
+IFT_DEV double pick(double a, double b, bool first) {
+  const double s = first ? 1.0 : 0.0;
+  return a * s + b * (1.0 - s);
+}
+
+template <class D, class R>
+IFT_DEV double aw_vol(const RefTab& t, const Pts<D, R>& p, int i, int c, int q, int cc) {
+  return -t.wv[q] * (double(p.gp[q][i][0]) * double(p.Af[q][c][0][cc]) +
+                     double(p.gp[q][i][1]) * double(p.Af[q][c][1][cc]));
+}
+
+template <class D, class R>
+IFT_DEV double aw_face(const RefTab& t, const Pts<D, R>& p, int i, int c, bool plus, int f, int q, int cc) {
+  const double hp = double(p.dHp[f][q][c][cc]);
+  const double hm = double(p.dHm[f][q][c][cc]);
+  return t.wl[i][f][q] * pick(hp, hm, plus);
+}
+
+template <class D, class R>
+IFT_DEV double ax_vol(const RefTab& t, const Pts<D, R>& p, int i, int c, int q, int ab) {
+  // d/dJ_ab of w_q f_c . (cof(J) grad phi_i), cof(J) = [[J11, -J10], [-J01, J00]]
+  const double px = t.dphiv[q][i][0], py = t.dphiv[q][i][1];
+  const double f0 = double(p.fv[q][c][0]), f1 = double(p.fv[q][c][1]);
+  const double sgn = (ab == 0 || ab == 3) ? -1.0 : 1.0;
+  return (sgn * t.wv[q]) * pick(f1, f0, ab < 2) * pick(px, py, (ab & 1) != 0);
+}
+
+template <class D, class R>
+IFT_DEV double ax_face(const RefTab& t, const Pts<D, R>& p, int i, int c, int f, int q, int d) {
+  // d/dt_d of n~ = (t_y, -t_x)
+  const double h0 = double(p.dHn[f][q][c][0]), h1 = double(p.dHn[f][q][c][1]);
+  return t.wl[i][f][q] * pick(-h1, h0, d == 0);
+}
+
+template <class D, class R>
+IFT_DEV double aw_entry(const RefTab& t, const Pts<D, R>& p, int r, int col) {
+  using O = EqOp<D>;
+  constexpr int NC = D::NC;
+  const int rr = r < D::NUE ? r : 0;
+  const int i = rr / NC, c = rr % NC;
+  const int cv = col < O::KV ? col : O::KV - 1;
+  const double vv = aw_vol<D, R>(t, p, i, c, cv / NC, cv % NC);
+  const int cfa = col - O::KV;
+  const bool plus = cfa >= O::KF;
+  int cf = plus ? cfa - O::KF : cfa;
+  cf = cf < 0 ? 0 : (cf >= O::KF ? O::KF - 1 : cf);
+  const double vf = aw_face<D, R>(t, p, i, c, plus, cf / (D::NQF * NC), (cf / NC) % D::NQF, cf % NC);
+  const double sv = col < O::KV ? 1.0 : 0.0;
+  return (vv * sv + vf * (1.0 - sv)) * ((r < D::NUE && col < O::KW) ? 1.0 : 0.0);
+}
+
+template <class D, class R>
+IFT_DEV double ax_entry(const RefTab& t, const Pts<D, R>& p, int r, int col) {
+  using O = EqOp<D>;
+  constexpr int NC = D::NC;
+  const int rr = r < D::NUE ? r : 0;
+  const int i = rr / NC, c = rr % NC;
+  const int cv = col < O::KXV ? col : O::KXV - 1;
+  const double vv = ax_vol<D, R>(t, p, i, c, cv >> 2, cv & 3);
+  int cf = col - O::KXV;
+  cf = cf < 0 ? 0 : (cf >= O::KX - O::KXV ? O::KX - O::KXV - 1 : cf);
+  const double vf = ax_face<D, R>(t, p, i, c, cf / (2 * D::NQF), (cf >> 1) % D::NQF, cf & 1);
+  const double sv = col < O::KXV ? 1.0 : 0.0;
+  return (vv * sv + vf * (1.0 - sv)) * ((r < D::NUE && col < O::KX) ? 1.0 : 0.0);
+}
+
+// Reduced bases at the quadrature points, per sampled element (ROM creation):
+//   Bw [n_s][KWP][n + 1], Bx [n_s][KXP][m + 1]; padded rows and the last
+//   column are zero, so a lane whose output column lies outside the block
+//   loads that zero instead of branching around its load.
+template <class D>
+__global__ __launch_bounds__(256) void k_point_bases(const double* Phi_s, const double* Phin_s, const double* Psi_s,
+                                                     int n, int m, double* Bw, double* Bx) {
+  using O = EqOp<D>;
+  constexpr int NC = D::NC;
+  const RefTab& t = c_tab[D::P - 1];
+  const int k = blockIdx.x;
+  const double* Ph = Phi_s + (long long)k * D::NUE * n;
+  const double* Pn = Phin_s + (long long)k * D::NUN * n;
+  const double* Ps = Psi_s + (long long)k * D::NXE * m;
+  const int lw = n + 1, lx = m + 1;
+  for (int e = threadIdx.x; e < O::KWP * lw; e += 256) {
+    const int row = e / lw, j = e % lw;
+    double a = 0.0;
+    if (j < n) {
+      if (row < O::KV) {
+        const int q = row / NC, cc = row % NC;
+        for (int jn = 0; jn < D::NN; ++jn) a += t.phiv[q][jn] * Ph[(jn * NC + cc) * n + j];
+      } else if (row < O::KW) {
+        const bool plus = row >= O::KV + O::KF;
+        const int cf = row - O::KV - (plus ? O::KF : 0);
+        const int f = cf / (D::NQF * NC), q = (cf / NC) % D::NQF, cc = cf % NC;
+        for (int kk = 0; kk < D::NE; ++kk)
+          a += t.L[q][kk] * (plus ? Pn[((f * D::NE + kk) * NC + cc) * n + j] : Ph[(t.en[f][kk] * NC + cc) * n + j]);
+      }
+    }
+    Bw[((long long)k * O::KWP + row) * lw + j] = a;
+  }
+  for (int e = threadIdx.x; e < O::KXP * lx; e += 256) {
+    const int row = e / lx, j = e % lx;
+    double a = 0.0;
+    if (j < m) {
+      if (row < O::KXV) {
+        const int q = row >> 2, ab = row & 3, ca = ab >> 1, db = ab & 1;
+        for (int kn = 0; kn < D::NN; ++kn) a += Ps[(2 * kn + ca) * m + j] * t.dphiv[q][kn][db];
+      } else if (row < O::KX) {
+        const int cf = row - O::KXV;
+        const int f = cf / (2 * D::NQF), q = (cf >> 1) % D::NQF, d = cf & 1;
+        for (int kk = 0; kk < D::NE; ++kk) a += t.dL[q][kk] * Ps[(2 * t.en[f][kk] + d) * m + j];
+      }
+    }
+    Bx[((long long)k * O::KXP + row) * lx + j] = a;
+  }
+}
+
+// C = A * B for one element on 16x16x4 FP64 matrix cores: A (nue x K) is
+// generated per lane by `aop(r, k)`, B (K x ncol, row stride ncol + 1, last
+// column zero) is read from global memory; output tiles are dealt to the
+// four waves.  Lane layout: A[i][k] from lane i + 16k, B[k][j] from lane
+// j + 16k, accumulator register v of lane l holds C[l/16 + 4v][l%16].  The
+// k-loop is straight-line code: out-of-range rows are multiplied by zero
+// and out-of-range columns load the zero column.
+template <class D, class AOp, class Out>
+IFT_DEV void mfma_elem(int K, const double* B, int ncol, int wave, int lane, AOp aop, Out out) {
   constexpr int MT = (D::NUE + 15) / 16;
   const int NT = (ncol + 15) / 16;
-  const int ntile = MT * NT;
-  for (int t = wave; t < ntile; t += NTHR / 64) {
-    const int mt = t % MT;   // row tile
-    const int nt = t / MT;   // column tile
+  const int ld = ncol + 1;
+  for (int tt = wave; tt < MT * NT; tt += NTHR / 64) {
+    const int mt = tt % MT, nt = tt / MT;
     const int row = 16 * mt + (lane & 15);
     const int col = 16 * nt + (lane & 15);
     const int kl = lane >> 4;
-    dvec4 c = {0.0, 0.0, 0.0, 0.0};
+    const int rowc = row < D::NUE ? row : D::NUE - 1;
+    const double rmask = row < D::NUE ? 1.0 : 0.0;
+    const int colc = col < ncol ? col : ncol;
+    dvec4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < K; k0 += 4) {
-      const int kk = k0 + kl;
-      const double av = (row < D::NUE && kk < K) ? double(s.Jx[row][a0 + kk]) : 0.0;
-      const double bv = (col < ncol && kk < K) ? B[kk * ldb + col] : 0.0;
-      c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, c, 0, 0, 0);
+      const double av = aop(rowc, k0 + kl) * rmask;
+      const double bv = B[(k0 + kl) * ld + colc];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * mt + kl + 4 * v;
       const int j = 16 * nt + (lane & 15);
-      if (r < D::NUE && j < ncol) out(r, j, c[v]);
+      if (r < D::NUE && j < ncol) out(r, j, acc[v]);
     }
   }
 }
 
-// Jacobian rows of the stacked least-squares problem at one evaluation point.
 template <class D, class R>
-__global__ __launch_bounds__(NTHR) void k_eq_asm(EqArgs a) {
-  __shared__ ElemLDS<D, R> s;
-  extern __shared__ double dyn[];
+__global__ __launch_bounds__(NTHR) void k_eq_asm(EqArgs a, const double* Bw, const double* Bx) {
+  using O = EqOp<D>;
+  __shared__ EqAsmLDS<D, R> s;
   const int n = a.n, m = a.m, Dd = a.D;
-  double* V = dyn;                                  // [nue+nun][n]
-  double* P = V + (D::NUE + D::NUN) * n;            // [nxe][m]
   const int k = blockIdx.x, pt = blockIdx.y;
   const int tid = threadIdx.x;
-  load_tab<D, R>(s, tid, NTHR);
-  copy_words<D, R>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), tid, NTHR);
   {
-    const double* src = a.Phi_s + (long long)k * D::NUE * n;
-    for (int i = tid; i < D::NUE * n; i += NTHR) V[i] = src[i];
-    src = a.Phin_s + (long long)k * D::NUN * n;
-    for (int i = tid; i < D::NUN * n; i += NTHR) V[D::NUE * n + i] = src[i];
-    src = a.Psi_s + (long long)k * D::NXE * m;
-    for (int i = tid; i < D::NXE * m; i += NTHR) P[i] = src[i];
+    const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
+    int* dst = reinterpret_cast<int*>(&s.tab);
+    for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
   }
-  __syncthreads();
-  phase_assemble<D, R, true>(s, tid);
+  copy_words<D, R>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), tid, NTHR);
   __syncthreads();
   const double sq = a.srho[k];
   const long long nrow_e = (long long)a.n_s * D::NUE;
   const long long po = (long long)pt * a.nrows;
-  if (tid < D::NUE) a.Ft[po + (long long)k * D::NUE + tid] = sq * double(s.Re[tid]);
-  if (tid == 0) {
-    double acc = 0.0;
-    for (int r = 0; r < D::NUE; ++r) acc += double(s.Re[r]) * double(s.Re[r]);
-    acc += double(s.p.N) * double(s.p.N);
-    a.Jpart[(long long)pt * a.n_s + k] = 0.5 * a.rho[k] * acc;
-    a.flags[(long long)pt * a.n_s + k] = s.p.bad;
-    a.Ft[po + nrow_e + k] = sq * double(s.p.N);
-  }
-  // distortion row sqrt(rho) [0, dN/dx_e Psi_e]
   double* Jt = a.Jt + po * Dd;
+  double* rows = Jt + (long long)k * D::NUE * Dd;
+  const int wave = tid >> 6, lane = tid & 63;
+  mfma_elem<D>(O::KWP, Bw + (long long)k * O::KWP * (n + 1), n, wave, lane,
+               [&](int r, int c) { return aw_entry<D, R>(s.tab, s.p, r, c); },
+               [&](int r, int j, double v) { rows[r * Dd + j] = sq * v; });
+  if (m > 0)
+    mfma_elem<D>(O::KXP, Bx + (long long)k * O::KXP * (m + 1), m, wave ^ 3, lane,
+                 [&](int r, int c) { return ax_entry<D, R>(s.tab, s.p, r, c); },
+                 [&](int r, int j, double v) { rows[r * Dd + n + j] = sq * v; });
+  // distortion row sqrt(rho) [0, dN/dx_e Psi_e]
+  const double* Ps = a.Psi_s + (long long)k * D::NXE * m;
   for (int j = tid; j < Dd; j += NTHR) {
     double acc = 0.0;
     if (j >= n)
-      for (int c = 0; c < D::NXE; ++c) acc += double(s.p.dN[c]) * P[c * m + (j - n)];
+      for (int c = 0; c < D::NXE; ++c) acc += double(s.p.dN[c]) * Ps[c * m + (j - n)];
     Jt[(nrow_e + k) * Dd + j] = sq * acc;
   }
-  // element rows sqrt(rho) [dR/dU_e Phi_e + dR/dU_e' Phi_e', dR/dx_e Psi_e]
-  const int wave = tid >> 6, lane = tid & 63;
-  double* rows = Jt + (long long)k * D::NUE * Dd;
-  project_tiles<D, R>(s, 0, D::NUE + D::NUN, V, n, n, wave, lane,
-                      [&](int r, int j, double v) { rows[r * Dd + j] = sq * v; });
-  if (m > 0)
-    project_tiles<D, R>(s, D::NUE + D::NUN, D::NXE, P, m, m, wave, lane,
-                        [&](int r, int j, double v) { rows[r * Dd + n + j] = sq * v; });
+  if (tid < D::NUE) {
+    const R rv = residual_entry_p<D, R>(s.p, s.tab, tid);
+    s.Re[tid] = rv;
+    a.Ft[po + (long long)k * D::NUE + tid] = sq * double(rv);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double r2 = 0.0;
+    for (int r = 0; r < D::NUE; ++r) r2 += double(s.Re[r]) * double(s.Re[r]);
+    r2 += double(s.p.N) * double(s.p.N);
+    a.Jpart[(long long)pt * a.n_s + k] = 0.5 * a.rho[k] * r2;
+    a.flags[(long long)pt * a.n_s + k] = s.p.bad;
+    a.Ft[po + nrow_e + k] = sq * double(s.p.N);
+  }
+}
+
+// ------------------------------------- fused assembly and Gram (A10-A12)
+// With the augmented element block
+//   M_e = sqrt(rho_e) [ A_e        B_e              R_e ]   (rows 0..nue-1)
+//                     [ 0   dN_e/dx_e Psi_e         N_e ]   (row nue)
+// of D + 1 columns, sum_e M_e^T M_e holds H = J~^T J~ (leading D x D block),
+// g = J~^T F~ (column D) and 2 J~ (corner).  Each wave owns E consecutive
+// sampled elements of one evaluation point: it forms M_e as MT x NT FP64
+// MFMA tiles and adds M_e^T M_e to NT(NT+1)/2 register tiles with a second
+// MFMA.  That works without moving data because an accumulator register v
+// of a tile holds rows 4v..4v+3 in exactly the lane order the A and B
+// operands of the next MFMA expect.  The four waves of a block are added in
+// wave order through LDS and the block writes one partial; k_fused_final
+// adds the partials in block order, so the result is deterministic.
+constexpr int FUSED_MAXNT = 3;
+constexpr int GF_ENT = 16, GF_GRP = 16;   // final reductions: entries x block groups per workgroup
+
+struct FusedArgs {
+  int E;              // sampled elements per wave
+  int nblk;           // blocks per evaluation point
+  double* part;       // [pt][nblk][NT(NT+1)/2][256]   (register-major tiles)
+  int* part_bad;      // [pt][nblk][2]  (count, OR of the invalid flags)
+  int rows;           // also store the rows of J~ and F~ (Jt, Ft)
+};
+
+template <class D, class R>
+struct alignas(16) FusedSlot {
+  Pts<D, R> p;
+};
+
+// One wave copies one element's point data (16-byte words where the array
+// stride allows).
+template <class D, class R>
+IFT_DEV void copy_pts_wave(Pts<D, R>* dst, const Pts<D, R>* src, int lane) {
+  if constexpr (sizeof(Pts<D, R>) % 16 == 0) {
+    constexpr int nw = sizeof(Pts<D, R>) / 16;
+    const int4* s4 = reinterpret_cast<const int4*>(src);
+    int4* d4 = reinterpret_cast<int4*>(dst);
+    for (int i = lane; i < nw; i += 64) d4[i] = s4[i];
+  } else if constexpr (sizeof(Pts<D, R>) % 8 == 0) {
+    constexpr int nw = sizeof(Pts<D, R>) / 8;
+    const int2* s2 = reinterpret_cast<const int2*>(src);
+    int2* d2 = reinterpret_cast<int2*>(dst);
+    for (int i = lane; i < nw; i += 64) d2[i] = s2[i];
+  } else {
+    constexpr int nw = sizeof(Pts<D, R>) / 4;
+    const int* s1 = reinterpret_cast<const int*>(src);
+    int* d1 = reinterpret_cast<int*>(dst);
+    for (int i = lane; i < nw; i += 64) d1[i] = s1[i];
+  }
+}
+
+template <class D, class R, int NT>
+__global__ __launch_bounds__(NTHR) void k_eq_fused(EqArgs a, const double* Bw, const double* Bx, FusedArgs f) {
+  using O = EqOp<D>;
+  constexpr int NUE = D::NUE;
+  constexpr int MT = (NUE + 1 + 15) / 16;           // row tiles (element rows + distortion row)
+  constexpr int NH = NT * (NT + 1) / 2;             // upper tiles of the Gram
+  constexpr int RD_MT = NUE / 16, RD_K = (NUE % 16) % 4, RD_V = (NUE % 16) / 4;  // distortion row
+  __shared__ RefTab tab;
+  __shared__ union {
+    FusedSlot<D, R> w[NTHR / 64];
+    double red[NTHR / 64 - 1][256];
+  } u;
+  __shared__ int sbad[NTHR / 64][2];
+  const int n = a.n, m = a.m, Dd = a.D;
+  const int blk = blockIdx.x, pt = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int kl = lane >> 4, li = lane & 15;
+  {
+    const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
+    int* dst = reinterpret_cast<int*>(&tab);
+    for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
+  }
+  dvec4 h[NH];
+#pragma unroll
+  for (int t = 0; t < NH; ++t) h[t] = dvec4{0.0, 0.0, 0.0, 0.0};
+  int nbad = 0, bor = 0;
+  const long long nrow_e = (long long)a.n_s * NUE;
+  const long long po = (long long)pt * a.nrows;
+  const int kbeg = (blk * (NTHR / 64) + wave) * f.E;
+  FusedSlot<D, R>& S = u.w[wave];
+  for (int e = 0; e < f.E; ++e) {
+    const int k = kbeg + e;
+    __syncthreads();   // the slot's previous contents are consumed; tab is loaded
+    if (k < a.n_s) copy_pts_wave<D, R>(&S.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), lane);
+    __syncthreads();
+    if (k >= a.n_s) continue;
+    const Pts<D, R>& p = S.p;
+    const double sq = a.srho[k];
+    // residual entry of row `lane` (row nue: the distortion), distortion
+    // row entry of x-column `lane`
+    double rv = 0.0, dv = 0.0;
+    if (lane < NUE) rv = double(residual_entry_p<D, R>(p, tab, lane));
+    else if (lane == NUE) rv = double(p.N);
+    if (lane < m) {
+      const double* Ps = a.Psi_s + (long long)k * D::NXE * m + lane;
+#pragma unroll
+      for (int c = 0; c < D::NXE; ++c) dv += double(p.dN[c]) * Ps[c * m];
+    }
+    // M_e projection: columns [0, n) from Aw * Bw, [n, D) from Ax * Bx
+    dvec4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = dvec4{0.0, 0.0, 0.0, 0.0};
+    // per-lane row constants; rows past nue are multiplied by zero
+    int ri[MT], rc[MT];
+    double rm[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int row = 16 * mt + li;
+      rm[mt] = row < NUE ? 1.0 : 0.0;
+      ri[mt] = (row < NUE ? row : 0) / D::NC;
+      rc[mt] = (row < NUE ? row : 0) % D::NC;
+    }
+    const double* bw = Bw + (long long)k * O::KWP * (n + 1);
+    // one k-step of the w columns: A values av[mt] for columns 4 ks + kl
+    auto wstep = [&](int ks, const double* av) {
+      double bv[NT];   // loaded for every tile (tiles without w columns read the zero column)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int c = 16 * nt + li;
+        bv[nt] = bw[(4 * ks + kl) * (n + 1) + (c < n ? c : n)];
+      }
+      // every tile takes part (a tile without w columns adds zeros), so the
+      // k-loop is one basic block and the loads of later steps can be hoisted
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+    };
+    if constexpr (D::NC == 4) {
+      // k-step = one quadrature point (volume) or one (face, point) pair;
+      // the lane's column component is kl
+#pragma unroll 1
+      for (int q = 0; q < D::NQV; ++q) {
+        double av[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          av[mt] = aw_vol<D, R>(tab, p, ri[mt], rc[mt], q, kl) * rm[mt];
+        }
+        wstep(q, av);
+      }
+#pragma unroll 1
+      for (int pl = 0; pl < 2; ++pl)
+#pragma unroll 1
+        for (int fq = 0; fq < 3 * D::NQF; ++fq) {
+          double av[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            av[mt] = aw_face<D, R>(tab, p, ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl) * rm[mt];
+          }
+          wstep(D::NQV + pl * 3 * D::NQF + fq, av);
+        }
+    } else {
+#pragma unroll 4
+      for (int ks = 0; ks < O::KWP / 4; ++ks) {
+        double av[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) av[mt] = aw_entry<D, R>(tab, p, 16 * mt + li, 4 * ks + kl);
+        wstep(ks, av);
+      }
+    }
+    if (m > 0) {
+      const double* bx = Bx + (long long)k * O::KXP * (m + 1);
+      auto xstep = [&](int ks, const double* av) {
+        double bv[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int jx = 16 * nt + li - n;
+          bv[nt] = bx[(4 * ks + kl) * (m + 1) + ((jx >= 0 && jx < m) ? jx : m)];
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+      };
+      // volume k-steps: quadrature point q, entry ab = kl of J
+#pragma unroll 1
+      for (int q = 0; q < D::NQV; ++q) {
+        double av[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          av[mt] = ax_vol<D, R>(tab, p, ri[mt], rc[mt], q, kl) * rm[mt];
+        }
+        xstep(q, av);
+      }
+      // face k-steps: column 4 ks' + kl of the (face, point, direction) block
+#pragma unroll 1
+      for (int ks = 0; ks < (O::KXP - O::KXV) / 4; ++ks) {
+        const int cf0 = 4 * ks + kl;
+        const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
+        const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
+        double av[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          av[mt] = ax_face<D, R>(tab, p, ri[mt], rc[mt], cf / (2 * D::NQF), (cf >> 1) % D::NQF, cf & 1) * (rm[mt] * cm);
+        xstep(D::NQV + ks, av);
+      }
+    }
+    // scale by sqrt(rho_e); insert the residual column and the distortion row
+    double dsrc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int jd = 16 * nt + li - n;
+      dsrc[nt] = __shfl(dv, (jd >= 0 && jd < 64) ? jd : 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * mt + kl + 4 * v;   // < 32
+        const double rsrc = __shfl(rv, row);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int c = 16 * nt + li, jd = c - n;
+          double x = sq * acc[mt][nt][v];
+          if (c == Dd) x = sq * rsrc;   // zero below the distortion row
+          else if (mt == RD_MT && kl == RD_K && v == RD_V && jd >= 0 && jd < m) x = sq * dsrc[nt];
+          acc[mt][nt][v] = x;
+        }
+      }
+    if (f.rows) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * mt + kl + 4 * v, c = 16 * nt + li;
+            if (row > NUE || c > Dd) continue;
+            const long long gr = row < NUE ? (long long)k * NUE + row : nrow_e + k;
+            if (c < Dd) a.Jt[(po + gr) * Dd + c] = acc[mt][nt][v];
+            else a.Ft[po + gr] = acc[mt][nt][v];
+          }
+    }
+    // Gram: rows 4v..4v+3 of row tile mt are the k-block of one MFMA step
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (16 * mt + 4 * v > NUE) continue;
+        int t = 0;
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = ta; tb < NT; ++tb, ++t)
+            h[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[mt][ta][v], acc[mt][tb][v], h[t], 0, 0, 0);
+      }
+    const int bad = p.bad;
+    nbad += bad != 0;
+    bor |= bad;
+    if (f.rows && lane == 0) a.flags[(long long)pt * a.n_s + k] = bad;
+  }
+  // add the four waves in wave order; one partial per block
+  __syncthreads();
+  if (lane == 0) {
+    sbad[wave][0] = nbad;
+    sbad[wave][1] = bor;
+  }
+  double* part = f.part + ((long long)pt * f.nblk + blk) * NH * 256;
+#pragma unroll
+  for (int t = 0; t < NH; ++t) {
+    if (wave > 0)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) u.red[wave - 1][v * 64 + lane] = h[t][v];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double x = h[t][v];
+#pragma unroll
+        for (int w = 0; w < NTHR / 64 - 1; ++w) x += u.red[w][v * 64 + lane];
+        part[t * 256 + v * 64 + lane] = x;
+      }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int c = 0, o = 0;
+    for (int w = 0; w < NTHR / 64; ++w) {
+      c += sbad[w][0];
+      o |= sbad[w][1];
+    }
+    f.part_bad[((long long)pt * f.nblk + blk) * 2] = c;
+    f.part_bad[((long long)pt * f.nblk + blk) * 2 + 1] = o;
+  }
+}
+
+// Sum of the block partials: workgroup x reduces 16 upper entries of the
+// augmented Gram (H, g and the objective); its 16 thread groups take the
+// blocks q, q + 16, ... and are then added in group order (fixed order).
+// The extra last workgroup reduces the invalid flags.
+__global__ __launch_bounds__(256) void k_fused_final(const double* part, const int* part_bad, int nblk, int NT, int D,
+                                                     double* H, double* g, double* Jobj, int* n_bad, int* flag_or) {
+  __shared__ double red[GF_GRP][GF_ENT];
+  const int pt = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int NH = NT * (NT + 1) / 2;
+  const int D1 = D + 1;
+  const int nent = D1 * (D1 + 1) / 2;
+  const int nbe = (nent + GF_ENT - 1) / GF_ENT;
+  const int* pb = part_bad + (long long)pt * nblk * 2;
+  if ((int)blockIdx.x == nbe) {
+    if (tid == 0) {
+      int c = 0, o = 0;
+      for (int b = 0; b < nblk; ++b) {
+        c += pb[2 * b];
+        o |= pb[2 * b + 1];
+      }
+      if (n_bad) n_bad[pt] = c;
+      if (flag_or) flag_or[pt] = o;
+    }
+    return;
+  }
+  const int el = tid % GF_ENT, q = tid / GF_ENT;
+  const int e = blockIdx.x * GF_ENT + el;
+  // e -> (i, j), i <= j <= D, row-major over the upper triangle
+  int i = 0, rem = e < nent ? e : 0;
+  while (rem >= D1 - i) {
+    rem -= D1 - i;
+    ++i;
+  }
+  const int j = i + rem;
+  const int ta = i / 16, tb = j / 16;
+  const int t = ta * NT - ta * (ta - 1) / 2 + (tb - ta);
+  const int r = i % 16, c = j % 16;
+  const long long stride = (long long)NH * 256;
+  const double* pp = part + (long long)pt * nblk * stride + t * 256 + (r / 4) * 64 + (r % 4) * 16 + c;
+  double v = 0.0;
+  if (e < nent)
+    for (int b = q; b < nblk; b += GF_GRP) v += pp[b * stride];
+  red[q][el] = v;
+  __syncthreads();
+  if (q != 0 || e >= nent) return;
+  for (int w = 1; w < GF_GRP; ++w) v += red[w][el];
+  if (j < D) {
+    H[(long long)pt * D * D + (long long)i * D + j] = v;
+    H[(long long)pt * D * D + (long long)j * D + i] = v;
+  } else if (i < D) {
+    g[(long long)pt * D + i] = v;
+  } else {
+    int o = 0;   // objective; +inf when any sampled element is invalid
+    for (int b = 0; b < nblk; ++b) o |= pb[2 * b + 1];
+    Jobj[pt] = o ? __builtin_inf() : 0.5 * v;
+  }
 }
 
 // ------------------------------------------------- Gram and objective
@@ -372,7 +880,7 @@ struct GramArgs {
 };
 
 // Row groups per block: as many as fit beside the TD x TD tile threads.
-IFT_DEV inline int gram_groups(int TD) { return TD * TD <= 64 ? 4 : (TD * TD <= 128 ? 2 : 1); }
+IFT_DEV int gram_groups(int TD) { return TD * TD <= 64 ? 4 : (TD * TD <= 128 ? 2 : 1); }
 
 __global__ __launch_bounds__(256) void k_gram_part(GramArgs a) {
   extern __shared__ double sh[];
@@ -466,7 +974,6 @@ __global__ __launch_bounds__(256) void k_gram_part(GramArgs a) {
 // its 16 thread groups read the partials of 16 entries as 128-byte
 // segments, group q taking blocks q, q+16, ...; the groups are then added
 // in group order.  The extra last block reduces the objective.
-constexpr int GF_ENT = 16, GF_GRP = 16;
 
 __global__ __launch_bounds__(256) void k_gram_final(GramArgs a) {
   __shared__ double red[GF_GRP][GF_ENT];

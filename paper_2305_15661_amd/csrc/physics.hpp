@@ -34,7 +34,8 @@ IFT_DEV void phys_flux(const T* u, T (*f)[2], R gamma) {
     f[0][1] = u[0];
   } else {
     T rho = u[0];
-    T vx = u[1] / rho, vy = u[2] / rho;
+    T ir = R(1) / rho;
+    T vx = u[1] * ir, vy = u[2] * ir;
     T p = (gamma - R(1)) * (u[3] - R(0.5) * rho * (vx * vx + vy * vy));
     f[0][0] = u[1];
     f[0][1] = u[2];
@@ -59,10 +60,11 @@ IFT_DEV bool physical_state(const T* u, R gamma) {
   }
 }
 
+// |lam| with Harten's entropy fix; i2d = 1 / (2 delta).
 template <class T, class R>
-IFT_DEV T harten_abs(T lam, T delta) {
+IFT_DEV T harten_abs(T lam, T delta, T i2d) {
   T a = tabs(lam);
-  if (val(a) < val(delta)) return (lam * lam + delta * delta) / (R(2) * delta);
+  if (val(a) < val(delta)) return (lam * lam + delta * delta) * i2d;
   return a;
 }
 
@@ -76,35 +78,40 @@ IFT_DEV void num_flux(const T* uL, const T* uR, T ntx, T nty, R gamma, T* H) {
   } else {
     const R gm1 = gamma - R(1);
     T nmag = tsqrt(ntx * ntx + nty * nty);
-    T nx = ntx / nmag, ny = nty / nmag;
+    T inm = R(1) / nmag;
+    T nx = ntx * inm, ny = nty * inm;
     T rL = uL[0], rR = uR[0];
-    T vxL = uL[1] / rL, vyL = uL[2] / rL, vxR = uR[1] / rR, vyR = uR[2] / rR;
+    T irL = R(1) / rL, irR = R(1) / rR;
+    T vxL = uL[1] * irL, vyL = uL[2] * irL, vxR = uR[1] * irR, vyR = uR[2] * irR;
     T pL = gm1 * (uL[3] - R(0.5) * rL * (vxL * vxL + vyL * vyL));
     T pR = gm1 * (uR[3] - R(0.5) * rR * (vxR * vxR + vyR * vyR));
     T qL = vxL * ntx + vyL * nty, qR = vxR * ntx + vyR * nty;   // v . n~
-    T HL = (uL[3] + pL) / rL, HR = (uR[3] + pR) / rR;
+    T HL = (uL[3] + pL) * irL, HR = (uR[3] + pR) * irR;
     T sL = tsqrt(rL), sR = tsqrt(rR);
-    T den = sL + sR;
+    T iden = R(1) / (sL + sR);
     T rt = sL * sR;
-    T ut = (sL * vxL + sR * vxR) / den;
-    T vt = (sL * vyL + sR * vyR) / den;
-    T Ht = (sL * HL + sR * HR) / den;
+    T ut = (sL * vxL + sR * vxR) * iden;
+    T vt = (sL * vyL + sR * vyR) * iden;
+    T Ht = (sL * HL + sR * HR) * iden;
     T q2 = ut * ut + vt * vt;
     T c2 = gm1 * (Ht - R(0.5) * q2);
     T ct = tsqrt(c2);
+    T ic2 = R(1) / c2;
     T vn = ut * nx + vt * ny;
     T vtan = vt * nx - ut * ny;
     T dr = rR - rL, dp = pR - pL;
     T dvn = (vxR * nx + vyR * ny) - (vxL * nx + vyL * ny);
     T dvt = (vyR * nx - vxR * ny) - (vyL * nx - vxL * ny);
-    T a1 = (dp - rt * ct * dvn) / (R(2) * c2);
-    T a4 = (dp + rt * ct * dvn) / (R(2) * c2);
-    T a2 = dr - dp / c2;
+    T h2 = R(0.5) * ic2;
+    T a1 = (dp - rt * ct * dvn) * h2;
+    T a4 = (dp + rt * ct * dvn) * h2;
+    T a2 = dr - dp * ic2;
     T a3 = rt * dvt;
     T delta = R(0.1) * ct;
-    T l1 = harten_abs<T, R>(vn - ct, delta) * a1;
-    T l2 = harten_abs<T, R>(vn, delta);
-    T l4 = harten_abs<T, R>(vn + ct, delta) * a4;
+    T i2d = R(0.5) / delta;
+    T l1 = harten_abs<T, R>(vn - ct, delta, i2d) * a1;
+    T l2 = harten_abs<T, R>(vn, delta, i2d);
+    T l4 = harten_abs<T, R>(vn + ct, delta, i2d) * a4;
     T l2a2 = l2 * a2, l2a3 = l2 * a3;
     T d0 = l1 + l2a2 + l4;
     T d1 = l1 * (ut - ct * nx) + l2a2 * ut - l2a3 * ny + l4 * (ut + ct * nx);
@@ -133,8 +140,8 @@ IFT_DEV void boundary_state(int tag, const T* um, T ntx, T nty, const PhysConst&
     } else if (tag == 2) {
       for (int c = 0; c < NC; ++c) up[c] = um[c];
     } else {
-      T nmag = tsqrt(ntx * ntx + nty * nty);
-      T nx = ntx / nmag, ny = nty / nmag;
+      T inm = R(1) / tsqrt(ntx * ntx + nty * nty);
+      T nx = ntx * inm, ny = nty * inm;
       T mn = um[1] * nx + um[2] * ny;
       up[0] = um[0];
       up[1] = um[1] - R(2) * mn * nx;
