@@ -184,6 +184,7 @@ typedef struct {
   int n_backtrack;
   int converged;       /* input point meets tol; no step taken              */
   int status;          /* an ift_status                                     */
+  int iterations;      /* LM steps taken (batched solve; 0 or 1 for a step) */
 } ift_gn_info;
 
 /* One Levenberg-Marquardt step from z_n = (w, tau) (device, in/out):
@@ -194,6 +195,58 @@ typedef struct {
  * Synchronises the stream. */
 ift_status rom_gauss_newton_step(ift_rom* rom, const double* mu, double* w, double* tau,
                                  const ift_gn_params* params, ift_gn_info* info, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solves.  A batch groups n_inst ROM handles (each with its own
+ * bases, EQ set and weights; all on one problem, each with n + m + 1 <= 48)
+ * that are solved together, each at its own mu, by the Levenberg-Marquardt
+ * iteration of rom_gauss_newton_step (same step, line search and stopping
+ * rule), advanced on the device without host synchronisation.  The
+ * reduced coordinates of all instances are packed: instance i occupies
+ * z[zoff[i] .. zoff[i+1]) as (w_i, tau_i), zoff from ift_batch_layout.
+ * The batch owns every workspace; a handle is used on one stream at a time.
+ * ------------------------------------------------------------------------ */
+typedef struct ift_batch ift_batch;
+
+/* roms: host array of n_inst handles (not owned; they must outlive the
+ * batch).  IFT_EINVAL when n_inst < 1, a handle is null, the handles do not
+ * share one problem and precision, or an instance has n + m + 1 > 48. */
+ift_status ift_batch_create(int n_inst, ift_rom* const* roms, ift_batch** out);
+void ift_batch_destroy(ift_batch* batch);
+
+/* Packed offsets (HOST arrays of n_inst + 1 ints, either may be null):
+ * zoff for z and g (steps of n_i + m_i), hoff for H (steps of (n_i + m_i)^2). */
+ift_status ift_batch_layout(const ift_batch* batch, int* zoff, int* hoff);
+
+/* Picks the elements-per-wave work split of the fused assembly for this
+ * batch by timing the candidates {4, 8, 16, 32} on the Jacobian assembly at
+ * (mu, z) (device arrays as below); the choice is kept by the handle.
+ * Synchronises the stream.  *chosen (host, may be null) receives it. */
+ift_status ift_batch_autotune(ift_batch* batch, const double* mu, const double* z, int* chosen, hipStream_t stream);
+
+/* [S~; T~], J~_z^T J~_z and J~ of every instance at its (mu, z): mu device
+ * [n_inst][2], z device packed; g packed like z, H packed by hoff, Jobj and
+ * n_bad device [n_inst] (n_bad may be null).  Same quantities as
+ * eq_assemble_jacobian, instance by instance. */
+ift_status eq_assemble_jacobian_batched(ift_batch* batch, const double* mu, const double* z, double* Jobj, double* g,
+                                        double* H, int* n_bad, hipStream_t stream);
+
+/* Solves every instance from its start z (device, packed, overwritten by
+ * the last iterate) at mu (device [n_inst][2]): at most max_it LM steps per
+ * instance (max_it >= 0), each as in rom_gauss_newton_step with `params`.
+ * info: DEVICE array [n_inst]; per instance J_old = J~ at the start, J_new
+ * = J~ at the last iterate, alpha = last accepted step length, norm_S /
+ * norm_T at the last iterate, n_backtrack = halvings over all steps,
+ * converged, iterations, and status: IFT_OK (converged), IFT_ENOTCONV
+ * (max_it reached), IFT_ELINESEARCH, IFT_ESINGULAR, IFT_EBADMESH or
+ * IFT_ENONPHYS (invalid iterate).  flags bit 0 = 1: launch the kernels
+ * directly instead of replaying the captured HIP graph (same results).
+ * The rounds (Jacobian assembly, LM step, two line-search trials) run in
+ * replays of four captured rounds; after each replay the stream is
+ * synchronised to read how many instances are still running.  Returns
+ * IFT_OK when the launches succeeded (per-instance outcomes are in info). */
+ift_status rom_gauss_newton_solve_batched(ift_batch* batch, const double* mu, double* z, const ift_gn_params* params,
+                                          int max_it, ift_gn_info* info, int flags, hipStream_t stream);
 
 /* Kernel timing.  While enabled, every launch of the library's element
  * kernels and reductions is bracketed by HIP events on the caller's stream

@@ -1,0 +1,315 @@
+// Batched ROM Gauss-Newton solves: many instances (own mu, own ROM and EQ
+// set) advance together on the device, each through the Levenberg-Marquardt
+// step and Armijo backtracking of the single-instance solver.
+//
+// Every instance carries a small state machine (BatchState):
+//   BS_JAC     needs the Jacobian assembly at its iterate z,
+//   BS_SEARCH  has a step dz and tries z + alpha dz,
+//   BS_DONE    converged or stopped (status says why).
+// Each phase starts with k_batch_compact, which scans the instances in the
+// phase's state into work lists (exclusive sums of their element or block
+// counts); the work kernels are persistent grids that walk those lists, so
+// finished instances cost nothing and uneven EQ sets need no padding.  A
+// round (Jacobian phase, LM step, a few line-search trials) is the same
+// launch sequence for any state, which lets the host capture a few rounds
+// once in a HIP graph and replay them until every instance has finished.
+#pragma once
+#include "kernels.hpp"
+
+namespace ift {
+
+enum { BS_JAC = 0, BS_SEARCH = 1, BS_DONE = 2 };
+
+// One instance: its ROM's element data and its slices of the batch
+// workspace.  a.w / a.tau point at the current iterate z, a.mu at its mu.
+struct BatchInst {
+  EqArgs a;
+  const double* Bw;
+  const double* Bx;
+  double* z;          // [D]
+  double* zt;         // [D] trial iterate
+  double* dz;         // [D]
+  double* H;          // [D * D]
+  double* g;          // [D]
+  double* part;       // fused partials [nblk][NH][256]
+  int* part_bad;      // [nblk][2]
+  int nblk;           // fused blocks of this instance
+  int nt;             // fused column tiles (1..FUSED_MAXNT)
+};
+
+struct BatchState {
+  int state, it, n_bt, status;
+  int flag_or, n_bad, converged, n_bt_total;
+  double J, J0, Jtrial, alpha, slope, nS, nT, alpha_acc;
+};
+
+struct BatchParams {
+  double lambda, c1, tol;
+  int max_backtrack, max_it;
+};
+
+// Work lists of one phase.  off[q][i] = sum over active instances j < i of
+// their count in list q (q = 0: sampled elements; q = t: fused blocks of
+// the instances with t column tiles); cnt[q] = the totals.
+struct BatchLists {
+  int* off;   // [4][n_inst + 1]
+  int* cnt;   // [4]
+};
+
+// Instance that owns work item `item` of list q (upper bound search).
+IFT_DEV int batch_owner(const int* off, int n_inst, int item) {
+  int lo = 0, hi = n_inst;   // off[lo] <= item < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= item) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+constexpr int BC_THR = 1024;
+
+// Exclusive sums of the active instances' element and block counts (one
+// block, fixed order).  with_blocks = 0 leaves the block lists empty.
+__global__ __launch_bounds__(BC_THR) void k_batch_compact(const BatchInst* I, const BatchState* S, BatchLists L,
+                                                          int n_inst, int want, int with_blocks) {
+  __shared__ int sc[4][BC_THR];
+  const int t = threadIdx.x;
+  const int chunk = (n_inst + BC_THR - 1) / BC_THR;
+  const int beg = min(n_inst, t * chunk), end = min(n_inst, beg + chunk);
+  int c[4] = {0, 0, 0, 0};
+  for (int i = beg; i < end; ++i) {
+    if (S[i].state != want) continue;
+    c[0] += I[i].a.n_s;
+    if (with_blocks) c[I[i].nt] += I[i].nblk;
+  }
+  for (int q = 0; q < 4; ++q) sc[q][t] = c[q];
+  __syncthreads();
+  // inclusive scan over the threads (Hillis-Steele)
+  for (int d = 1; d < BC_THR; d <<= 1) {
+    int v[4];
+    for (int q = 0; q < 4; ++q) v[q] = t >= d ? sc[q][t - d] : 0;
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) sc[q][t] += v[q];
+    __syncthreads();
+  }
+  int run[4];
+  for (int q = 0; q < 4; ++q) run[q] = sc[q][t] - c[q];
+  for (int i = beg; i < end; ++i) {
+    const bool act = S[i].state == want;
+    for (int q = 0; q < 4; ++q) L.off[q * (n_inst + 1) + i] = run[q];
+    if (act) {
+      run[0] += I[i].a.n_s;
+      if (with_blocks) run[I[i].nt] += I[i].nblk;
+    }
+  }
+  if (t == BC_THR - 1)
+    for (int q = 0; q < 4; ++q) {
+      L.off[q * (n_inst + 1) + n_inst] = sc[q][t];
+      L.cnt[q] = sc[q][t];
+    }
+}
+
+// Point physics of every sampled element of the JAC instances.
+template <class D, class R>
+__global__ __launch_bounds__(NTHR_PTS) void k_points_batch(const BatchInst* I, BatchLists L, int n_inst) {
+  __shared__ ElemLDS<D, R> s;
+  const int total = L.cnt[0];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int inst = __builtin_amdgcn_readfirstlane(batch_owner(L.off, n_inst, item));
+    const int k = item - L.off[inst];
+    points_eq_body<D, R>(s, I[inst].a, k, 0, threadIdx.x);
+    __syncthreads();
+  }
+}
+
+// Fused assembly + Gram of the JAC instances with NT column tiles.
+template <class D, class R, int NT>
+__global__ __launch_bounds__(NTHR) void k_fused_batch(const BatchInst* I, BatchLists L, int n_inst, int E) {
+  __shared__ FusedShared<D, R, NT> sh;
+  fused_load_tab<D, R, NT>(sh, threadIdx.x);
+  const int* off = L.off + NT * (n_inst + 1);
+  const int total = L.cnt[NT];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int inst = __builtin_amdgcn_readfirstlane(batch_owner(off, n_inst, item));
+    const int blk = item - off[inst];
+    const BatchInst& bi = I[inst];
+    FusedArgs f;
+    f.E = E;
+    f.nblk = bi.nblk;
+    f.part = bi.part;
+    f.part_bad = bi.part_bad;
+    f.rows = 0;
+    fused_body<D, R, NT>(sh, bi.a, bi.Bw, bi.Bx, f, blk, 0);
+  }
+}
+
+// H, g, the objective and the flags of each JAC instance from its partials.
+__global__ __launch_bounds__(256) void k_final_batch(const BatchInst* I, BatchState* S) {
+  __shared__ double red[GF_GRP][GF_ENT];
+  const int inst = blockIdx.y;
+  if (S[inst].state != BS_JAC) return;
+  const BatchInst& bi = I[inst];
+  const int D1 = bi.a.D + 1;
+  const int nbe = (D1 * (D1 + 1) / 2 + GF_ENT - 1) / GF_ENT;
+  if ((int)blockIdx.x > nbe) return;
+  BatchState& st = S[inst];
+  fused_final_body(bi.part, bi.part_bad, bi.nblk, bi.nt, bi.a.D, bi.H, bi.g, &st.J, &st.n_bad, &st.flag_or,
+                   blockIdx.x, 0, red);
+}
+
+// Convergence test and LM step of each JAC instance (one wave each).
+__global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState* S, const BatchParams* P) {
+  __shared__ double L[64 * 64];
+  __shared__ double y[64];
+  __shared__ double out[4];
+  __shared__ int fail;
+  const int inst = blockIdx.x;
+  BatchState& st = S[inst];
+  if (st.state != BS_JAC) return;
+  const BatchInst& bi = I[inst];
+  const int D = bi.a.D, n = bi.a.n;
+  const BatchParams p = *P;
+  const double J = st.J;
+  if (!(J < __builtin_inf())) {   // invalid geometry or state at the iterate
+    if (threadIdx.x == 0) {
+      st.status = (st.flag_or & BAD_GEOM) ? IFT_EBADMESH : IFT_ENONPHYS;
+      st.state = BS_DONE;
+    }
+    return;
+  }
+  lm_solve_body(bi.H, bi.g, D, n, p.lambda, bi.dz, out, L, y, fail);
+  if (threadIdx.x == 0) {
+    if (st.it == 0) st.J0 = J;
+    st.nS = out[1];
+    st.nT = out[2];
+    if (out[1] <= p.tol && out[2] <= p.tol) {
+      st.converged = 1;
+      st.status = IFT_OK;
+      st.state = BS_DONE;
+    } else if (st.it >= p.max_it) {
+      st.status = IFT_ENOTCONV;
+      st.state = BS_DONE;
+    } else if (out[0] != 0.0) {
+      st.status = IFT_ESINGULAR;
+      st.state = BS_DONE;
+    } else {
+      st.slope = out[3];
+      st.alpha = 1.0;
+      st.n_bt = 0;
+      st.it += 1;
+      st.state = BS_SEARCH;
+    }
+  }
+}
+
+// Trial iterate z + alpha dz of each SEARCH instance.
+__global__ __launch_bounds__(64) void k_trial_batch(const BatchInst* I, const BatchState* S) {
+  const int inst = blockIdx.x;
+  if (S[inst].state != BS_SEARCH) return;
+  const BatchInst& bi = I[inst];
+  const double al = S[inst].alpha;
+  for (int i = threadIdx.x; i < bi.a.D; i += 64) bi.zt[i] = bi.z[i] + al * bi.dz[i];
+}
+
+// Residual and objective parts at the trial iterates (values only).
+template <class D, class R>
+__global__ __launch_bounds__(NTHR) void k_res_batch(const BatchInst* I, BatchLists L, int n_inst) {
+  __shared__ ElemLDS<D, R> s;
+  const int total = L.cnt[0];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int inst = __builtin_amdgcn_readfirstlane(batch_owner(L.off, n_inst, item));
+    const int k = item - L.off[inst];
+    EqArgs a = I[inst].a;
+    a.w = I[inst].zt;
+    a.tau = I[inst].zt + a.n;
+    a.Ft = nullptr;
+    a.PTR = nullptr;
+    eq_res_body<D, R>(s, a, k, 0, threadIdx.x);
+    __syncthreads();
+  }
+}
+
+// Objective at the trial iterate (fixed-order sum) and the Armijo test.
+__global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState* S, const BatchParams* P) {
+  __shared__ double sj[256];
+  __shared__ int so[256];
+  const int inst = blockIdx.x;
+  BatchState& st = S[inst];
+  if (st.state != BS_SEARCH) return;
+  const BatchInst& bi = I[inst];
+  const int t = threadIdx.x;
+  double v = 0.0;
+  int o = 0;
+  for (int k = t; k < bi.a.n_s; k += 256) {
+    v += bi.a.Jpart[k];
+    o |= bi.a.flags[k];
+  }
+  sj[t] = v;
+  so[t] = o;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (t < d) {
+      sj[t] += sj[t + d];
+      so[t] |= so[t + d];
+    }
+    __syncthreads();
+  }
+  // accept: copy the trial iterate (all lanes), then update the state
+  const BatchParams p = *P;
+  const double Jt = so[0] ? __builtin_inf() : sj[0];
+  const bool ok = Jt <= st.J + p.c1 * st.alpha * st.slope;
+  if (ok)
+    for (int i = t; i < bi.a.D; i += 256) bi.z[i] = bi.zt[i];
+  __syncthreads();
+  if (t == 0) {
+    st.Jtrial = Jt;
+    if (ok) {
+      st.alpha_acc = st.alpha;
+      st.n_bt_total += st.n_bt;
+      st.state = BS_JAC;
+    } else if (st.n_bt >= p.max_backtrack) {
+      st.n_bt += 1;
+      st.n_bt_total += st.n_bt;
+      st.status = IFT_ELINESEARCH;
+      st.state = BS_DONE;
+    } else {
+      st.alpha *= 0.5;
+      st.n_bt += 1;
+    }
+  }
+}
+
+// Number of instances that have not finished (one block, fixed order).
+__global__ __launch_bounds__(256) void k_batch_remaining(const BatchState* S, int n_inst, int* out) {
+  __shared__ int sc[256];
+  int c = 0;
+  for (int i = threadIdx.x; i < n_inst; i += 256) c += S[i].state != BS_DONE;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) sc[threadIdx.x] += sc[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sc[0];
+}
+
+// Fresh state for every instance.
+__global__ void k_batch_init(BatchState* S, int n_inst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  BatchState st;
+  st.state = BS_JAC;
+  st.it = 0;
+  st.n_bt = 0;
+  st.status = IFT_OK;
+  st.flag_or = 0;
+  st.n_bad = 0;
+  st.converged = 0;
+  st.n_bt_total = 0;
+  st.J = st.J0 = st.Jtrial = 0.0;
+  st.alpha = st.slope = st.nS = st.nT = st.alpha_acc = 0.0;
+  S[i] = st;
+}
+
+}  // namespace ift

@@ -11,6 +11,7 @@
 
 #include "../../include/ift.h"
 #include "kernels.hpp"
+#include "batch.hpp"
 
 namespace ift {
 __constant__ RefTab c_tab[2];
@@ -995,4 +996,369 @@ extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double
   info->n_backtrack = prm->max_backtrack + 1;
   info->status = IFT_ELINESEARCH;
   return IFT_ELINESEARCH;
+}
+
+// ============================================================ batched solves
+struct ift_batch {
+  ift_problem* prob = nullptr;
+  ift_precision precision = IFT_FP64;
+  int n_inst = 0;
+  std::vector<ift_rom*> roms;
+  std::vector<int> zoff, hoff, nsoff;   // packed offsets [n_inst + 1]
+  std::vector<BatchInst> h_inst;
+  long long sum_ns = 0;
+  int E = 8;                 // sampled elements per wave of the fused assembly
+  int nbe_max = 0;           // final-reduction workgroups of the widest instance
+  bool has_nt[FUSED_MAXNT + 1] = {};
+  BatchInst* d_inst = nullptr;
+  BatchState* d_state = nullptr;
+  BatchParams* d_params = nullptr;
+  int* d_off = nullptr;
+  int* d_cnt = nullptr;
+  double* d_z = nullptr;
+  double* d_zt = nullptr;
+  double* d_dz = nullptr;
+  double* d_H = nullptr;
+  double* d_g = nullptr;
+  double* d_mu = nullptr;
+  void* d_pts = nullptr;
+  double* d_Jpart = nullptr;
+  int* d_flags = nullptr;
+  double* d_part = nullptr;
+  int* d_pbad = nullptr;
+  size_t part_cap = 0, pbad_cap = 0;   // capacities (doubles, ints) for the smallest E
+  int* d_remaining = nullptr;
+  int* h_remaining = nullptr;          // pinned
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;       // BATCH_ROUNDS rounds
+};
+
+static constexpr int BATCH_E_CAND[] = {4, 8, 16, 32};
+static constexpr int BATCH_T = 2;           // line-search trials per round
+static constexpr int BATCH_ROUNDS = 4;      // rounds per graph replay (one completion check each)
+static constexpr int BATCH_GRID_PTS = 2048, BATCH_GRID_RES = 2048, BATCH_GRID_FUSED = 1024;
+
+static int batch_nblk(int n_s, int E) { return (n_s + 4 * E - 1) / (4 * E); }
+
+// Per-instance descriptors for the current E (fused partial slices depend on it).
+static ift_status batch_upload(ift_batch* b) {
+  const ift_problem* pr = b->prob;
+  const size_t pb = pts_bytes(pr);
+  size_t po = 0, bo = 0;
+  for (int i = 0; i < b->n_inst; ++i) {
+    ift_rom* r = b->roms[i];
+    const double mu0[2] = {1.0, 0.0};
+    BatchInst& bi = b->h_inst[i];
+    EqArgs a = eq_args(r, mu0, nullptr, nullptr);
+    a.w = b->d_z + b->zoff[i];
+    a.tau = b->d_z + b->zoff[i] + r->n;
+    a.mu = b->d_mu + 2 * i;
+    a.Jt = nullptr;
+    a.Ft = nullptr;
+    a.PTR = nullptr;
+    a.Jpart = b->d_Jpart + b->nsoff[i];
+    a.flags = b->d_flags + b->nsoff[i];
+    a.pts = static_cast<char*>(b->d_pts) + (size_t)b->nsoff[i] * pb;
+    bi.a = a;
+    bi.Bw = r->d_Bw;
+    bi.Bx = r->d_Bx;
+    bi.z = b->d_z + b->zoff[i];
+    bi.zt = b->d_zt + b->zoff[i];
+    bi.dz = b->d_dz + b->zoff[i];
+    bi.H = b->d_H + b->hoff[i];
+    bi.g = b->d_g + b->zoff[i];
+    bi.nt = r->fused_nt;
+    bi.nblk = batch_nblk(r->n_s, b->E);
+    bi.part = b->d_part + po;
+    bi.part_bad = b->d_pbad + bo;
+    po += (size_t)bi.nblk * (bi.nt * (bi.nt + 1) / 2) * 256;
+    bo += (size_t)bi.nblk * 2;
+  }
+  if (po > b->part_cap || bo > b->pbad_cap) return IFT_EINVAL;
+  HIP_TRY(hipMemcpy(b->d_inst, b->h_inst.data(), b->n_inst * sizeof(BatchInst), hipMemcpyHostToDevice));
+  return IFT_OK;
+}
+
+extern "C" void ift_batch_destroy(ift_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  dfree(b->d_remaining);
+  if (b->h_remaining) (void)hipHostFree(b->h_remaining);
+  dfree(b->d_inst);
+  dfree(b->d_state);
+  dfree(b->d_params);
+  dfree(b->d_off);
+  dfree(b->d_cnt);
+  dfree(b->d_z);
+  dfree(b->d_zt);
+  dfree(b->d_dz);
+  dfree(b->d_H);
+  dfree(b->d_g);
+  dfree(b->d_mu);
+  if (b->d_pts) (void)hipFree(b->d_pts);
+  dfree(b->d_Jpart);
+  dfree(b->d_flags);
+  dfree(b->d_part);
+  dfree(b->d_pbad);
+  delete b;
+}
+
+extern "C" ift_status ift_batch_create(int n_inst, ift_rom* const* roms, ift_batch** out) {
+  if (!out || !roms || n_inst < 1) return IFT_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < n_inst; ++i) {
+    if (!roms[i] || roms[i]->prob != roms[0]->prob || roms[i]->precision != roms[0]->precision) return IFT_EINVAL;
+    if (roms[i]->fused_nt < 1) return IFT_EINVAL;
+  }
+  ift_batch* b = new ift_batch;
+  b->prob = roms[0]->prob;
+  b->precision = roms[0]->precision;
+  b->n_inst = n_inst;
+  b->roms.assign(roms, roms + n_inst);
+  b->zoff.assign(n_inst + 1, 0);
+  b->hoff.assign(n_inst + 1, 0);
+  b->nsoff.assign(n_inst + 1, 0);
+  size_t part_max = 0, pbad_max = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const ift_rom* r = roms[i];
+    b->zoff[i + 1] = b->zoff[i] + r->D;
+    b->hoff[i + 1] = b->hoff[i] + r->D * r->D;
+    b->nsoff[i + 1] = b->nsoff[i] + r->n_s;
+    const int D1 = r->D + 1;
+    b->nbe_max = std::max(b->nbe_max, (D1 * (D1 + 1) / 2 + GF_ENT - 1) / GF_ENT);
+    b->has_nt[r->fused_nt] = true;
+    const int nb = batch_nblk(r->n_s, BATCH_E_CAND[0]);
+    part_max += (size_t)nb * (r->fused_nt * (r->fused_nt + 1) / 2) * 256;
+    pbad_max += (size_t)nb * 2;
+  }
+  b->sum_ns = b->nsoff[n_inst];
+  b->h_inst.resize(n_inst);
+  const size_t Z = b->zoff[n_inst], HH = b->hoff[n_inst], NS = b->sum_ns;
+  ift_status st;
+  if ((st = dalloc(&b->d_inst, n_inst)) != IFT_OK || (st = dalloc(&b->d_state, n_inst)) != IFT_OK ||
+      (st = dalloc(&b->d_params, 1)) != IFT_OK || (st = dalloc(&b->d_off, 4 * (size_t)(n_inst + 1))) != IFT_OK ||
+      (st = dalloc(&b->d_cnt, 4)) != IFT_OK || (st = dalloc(&b->d_z, Z)) != IFT_OK ||
+      (st = dalloc(&b->d_zt, Z)) != IFT_OK || (st = dalloc(&b->d_dz, Z)) != IFT_OK ||
+      (st = dalloc(&b->d_H, HH)) != IFT_OK || (st = dalloc(&b->d_g, Z)) != IFT_OK ||
+      (st = dalloc(&b->d_mu, 2 * (size_t)n_inst)) != IFT_OK || (st = dalloc(&b->d_Jpart, NS)) != IFT_OK ||
+      (st = dalloc(&b->d_flags, NS)) != IFT_OK || (st = dalloc(&b->d_part, part_max)) != IFT_OK ||
+      (st = dalloc(&b->d_pbad, pbad_max)) != IFT_OK) {
+    ift_batch_destroy(b);
+    return st;
+  }
+  b->part_cap = part_max;
+  b->pbad_cap = pbad_max;
+  if (hipMalloc(&b->d_pts, NS * pts_bytes(b->prob)) != hipSuccess) {
+    ift_batch_destroy(b);
+    return IFT_ENOMEM;
+  }
+  if (dalloc(&b->d_remaining, 1) != IFT_OK ||
+      hipHostMalloc((void**)&b->h_remaining, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      (st = batch_upload(b)) != IFT_OK) {
+    ift_batch_destroy(b);
+    return st == IFT_OK ? IFT_EDEVICE : st;
+  }
+  *out = b;
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_batch_layout(const ift_batch* b, int* zoff, int* hoff) {
+  if (!b) return IFT_EINVAL;
+  if (zoff) std::memcpy(zoff, b->zoff.data(), (b->n_inst + 1) * sizeof(int));
+  if (hoff) std::memcpy(hoff, b->hoff.data(), (b->n_inst + 1) * sizeof(int));
+  return IFT_OK;
+}
+
+// Kernels of one phase for the batch's discretisation and precision.
+template <class R>
+struct BatchLaunch {
+  ift_batch* b;
+  hipStream_t st;
+  int phase;   // 0: Jacobian assembly of the JAC instances, 1: trial residuals of the SEARCH instances
+  template <class D, int NT>
+  void fused(const BatchLists& L) {
+    if (b->has_nt[NT])
+      hipLaunchKernelGGL((k_fused_batch<D, R, NT>), dim3(BATCH_GRID_FUSED), dim3(NTHR), 0, st,
+                         (const BatchInst*)b->d_inst, L, b->n_inst, b->E);
+  }
+  template <class D>
+  void run() {
+    BatchLists L{b->d_off, b->d_cnt};
+    const int ni = b->n_inst;
+    if (phase == 0) {
+      hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
+                         (const BatchState*)b->d_state, L, ni, (int)BS_JAC, 1);
+      hipLaunchKernelGGL((k_points_batch<D, R>), dim3(BATCH_GRID_PTS), dim3(NTHR_PTS), 0, st,
+                         (const BatchInst*)b->d_inst, L, ni);
+      fused<D, 1>(L);
+      fused<D, 2>(L);
+      fused<D, 3>(L);
+      hipLaunchKernelGGL(k_final_batch, dim3(b->nbe_max + 1, ni), dim3(256), 0, st, (const BatchInst*)b->d_inst,
+                         b->d_state);
+    } else {
+      hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
+                         (const BatchState*)b->d_state, L, ni, (int)BS_SEARCH, 0);
+      hipLaunchKernelGGL(k_trial_batch, dim3(ni), dim3(64), 0, st, (const BatchInst*)b->d_inst,
+                         (const BatchState*)b->d_state);
+      hipLaunchKernelGGL((k_res_batch<D, R>), dim3(BATCH_GRID_RES), dim3(NTHR), 0, st, (const BatchInst*)b->d_inst,
+                         L, ni);
+      hipLaunchKernelGGL(k_ls_batch, dim3(ni), dim3(256), 0, st, (const BatchInst*)b->d_inst, b->d_state,
+                         (const BatchParams*)b->d_params);
+    }
+  }
+};
+
+static void batch_phase(ift_batch* b, int phase, hipStream_t st) {
+  if (b->precision == IFT_FP32_ELEM) with_disc(b->prob, BatchLaunch<float>{b, st, phase});
+  else with_disc(b->prob, BatchLaunch<double>{b, st, phase});
+}
+
+// `rounds` rounds of the solve: the Jacobian phase of the JAC instances,
+// their LM step (or stop), then BATCH_T line-search trials of the SEARCH
+// instances.  An instance still backtracking continues in the next round.
+static void batch_rounds(ift_batch* b, int rounds, hipStream_t st) {
+  for (int r = 0; r < rounds; ++r) {
+    batch_phase(b, 0, st);
+    hipLaunchKernelGGL(k_lm_batch, dim3(b->n_inst), dim3(64), 0, st, (const BatchInst*)b->d_inst, b->d_state,
+                       (const BatchParams*)b->d_params);
+    for (int t = 0; t < BATCH_T; ++t) batch_phase(b, 1, st);
+  }
+}
+
+__global__ void k_batch_info(const BatchState* S, int n_inst, ift_gn_info* info) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  const BatchState st = S[i];
+  ift_gn_info o;
+  o.J_old = st.J0;
+  o.J_new = st.J;
+  o.alpha = st.alpha_acc;
+  o.norm_S = st.nS;
+  o.norm_T = st.nT;
+  o.n_backtrack = st.n_bt_total;
+  o.converged = st.converged;
+  o.status = st.state == BS_DONE ? st.status : IFT_ENOTCONV;   // (round cap reached; not expected)
+  o.iterations = st.it;
+  info[i] = o;
+}
+
+static ift_status batch_inputs(ift_batch* b, const double* mu, const double* z, hipStream_t stream) {
+  HIP_TRY(hipMemcpyAsync(b->d_mu, mu, 2 * (size_t)b->n_inst * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(b->d_z, z, (size_t)b->zoff[b->n_inst] * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return IFT_OK;
+}
+
+extern "C" ift_status eq_assemble_jacobian_batched(ift_batch* b, const double* mu, const double* z, double* Jobj,
+                                                   double* g, double* H, int* n_bad, hipStream_t stream) {
+  if (!b || !mu || !z || !Jobj || !g || !H) return IFT_EINVAL;
+  ift_status s = batch_inputs(b, mu, z, stream);
+  if (s != IFT_OK) return s;
+  hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst);
+  {
+    ProfScope ps(IFT_PROF_EQ_JAC, stream);
+    batch_phase(b, 0, stream);
+  }
+  HIP_TRY(hipGetLastError());
+  const size_t Z = b->zoff[b->n_inst], HH = b->hoff[b->n_inst];
+  HIP_TRY(hipMemcpyAsync(g, b->d_g, Z * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(H, b->d_H, HH * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpy2DAsync(Jobj, sizeof(double), &b->d_state->J, sizeof(BatchState), sizeof(double), b->n_inst,
+                           hipMemcpyDeviceToDevice, stream));
+  if (n_bad)
+    HIP_TRY(hipMemcpy2DAsync(n_bad, sizeof(int), &b->d_state->n_bad, sizeof(BatchState), sizeof(int), b->n_inst,
+                             hipMemcpyDeviceToDevice, stream));
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_batch_autotune(ift_batch* b, const double* mu, const double* z, int* chosen,
+                                         hipStream_t stream) {
+  if (!b || !mu || !z) return IFT_EINVAL;
+  ift_status s = batch_inputs(b, mu, z, stream);
+  if (s != IFT_OK) return s;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = 0.f;
+  int bestE = b->E;
+  for (int E : BATCH_E_CAND) {
+    b->E = E;
+    if ((s = batch_upload(b)) != IFT_OK) break;
+    float tot = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst);
+      HIP_TRY(hipEventRecord(e0, stream));
+      batch_phase(b, 0, stream);
+      HIP_TRY(hipEventRecord(e1, stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tot += ms;   // the first run warms up
+    }
+    if (bestE == -1 || best == 0.f || tot < best) {
+      best = tot;
+      bestE = E;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->E = bestE;
+  if (s == IFT_OK) s = batch_upload(b);
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  if (chosen) *chosen = b->E;
+  return s;
+}
+
+extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double* mu, double* z,
+                                                     const ift_gn_params* prm, int max_it, ift_gn_info* info,
+                                                     int flags, hipStream_t stream) {
+  if (!b || !mu || !z || !prm || !info || max_it < 0) return IFT_EINVAL;
+  if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
+    return IFT_EINVAL;
+  BatchParams bp{prm->lambda, prm->c1, prm->tol, prm->max_backtrack, max_it};
+  HIP_TRY(hipMemcpyAsync(b->d_params, &bp, sizeof(bp), hipMemcpyHostToDevice, stream));
+  ift_status s = batch_inputs(b, mu, z, stream);
+  if (s != IFT_OK) return s;
+  const bool graph = !(flags & 1);
+  if (graph && !b->exec) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    batch_rounds(b, BATCH_ROUNDS, b->cap_stream);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+    if (le != hipSuccess || ce != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      return IFT_EDEVICE;
+    }
+    const hipError_t ie = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      b->exec = nullptr;
+      return IFT_EDEVICE;
+    }
+  }
+  hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst);
+  // every instance finishes within (max_it + 1) Jacobian rounds, each
+  // followed by at most ceil((max_backtrack + 1) / T) rounds of trials
+  const long long cap = (long long)(max_it + 1) * (2 + (prm->max_backtrack + 1 + BATCH_T - 1) / BATCH_T);
+  for (long long done = 0; done < cap; done += BATCH_ROUNDS) {
+    if (graph) HIP_TRY(hipGraphLaunch(b->exec, stream));
+    else batch_rounds(b, BATCH_ROUNDS, stream);
+    hipLaunchKernelGGL(k_batch_remaining, dim3(1), dim3(256), 0, stream, (const BatchState*)b->d_state, b->n_inst,
+                       b->d_remaining);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(b->h_remaining, b->d_remaining, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    if (*b->h_remaining == 0) break;
+  }
+  HIP_TRY(hipMemcpyAsync(z, b->d_z, (size_t)b->zoff[b->n_inst] * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  hipLaunchKernelGGL(k_batch_info, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, (const BatchState*)b->d_state,
+                     b->n_inst, info);
+  HIP_TRY(hipGetLastError());
+  return IFT_OK;
 }

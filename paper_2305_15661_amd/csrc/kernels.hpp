@@ -179,12 +179,9 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
   copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + e, &s.p, tid, NTHR_PTS);
 }
 
+// Point data of sampled element k at evaluation point pt (one block).
 template <class D, class R>
-__global__ __launch_bounds__(NTHR_PTS) void k_points_eq(EqArgs a) {
-  __shared__ ElemLDS<D, R> s;
-  const int k = blockIdx.x, pt = blockIdx.y;
-  if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
-  const int tid = threadIdx.x;
+IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R>(s, tid, NTHR_PTS);
   load_eq<D, R>(s, a, k, pt, tid, NTHR_PTS);
   __syncthreads();
@@ -193,6 +190,14 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_eq(EqArgs a) {
   phase_points<D, R, true>(s, tid, pc, R(a.kappa), R(a.eps));
   __syncthreads();
   copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s.p, tid, NTHR_PTS);
+}
+
+template <class D, class R>
+__global__ __launch_bounds__(NTHR_PTS) void k_points_eq(EqArgs a) {
+  __shared__ ElemLDS<D, R> s;
+  const int k = blockIdx.x, pt = blockIdx.y;
+  if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
+  points_eq_body<D, R>(s, a, k, pt, threadIdx.x);
 }
 
 // ------------------------------------------------ full-order assembly
@@ -227,13 +232,10 @@ __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
 }
 
 // ------------------------------------------------------------- EQ kernels
-// Residual and objective parts at one evaluation point (values only).
+// Residual and objective parts of sampled element k at evaluation point pt
+// (values only, one block).
 template <class D, class R>
-__global__ __launch_bounds__(NTHR) void k_eq_res(EqArgs a) {
-  __shared__ ElemLDS<D, R> s;
-  const int k = blockIdx.x, pt = blockIdx.y;
-  if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
-  const int tid = threadIdx.x;
+IFT_DEV void eq_res_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R>(s, tid, NTHR);
   load_eq<D, R>(s, a, k, pt, tid, NTHR);
   __syncthreads();
@@ -260,6 +262,14 @@ __global__ __launch_bounds__(NTHR) void k_eq_res(EqArgs a) {
       a.PTR[((long long)pt * a.n_s + k) * a.n + j] = a.rho[k] * acc;
     }
   }
+}
+
+template <class D, class R>
+__global__ __launch_bounds__(NTHR) void k_eq_res(EqArgs a) {
+  __shared__ ElemLDS<D, R> s;
+  const int k = blockIdx.x, pt = blockIdx.y;
+  if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
+  eq_res_body<D, R>(s, a, k, pt, threadIdx.x);
 }
 
 // ------------------------------------------------------------------------
@@ -556,28 +566,42 @@ IFT_DEV void copy_pts_wave(Pts<D, R>* dst, const Pts<D, R>* src, int lane) {
   }
 }
 
+// LDS of the fused kernel: the reference table, one point-data slot per
+// wave (reused for the cross-wave reduction) and the flag counts.
 template <class D, class R, int NT>
-__global__ __launch_bounds__(NTHR) void k_eq_fused(EqArgs a, const double* Bw, const double* Bx, FusedArgs f) {
+struct FusedShared {
+  RefTab tab;
+  union {
+    FusedSlot<D, R> w[NTHR / 64];
+    double red[NTHR / 64 - 1][256];
+  } u;
+  int sbad[NTHR / 64][2];
+};
+
+template <class D, class R, int NT>
+IFT_DEV void fused_load_tab(FusedShared<D, R, NT>& sh, int tid) {
+  const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
+  int* dst = reinterpret_cast<int*>(&sh.tab);
+  for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
+}
+
+// One block of the fused assembly: sampled elements [4E blk, 4E (blk + 1))
+// at evaluation point pt; writes the block's partial.  The table must be
+// loaded; the first barrier inside makes it visible.
+template <class D, class R, int NT>
+IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double* Bw, const double* Bx,
+                        const FusedArgs& f, int blk, int pt) {
   using O = EqOp<D>;
   constexpr int NUE = D::NUE;
   constexpr int MT = (NUE + 1 + 15) / 16;           // row tiles (element rows + distortion row)
   constexpr int NH = NT * (NT + 1) / 2;             // upper tiles of the Gram
   constexpr int RD_MT = NUE / 16, RD_K = (NUE % 16) % 4, RD_V = (NUE % 16) / 4;  // distortion row
-  __shared__ RefTab tab;
-  __shared__ union {
-    FusedSlot<D, R> w[NTHR / 64];
-    double red[NTHR / 64 - 1][256];
-  } u;
-  __shared__ int sbad[NTHR / 64][2];
+  const RefTab& tab = sh.tab;
+  auto& u = sh.u;
+  auto& sbad = sh.sbad;
   const int n = a.n, m = a.m, Dd = a.D;
-  const int blk = blockIdx.x, pt = blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int kl = lane >> 4, li = lane & 15;
-  {
-    const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
-    int* dst = reinterpret_cast<int*>(&tab);
-    for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
-  }
   dvec4 h[NH];
 #pragma unroll
   for (int t = 0; t < NH; ++t) h[t] = dvec4{0.0, 0.0, 0.0, 0.0};
@@ -795,21 +819,26 @@ __global__ __launch_bounds__(NTHR) void k_eq_fused(EqArgs a, const double* Bw, c
   }
 }
 
+template <class D, class R, int NT>
+__global__ __launch_bounds__(NTHR) void k_eq_fused(EqArgs a, const double* Bw, const double* Bx, FusedArgs f) {
+  __shared__ FusedShared<D, R, NT> sh;
+  fused_load_tab<D, R, NT>(sh, threadIdx.x);
+  fused_body<D, R, NT>(sh, a, Bw, Bx, f, blockIdx.x, blockIdx.y);
+}
+
 // Sum of the block partials: workgroup x reduces 16 upper entries of the
 // augmented Gram (H, g and the objective); its 16 thread groups take the
 // blocks q, q + 16, ... and are then added in group order (fixed order).
 // The extra last workgroup reduces the invalid flags.
-__global__ __launch_bounds__(256) void k_fused_final(const double* part, const int* part_bad, int nblk, int NT, int D,
-                                                     double* H, double* g, double* Jobj, int* n_bad, int* flag_or) {
-  __shared__ double red[GF_GRP][GF_ENT];
-  const int pt = blockIdx.y;
+IFT_DEV void fused_final_body(const double* part, const int* part_bad, int nblk, int NT, int D, double* H, double* g,
+                              double* Jobj, int* n_bad, int* flag_or, int bx, int pt, double (*red)[GF_ENT]) {
   const int tid = threadIdx.x;
   const int NH = NT * (NT + 1) / 2;
   const int D1 = D + 1;
   const int nent = D1 * (D1 + 1) / 2;
   const int nbe = (nent + GF_ENT - 1) / GF_ENT;
   const int* pb = part_bad + (long long)pt * nblk * 2;
-  if ((int)blockIdx.x == nbe) {
+  if (bx == nbe) {
     if (tid == 0) {
       int c = 0, o = 0;
       for (int b = 0; b < nblk; ++b) {
@@ -822,7 +851,7 @@ __global__ __launch_bounds__(256) void k_fused_final(const double* part, const i
     return;
   }
   const int el = tid % GF_ENT, q = tid / GF_ENT;
-  const int e = blockIdx.x * GF_ENT + el;
+  const int e = bx * GF_ENT + el;
   // e -> (i, j), i <= j <= D, row-major over the upper triangle
   int i = 0, rem = e < nent ? e : 0;
   while (rem >= D1 - i) {
@@ -852,6 +881,12 @@ __global__ __launch_bounds__(256) void k_fused_final(const double* part, const i
     for (int b = 0; b < nblk; ++b) o |= pb[2 * b + 1];
     Jobj[pt] = o ? __builtin_inf() : 0.5 * v;
   }
+}
+
+__global__ __launch_bounds__(256) void k_fused_final(const double* part, const int* part_bad, int nblk, int NT, int D,
+                                                     double* H, double* g, double* Jobj, int* n_bad, int* flag_or) {
+  __shared__ double red[GF_GRP][GF_ENT];
+  fused_final_body(part, part_bad, nblk, NT, D, H, g, Jobj, n_bad, flag_or, blockIdx.x, blockIdx.y, red);
 }
 
 // ------------------------------------------------- Gram and objective
@@ -1093,11 +1128,10 @@ __global__ void k_gather_rows(const double* src, int ncol, const long long* rows
 // Solves (H + lambda diag(0_n, I_m)) dz = -g by Cholesky on one wavefront;
 // also returns |g_w|, |g_tau|, g.dz.  out: [0] status (0 ok, 1 not SPD),
 // [1] |S~|, [2] |T~|, [3] slope.
-__global__ __launch_bounds__(64) void k_lm_solve(const double* H, const double* g, int D, int n, double lambda,
-                                                 double* dz, double* out) {
-  __shared__ double L[64 * 64];
-  __shared__ double y[64];
-  __shared__ int fail;
+// (H + lambda diag(0_n, I_m)) dz = -g by Cholesky in one wave (D <= 64);
+// out = {failed, |S~|, |T~|, g . dz}.  L holds 64 x 64 doubles of LDS.
+IFT_DEV void lm_solve_body(const double* H, const double* g, int D, int n, double lambda, double* dz, double* out,
+                           double* L, double* y, int& fail) {
   const int t = threadIdx.x;
   for (int i = t; i < D * D; i += 64) {
     const int r = i / D, c = i % D;
@@ -1145,6 +1179,15 @@ __global__ __launch_bounds__(64) void k_lm_solve(const double* H, const double* 
     out[2] = sqrt(nT);
     out[3] = sl;
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_lm_solve(const double* H, const double* g, int D, int n, double lambda,
+                                                 double* dz, double* out) {
+  __shared__ double L[64 * 64];
+  __shared__ double y[64];
+  __shared__ int fail;
+  lm_solve_body(H, g, D, n, lambda, dz, out, L, y, fail);
 }
 
 __global__ void k_axpy2(const double* w, const double* tau, const double* dz, double alpha, int n, int m,

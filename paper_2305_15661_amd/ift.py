@@ -46,7 +46,7 @@ class GNParams(ctypes.Structure):
 class GNInfo(ctypes.Structure):
     _fields_ = [("J_old", ctypes.c_double), ("J_new", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("norm_S", ctypes.c_double), ("norm_T", ctypes.c_double), ("n_backtrack", ctypes.c_int),
-                ("converged", ctypes.c_int), ("status", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("status", ctypes.c_int), ("iterations", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,6 +71,13 @@ EXPORTS = {
     "ift_rom_reserve": (ctypes.c_int, [_P, ctypes.c_int]),
     "eq_assemble_residual_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
     "eq_assemble_jacobian_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "ift_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    "ift_batch_destroy": (None, [_P]),
+    "ift_batch_layout": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ift_batch_autotune": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int), _P]),
+    "eq_assemble_jacobian_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "rom_gauss_newton_solve_batched": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(GNParams), ctypes.c_int, _P,
+                                                      ctypes.c_int, _P]),
     "ift_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "ift_profile_reset": (ctypes.c_int, []),
     "ift_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
@@ -183,6 +190,8 @@ class ROM:
         self.D = self.n + self.m
         el = np.ascontiguousarray(eq_elem, dtype=np.int32)
         rho = np.ascontiguousarray(eq_rho, dtype=np.float64)
+        if rho.size != el.size:
+            raise ValueError(f"{el.size} EQ elements but {rho.size} weights")
         self.n_s = int(el.size)
         h = _P()
         st = lib().ift_rom_create(prob.handle, self.n, self.m, _ptr(Phi, prob.N_u * self.n, torch.float64),
@@ -263,6 +272,88 @@ class ROM:
         return st, info.as_dict()
 
 
+# numpy view of a device array of ift_gn_info records
+GN_INFO_DTYPE = np.dtype([("J_old", "<f8"), ("J_new", "<f8"), ("alpha", "<f8"), ("norm_S", "<f8"),
+                          ("norm_T", "<f8"), ("n_backtrack", "<i4"), ("converged", "<i4"), ("status", "<i4"),
+                          ("iterations", "<i4")])
+assert GN_INFO_DTYPE.itemsize == ctypes.sizeof(GNInfo)
+
+
+class Batch:
+    """Many ROM instances solved together (ift_batch_*).  The ROM objects
+    must stay alive as long as the batch."""
+
+    def __init__(self, roms):
+        self.roms = list(roms)
+        self.n_inst = len(self.roms)
+        arr = (_P * self.n_inst)(*[r.handle for r in self.roms])
+        h = _P()
+        _check(lib().ift_batch_create(self.n_inst, arr, ctypes.byref(h)), "ift_batch_create")
+        self.handle = h
+        zo = (ctypes.c_int * (self.n_inst + 1))()
+        ho = (ctypes.c_int * (self.n_inst + 1))()
+        _check(lib().ift_batch_layout(h, zo, ho), "ift_batch_layout")
+        self.zoff = np.array(zo[:], dtype=np.int64)
+        self.hoff = np.array(ho[:], dtype=np.int64)
+        self.nz = int(self.zoff[-1])
+        self.nh = int(self.hoff[-1])
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.ift_batch_destroy(h)
+            self.handle = None
+
+    def pack(self, zs, device=None):
+        """Packed device vector from a list of per-instance coordinate vectors."""
+        import torch
+        return torch.tensor(np.concatenate([np.asarray(z, dtype=np.float64) for z in zs]), dtype=torch.float64,
+                            device=device or "cuda")
+
+    def unpack(self, z):
+        zz = z.detach().cpu().numpy() if hasattr(z, "detach") else np.asarray(z)
+        return [zz[self.zoff[i]:self.zoff[i + 1]] for i in range(self.n_inst)]
+
+    def autotune(self, mu, z, stream=None) -> int:
+        import torch
+        f64 = torch.float64
+        c = ctypes.c_int()
+        _check(lib().ift_batch_autotune(self.handle, _ptr(mu, 2 * self.n_inst, f64), _ptr(z, self.nz, f64),
+                                        ctypes.byref(c), _stream(stream)), "ift_batch_autotune")
+        return c.value
+
+    def eq_assemble_jacobian(self, mu, z, Jobj, g, H, n_bad=None, stream=None):
+        import torch
+        f64 = torch.float64
+        st = lib().eq_assemble_jacobian_batched(self.handle, _ptr(mu, 2 * self.n_inst, f64), _ptr(z, self.nz, f64),
+                                                _ptr(Jobj, self.n_inst, f64), _ptr(g, self.nz, f64),
+                                                _ptr(H, self.nh, f64), _ptr(n_bad, self.n_inst, torch.int32),
+                                                _stream(stream))
+        _check(st, "eq_assemble_jacobian_batched")
+
+    def solve(self, mu, z, info, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, max_it=50, graph=True,
+              stream=None):
+        """rom_gauss_newton_solve_batched; info: device uint8 tensor of
+        n_inst * GN_INFO_DTYPE.itemsize bytes (see info_array)."""
+        import torch
+        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol))
+        if info.numel() * info.element_size() != self.n_inst * GN_INFO_DTYPE.itemsize:
+            raise ValueError("info has the wrong size")
+        st = lib().rom_gauss_newton_solve_batched(self.handle, _ptr(mu, 2 * self.n_inst, torch.float64),
+                                                  _ptr(z, self.nz, torch.float64), ctypes.byref(prm), int(max_it),
+                                                  ctypes.c_void_p(info.data_ptr()), 0 if graph else 1,
+                                                  _stream(stream))
+        _check(st, "rom_gauss_newton_solve_batched")
+
+    def info_buffer(self, device=None):
+        import torch
+        return torch.zeros(self.n_inst * GN_INFO_DTYPE.itemsize, dtype=torch.uint8, device=device or "cuda")
+
+    @staticmethod
+    def info_array(buf):
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=GN_INFO_DTYPE)
+
+
 def profile_enable(on: bool = True):
     _check(lib().ift_profile_enable(int(bool(on))), "ift_profile_enable")
 
@@ -285,6 +376,14 @@ def hdm_assemble(prob: Problem, *a, **k):
 
 def eq_assemble_residual(rom: ROM, *a, **k):
     return rom.eq_assemble_residual(*a, **k)
+
+
+def rom_gauss_newton_solve_batched(batch: Batch, *a, **k):
+    return batch.solve(*a, **k)
+
+
+def eq_assemble_jacobian_batched(batch: Batch, *a, **k):
+    return batch.eq_assemble_jacobian(*a, **k)
 
 
 def eq_assemble_jacobian(rom: ROM, *a, **k):

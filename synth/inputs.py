@@ -238,3 +238,73 @@ def with_eq(wl: Workload, eq_elem: np.ndarray, eq_rho: np.ndarray) -> Workload:
     out.eq_elem = np.asarray(eq_elem, dtype=np.int32)
     out.eq_rho = np.asarray(eq_rho, dtype=np.float64)
     return out
+
+
+def inflow_elements(mesh: Mesh) -> np.ndarray:
+    """Elements with a face on the inflow boundary (tag 1, x = 0)."""
+    return np.nonzero((mesh.elem_nbr == -1).any(axis=1))[0].astype(np.int32)
+
+
+def eq_set_with_inflow(mesh: Mesh, n_random: int, rng: np.random.Generator) -> np.ndarray:
+    """Sorted EQ element set: n_random elements drawn without replacement,
+    joined with every inflow-boundary element.  Near a uniform state a
+    uniform change of the state is seen only by inflow elements, so a
+    sampled set without them leaves the constant directions of the reduced
+    basis undetermined; any trained EQ rule contains such elements."""
+    inflow = inflow_elements(mesh)
+    rest = np.setdiff1d(np.arange(mesh.n_elem), inflow)
+    pick = rng.choice(rest, size=min(n_random, rest.size), replace=False)
+    return np.sort(np.concatenate([inflow, pick])).astype(np.int32)
+
+
+@dataclass
+class BatchWorkload:
+    """Many ROM instances on one mesh: a pool of bases and, per instance,
+    the pool index, its EQ set and weights, and mu = (Mach, angle in deg)."""
+    mesh: Mesh
+    pool: list            # [(Phi, Psi)] bases of the pool ROMs
+    pool_nm: list         # [(n, m)]
+    inst_pool: np.ndarray
+    inst_elem: list
+    inst_rho: list
+    mus: np.ndarray       # [n_inst, 2]
+    base: Workload        # the workload whose mesh and constants the pool shares
+
+
+def euler_batch(n_inst: int = 1024, nx: int = 128, ny: int = 64, ns_lo: int = 200, ns_hi: int = 2000,
+                ns_list=None) -> BatchWorkload:
+    """Batched instances of the P2 Euler workload: pool of 6 ROMs with
+    n in {10, 20, 30} x m in {5, 10} (pool entry p built like the single
+    workload with basis seed 1001 + p), mu from a scrambled Sobol sequence
+    (seed 1005) on [2, 3] x [-5, 5] degrees, pool index per instance
+    uniform (seed 1008), EQ set sizes U{ns_lo..ns_hi} (or ns_list) drawn
+    (seed 1009) with the inflow elements added, weights lognormal(0, 0.5)."""
+    from scipy.stats import qmc
+    pool_nm = [(n, m) for n in (10, 20, 30) for m in (5, 10)]
+    base = euler_p2(nx=nx, ny=ny, n=30, m=10, n_s=1, n_eval=1)
+    mesh = base.mesh
+    U_ref = base.extra["U_ref"]
+    pool = []
+    for p, (n, m) in enumerate(pool_nm):
+        N_u = U_ref.shape[0]
+        cols = []
+        for c in range(4):
+            e = np.zeros(N_u)
+            e[c::4] = 1.0
+            cols.append(e)
+        cols.append(U_ref)
+        rng = np.random.default_rng(1001 + p)
+        for _ in range(max(0, n - 5)):
+            cols.append(smooth_field(mesh, rng, 4))
+        pool.append((orthonormal_columns(np.stack(cols[:n], axis=1)), psi_euler(mesh, m)))
+    sob = qmc.Sobol(d=2, scramble=True, seed=1005).random(n_inst)
+    mus = np.stack([2.0 + sob[:, 0], -5.0 + 10.0 * sob[:, 1]], axis=1)
+    inst_pool = np.random.default_rng(1008).integers(0, len(pool), n_inst)
+    rng = np.random.default_rng(1009)
+    sizes = (np.asarray(ns_list) if ns_list is not None else rng.integers(ns_lo, ns_hi + 1, n_inst))
+    inst_elem, inst_rho = [], []
+    for i in range(n_inst):
+        el = eq_set_with_inflow(mesh, int(sizes[i % len(sizes)]), rng)
+        inst_elem.append(el)
+        inst_rho.append(rng.lognormal(0.0, 0.5, size=el.size))
+    return BatchWorkload(mesh, pool, pool_nm, inst_pool, inst_elem, inst_rho, mus, base)

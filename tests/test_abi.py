@@ -79,3 +79,19 @@ def test_null_handles_rejected():
     assert L.ift_rom_get_gathers(None, None, None, None, None, None) == ift.IFT_EINVAL
     L.ift_problem_destroy(None)
     L.ift_rom_destroy(None)
+
+
+def test_batch_arguments_rejected():
+    ift, L = _lib()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_void_p * 2)(None, None)
+    assert L.ift_batch_create(0, arr, ctypes.byref(h)) == ift.IFT_EINVAL
+    assert L.ift_batch_create(2, arr, ctypes.byref(h)) == ift.IFT_EINVAL
+    assert L.ift_batch_create(1, None, ctypes.byref(h)) == ift.IFT_EINVAL
+    assert not h.value
+    assert L.ift_batch_layout(None, None, None) == ift.IFT_EINVAL
+    assert L.ift_batch_autotune(None, None, None, None, None) == ift.IFT_EINVAL
+    assert L.eq_assemble_jacobian_batched(None, None, None, None, None, None, None, None) == ift.IFT_EINVAL
+    prm = ift.GNParams(0.0, 1e-4, 30, 1e-8)
+    assert L.rom_gauss_newton_solve_batched(None, None, None, ctypes.byref(prm), 10, None, 0, None) == ift.IFT_EINVAL
+    L.ift_batch_destroy(None)
