@@ -98,6 +98,97 @@ def cpu_baseline(wl, budget_s: float):
                       f"(same 16384-element Euler P2 workload), {dt:.1f} s, one thread"}
 
 
+BATCH_LAMBDA = 1e-10   # Levenberg-Marquardt weight on the mapping block
+BATCH_MAX_IT = 50
+
+
+def batched_leg(n_inst: int, n_loop: int, dev):
+    """Batched solves of many instances (pool of 6 bases with n in
+    {10, 20, 30}, m in {5, 10}; EQ sets of U{200..2000} elements plus the
+    inflow elements; mu = (Mach, angle) from a scrambled Sobol sequence on
+    [2, 3] x [-5, 5] degrees), all from the plain start, versus a loop of
+    rom_gauss_newton_step over the first n_loop instances."""
+    import torch
+    import synth
+    from paper_2305_15661_amd import ift
+    t0 = time.perf_counter()
+    bw = synth.euler_batch(n_inst=n_inst)
+    prob = ift.Problem.from_workload(bw.base)
+    pool = [(torch.tensor(np.ascontiguousarray(P), device=dev), torch.tensor(np.ascontiguousarray(S), device=dev))
+            for P, S in bw.pool]
+    roms = [ift.ROM(prob, *pool[bw.inst_pool[i]], bw.inst_elem[i], bw.inst_rho[i]) for i in range(n_inst)]
+    b = ift.Batch(roms)
+    torch.cuda.synchronize()
+    log(f"batched leg: setup {time.perf_counter() - t0:.1f} s")
+    ns = int(sum(e.size for e in bw.inst_elem))
+    mu = torch.tensor(bw.mus, dtype=torch.float64, device=dev)
+    z0 = torch.zeros(b.nz, dtype=torch.float64, device=dev)
+    b.plain_start(mu, z0)
+    E = b.autotune(mu, z0)
+    # Jacobian assembly over the whole batch
+    J = torch.zeros(n_inst, dtype=torch.float64, device=dev)
+    g = torch.zeros(b.nz, dtype=torch.float64, device=dev)
+    H = torch.zeros(b.nh, dtype=torch.float64, device=dev)
+    for _ in range(2):
+        b.eq_assemble_jacobian(mu, z0, J, g, H)
+    torch.cuda.synchronize()
+    reps = 5
+    t = time.perf_counter()
+    for _ in range(reps):
+        b.eq_assemble_jacobian(mu, z0, J, g, H)
+    torch.cuda.synchronize()
+    t_jac = (time.perf_counter() - t) / reps
+    # solves (graph replay); the first call captures the graph
+    info = b.info_buffer(dev)
+    z = z0.clone()
+    b.solve(mu, z, info, lam=BATCH_LAMBDA, max_it=BATCH_MAX_IT)
+    torch.cuda.synchronize()
+    z = z0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.solve(mu, z, info, lam=BATCH_LAMBDA, max_it=BATCH_MAX_IT)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t
+    o = ift.Batch.info_array(info)
+    conv = int(o["converged"].sum())
+    st, cnt = np.unique(o["status"], return_counts=True)
+    log(f"batched: {n_inst} instances, {conv} converged in {t_solve:.3f} s ({conv / t_solve:.1f} solves/s), "
+        f"jacobian {t_jac * 1e3:.2f} ms ({ns / t_jac:.3e} evals/s), E={E}")
+    # per-instance loop of the same FP64 path on the first n_loop instances
+    t = time.perf_counter()
+    lconv, lits = 0, []
+    for i in range(min(n_loop, n_inst)):
+        r = roms[i]
+        w = torch.zeros(r.n, dtype=torch.float64, device=dev)
+        tau = torch.zeros(r.m, dtype=torch.float64, device=dev)
+        r.plain_start(bw.mus[i], w, tau)
+        steps = 0
+        while True:
+            last = steps == BATCH_MAX_IT
+            wc, tc = (w.clone(), tau.clone()) if last else (w, tau)
+            st_, inf_ = r.gauss_newton_step(bw.mus[i], wc, tc, lam=BATCH_LAMBDA)
+            if inf_["converged"] or st_ != 0 or last:
+                break
+            steps += 1
+        lconv += int(inf_["converged"])
+        lits.append(steps)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t
+    loop_rate = lconv / t_loop
+    log(f"loop: {min(n_loop, n_inst)} instances, {lconv} converged in {t_loop:.2f} s ({loop_rate:.1f} solves/s)")
+    return {"workload": f"{n_inst} instances of the 16384-element P2 Euler problem, pool n in (10,20,30) x m in "
+                        f"(5,10), EQ sets U(200..2000) + 64 inflow elements, mu Sobol on [2,3] x [-5,5] deg",
+            "instances": n_inst, "sum_n_s": ns, "lambda": BATCH_LAMBDA, "max_it": BATCH_MAX_IT, "tol": 1e-8,
+            "elements_per_wave": E,
+            "solves_per_s": conv / t_solve, "converged": conv, "seconds": t_solve,
+            "status_counts": {int(k): int(v) for k, v in zip(st, cnt)},
+            "mean_gn_iterations": float(o["iterations"].mean()),
+            "jacobian_evals_per_s": ns / t_jac, "jacobian_ms": t_jac * 1e3,
+            "loop": {"instances": min(n_loop, n_inst), "converged": lconv, "seconds": t_loop,
+                     "solves_per_s": loop_rate, "mean_gn_iterations": float(np.mean(lits))},
+            "speedup_vs_loop": (conv / t_solve) / loop_rate if loop_rate > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +198,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-solve", action="store_true", help="skip the solves/s leg")
     ap.add_argument("--no-hdm", action="store_true", help="skip the full-order leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve leg")
+    ap.add_argument("--batch-inst", type=int, default=1024, help="instances of the batched-solve leg")
+    ap.add_argument("--batch-loop", type=int, default=64, help="instances timed in the per-instance loop")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (traffic-counter calibration)")
     args = ap.parse_args()
@@ -221,6 +315,10 @@ def main():
         out["solves"] = {"converged": conv, "attempted": n_eval, "mean_gn_iterations": float(np.mean(iters)),
                          "tol": 1e-8, "seconds": dt}
         log(f"solves: {conv}/{n_eval} converged, {conv / dt:.1f} solves/s, mean iterations {np.mean(iters):.1f}")
+
+    # ------------------------------------------------------- batched solves
+    if not args.no_batch:
+        out["batched"] = batched_leg(args.batch_inst, args.batch_loop, dev)
 
     # ---------------------------------------------------------- full order
     if not args.no_hdm:

@@ -123,8 +123,11 @@ ift_status hdm_assemble(ift_problem* prob, const double* mu, const double* U, co
  * eq_elem [n_s] and eq_rho [n_s] are HOST pointers (rho_k >= 0).  Creation
  * gathers Phi_e = P_e^T Phi, Phi_e' = P_e'^T Phi, Psi_e = Q_e^T Psi and
  * X_e = Q_e^T X for every sampled element (end of Section 3.0) into
- * library-owned device memory and allocates all workspaces; no later call
- * allocates.  Limits: 1 <= n, 0 <= m, n + m <= 64, n_s >= 1.
+ * library-owned device memory, with the reduced bases evaluated at the
+ * quadrature points.  The per-point workspaces of the single-instance
+ * calls are allocated by the first such call (or by ift_rom_reserve), so
+ * a handle used only through a batch never holds them; later calls
+ * allocate nothing.  Limits: 1 <= n, 0 <= m, n + m <= 64, n_s >= 1.
  * Synchronises the stream of the default device context. */
 ift_status ift_rom_create(ift_problem* prob, int n, int m, const double* Phi, const double* Psi,
                           int n_s, const int* eq_elem, const double* eq_rho,
@@ -247,6 +250,14 @@ ift_status eq_assemble_jacobian_batched(ift_batch* batch, const double* mu, cons
  * IFT_OK when the launches succeeded (per-instance outcomes are in info). */
 ift_status rom_gauss_newton_solve_batched(ift_batch* batch, const double* mu, double* z, const ift_gn_params* params,
                                           int max_it, ift_gn_info* info, int flags, hipStream_t stream);
+
+/* The plain start of the reduced iteration: w0 = Phi^T U_fs(mu), the
+ * reduced coordinates of the uniform free stream (Euler) or of the inflow
+ * value (Burgers) on every node (Phi has orthonormal columns), and tau0 = 0,
+ * the unmapped mesh.  rom_plain_start: mu HOST [2], w and tau DEVICE;
+ * rom_plain_start_batched: mu DEVICE [n_inst][2], z DEVICE packed. */
+ift_status rom_plain_start(ift_rom* rom, const double* mu, double* w, double* tau, hipStream_t stream);
+ift_status rom_plain_start_batched(ift_batch* batch, const double* mu, double* z, hipStream_t stream);
 
 /* Kernel timing.  While enabled, every launch of the library's element
  * kernels and reductions is bracketed by HIP events on the caller's stream

@@ -50,6 +50,7 @@ struct ift_rom {
   double* d_rho = nullptr;
   double* d_srho = nullptr;
   double* d_Phi_s = nullptr;
+  double* d_phisum = nullptr;   // [n_c][n]: sum over the nodes of Phi's component-c rows
   double* d_Phin_s = nullptr;
   double* d_Psi_s = nullptr;
   double* d_X_s = nullptr;
@@ -522,6 +523,7 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   dfree(r->d_rho);
   dfree(r->d_srho);
   dfree(r->d_Phi_s);
+  dfree(r->d_phisum);
   dfree(r->d_Phin_s);
   dfree(r->d_Psi_s);
   dfree(r->d_X_s);
@@ -640,6 +642,10 @@ static ift_status reserve_points(ift_rom* r, int max_pts) {
   return IFT_OK;
 }
 
+// Per-point workspaces are allocated on first use, so that handles used
+// only through a batch never hold them.
+static bool lazy_points(ift_rom* r) { return r->max_pts >= 1 || reserve_points(r, 1) == IFT_OK; }
+
 extern "C" ift_status ift_rom_reserve(ift_rom* r, int max_pts) {
   if (!r || max_pts < 1) return IFT_EINVAL;
   if (hipDeviceSynchronize() != hipSuccess) return IFT_EDEVICE;
@@ -703,11 +709,6 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   ALLOC(r->d_Psi_s, (size_t)n_s * nxe * std::max(m, 1));
   ALLOC(r->d_X_s, (size_t)n_s * nxe);
 #undef ALLOC
-  if ((st = reserve_points(r, 1)) != IFT_OK) {
-    dfree(d_rows);
-    ift_rom_destroy(r);
-    return st;
-  }
   bool ok = hipMemcpy(r->d_eq, eq_elem, n_s * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(r->d_rho, eq_rho, n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(r->d_srho, hsr.data(), n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
@@ -723,6 +724,14 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   };
   gather(Phi, n, rows_u, r->d_Phi_s);
   gather(Phi, n, rows_n, r->d_Phin_s);
+  if (ok) {
+    ok = dalloc(&r->d_phisum, (size_t)pr->nc * n) == IFT_OK;
+    if (ok) {
+      hipLaunchKernelGGL(k_phi_colsum, dim3(pr->nc * n), dim3(256), 0, 0, Phi, (long long)(pr->N_u / pr->nc), pr->nc,
+                         n, r->d_phisum);
+      ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
+  }
   gather(Psi, m, rows_x, r->d_Psi_s);
   dfree(d_rows);
   if (ok) ok = build_point_bases(r);
@@ -852,6 +861,7 @@ extern "C" ift_status eq_assemble_residual(ift_rom* r, const double* mu, const d
                                            double* Jobj, double* Ft, double* PhiT_r, int* n_bad,
                                            hipStream_t stream) {
   if (!r || !w || (r->m > 0 && !tau) || !finite_mu(r->prob, mu)) return IFT_EINVAL;
+  if (!lazy_points(r)) return IFT_ENOMEM;
   EqArgs a = eq_args(r, mu, w, tau);
   a.Ft = Ft;
   a.PTR = PhiT_r ? r->d_PTR : nullptr;
@@ -894,6 +904,7 @@ extern "C" ift_status eq_assemble_jacobian(ift_rom* r, const double* mu, const d
                                            double* Jobj, double* g, double* H, double* Jt, int* n_bad,
                                            hipStream_t stream) {
   if (!r || !w || (r->m > 0 && !tau) || !finite_mu(r->prob, mu)) return IFT_EINVAL;
+  if (!lazy_points(r)) return IFT_ENOMEM;
   EqArgs a = eq_args(r, mu, w, tau);
   ift_status s;
   if (r->fused_nt > 0) {
@@ -909,6 +920,7 @@ extern "C" ift_status eq_assemble_jacobian(ift_rom* r, const double* mu, const d
 
 extern "C" ift_status eq_assemble_residual_batch(ift_rom* r, int n_pts, const double* mu, const double* w,
                                                  const double* tau, double* Jobj, int* n_bad, hipStream_t stream) {
+  if (r && !lazy_points(r)) return IFT_ENOMEM;
   if (!r || n_pts < 1 || n_pts > r->max_pts || !mu || !w || (r->m > 0 && !tau) || !Jobj) return IFT_EINVAL;
   double mu0[2] = {1.0, 0.0};
   EqArgs a = eq_args(r, mu0, w, tau);
@@ -924,6 +936,7 @@ extern "C" ift_status eq_assemble_residual_batch(ift_rom* r, int n_pts, const do
 extern "C" ift_status eq_assemble_jacobian_batch(ift_rom* r, int n_pts, const double* mu, const double* w,
                                                  const double* tau, double* Jobj, double* g, double* H, int* n_bad,
                                                  hipStream_t stream) {
+  if (r && !lazy_points(r)) return IFT_ENOMEM;
   if (!r || n_pts < 1 || n_pts > r->max_pts || !mu || !w || (r->m > 0 && !tau) || !Jobj || !g || !H)
     return IFT_EINVAL;
   double mu0[2] = {1.0, 0.0};
@@ -941,6 +954,7 @@ extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double
   if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
     return IFT_EINVAL;
   std::memset(info, 0, sizeof(*info));
+  if (!lazy_points(r)) return IFT_ENOMEM;
   const int n = r->n, m = r->m, D = r->D;
   ift_status s = eq_assemble_jacobian(r, mu, w, tau, r->d_J, r->d_g, r->d_H, nullptr, r->d_nbad, stream);
   if (s != IFT_OK) return s;
@@ -1361,4 +1375,44 @@ extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double*
                      b->n_inst, info);
   HIP_TRY(hipGetLastError());
   return IFT_OK;
+}
+
+// ------------------------------------------------------------ plain start
+// w0 = Phi^T U_fs(mu) with U_fs the uniform free stream (Euler) or inflow
+// value (Burgers) on every node, tau0 = 0.
+__global__ void k_plain_start(const double* phisum, int nc, int n, int m, PhysConst pc, int pde, double bc_scale,
+                              const double* mu, double* w, double* tau) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const PhysConst q = mu ? phys_from_mu(pc, pde, bc_scale, mu) : pc;
+  if (j < n) {
+    double a = 0.0;
+    for (int c = 0; c < nc; ++c) a += q.uinf[c] * phisum[c * n + j];
+    w[j] = a;
+  } else if (j < n + m) {
+    tau[j - n] = 0.0;
+  }
+}
+
+extern "C" ift_status rom_plain_start(ift_rom* r, const double* mu, double* w, double* tau, hipStream_t stream) {
+  if (!r || !w || (r->m > 0 && !tau) || !finite_mu(r->prob, mu)) return IFT_EINVAL;
+  const ift_problem* pr = r->prob;
+  hipLaunchKernelGGL(k_plain_start, dim3((r->D + 63) / 64), dim3(64), 0, stream, (const double*)r->d_phisum, pr->nc,
+                     r->n, r->m, phys_const(pr, mu), pr->pde == IFT_BURGERS2D ? (int)PDE_BURGERS : (int)PDE_EULER,
+                     pr->bc_mu_scale, (const double*)nullptr, w, tau);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+extern "C" ift_status rom_plain_start_batched(ift_batch* b, const double* mu, double* z, hipStream_t stream) {
+  if (!b || !mu || !z) return IFT_EINVAL;
+  const ift_problem* pr = b->prob;
+  const double mu0[2] = {1.0, 0.0};
+  const PhysConst pc = phys_const(pr, mu0);
+  const int pde = pr->pde == IFT_BURGERS2D ? (int)PDE_BURGERS : (int)PDE_EULER;
+  for (int i = 0; i < b->n_inst; ++i) {
+    const ift_rom* r = b->roms[i];
+    double* zi = z + b->zoff[i];
+    hipLaunchKernelGGL(k_plain_start, dim3((r->D + 63) / 64), dim3(64), 0, stream, (const double*)r->d_phisum,
+                       pr->nc, r->n, r->m, pc, pde, pr->bc_mu_scale, mu + 2 * i, zi, zi + r->n);
+  }
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }

@@ -1114,6 +1114,22 @@ __global__ void k_sum_rows(const double* part, int nrows, int ncols, double* out
   out[j] = v;
 }
 
+// Column sums of Phi per solution component: out[c][j] = sum_i Phi[i*nc + c][j]
+// (fixed order: per-thread strided sums, then a tree over the block).
+__global__ __launch_bounds__(256) void k_phi_colsum(const double* Phi, long long n_nodes, int nc, int n, double* out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x / n, j = blockIdx.x % n;
+  double a = 0.0;
+  for (long long i = threadIdx.x; i < n_nodes; i += 256) a += Phi[(i * nc + c) * n + j];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d) red[threadIdx.x] += red[threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c * n + j] = red[0];
+}
+
 // ------------------------------------------------------------ gathers (A1)
 __global__ void k_gather_rows(const double* src, int ncol, const long long* rows, long long nrows, double* dst) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;

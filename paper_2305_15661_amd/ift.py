@@ -78,6 +78,8 @@ EXPORTS = {
     "eq_assemble_jacobian_batched": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "rom_gauss_newton_solve_batched": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(GNParams), ctypes.c_int, _P,
                                                       ctypes.c_int, _P]),
+    "rom_plain_start": (ctypes.c_int, [_P, _D, _P, _P, _P]),
+    "rom_plain_start_batched": (ctypes.c_int, [_P, _P, _P, _P]),
     "ift_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "ift_profile_reset": (ctypes.c_int, []),
     "ift_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
@@ -257,6 +259,13 @@ class ROM:
                                               _ptr(n_bad, P, torch.int32), _stream(stream))
         _check(st, "eq_assemble_jacobian_batch")
 
+    def plain_start(self, mu, w, tau, stream=None):
+        """w = Phi^T U_fs(mu), tau = 0 (device tensors, overwritten)."""
+        import torch
+        f64 = torch.float64
+        _check(lib().rom_plain_start(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
+                                     _stream(stream)), "rom_plain_start")
+
     def gauss_newton_step(self, mu, w, tau, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, stream=None):
         """rom_gauss_newton_step; returns (status, info dict).  Soft outcomes
         (converged / line-search failure / invalid point) are reported in the
@@ -313,6 +322,13 @@ class Batch:
     def unpack(self, z):
         zz = z.detach().cpu().numpy() if hasattr(z, "detach") else np.asarray(z)
         return [zz[self.zoff[i]:self.zoff[i + 1]] for i in range(self.n_inst)]
+
+    def plain_start(self, mu, z, stream=None):
+        """Packed plain starts of every instance into z (device)."""
+        import torch
+        f64 = torch.float64
+        _check(lib().rom_plain_start_batched(self.handle, _ptr(mu, 2 * self.n_inst, f64), _ptr(z, self.nz, f64),
+                                             _stream(stream)), "rom_plain_start_batched")
 
     def autotune(self, mu, z, stream=None) -> int:
         import torch

@@ -250,3 +250,23 @@ def test_invalid_instance_is_isolated_and_max_it_zero(setup):
         else:
             assert out["status"][i] == ift.IFT_ENOTCONV
     assert not np.all(out["converged"] == 1)
+
+
+def test_plain_start_matches_oracle(setup):
+    import torch
+    S = setup
+    b, insts, dev = S["batch"], S["insts"], S["dev"]
+    mu = torch.tensor(np.stack([c["mu"] for c in insts]), dtype=torch.float64, device=dev)
+    z = torch.full((b.nz,), np.nan, dtype=torch.float64, device=dev)
+    _say("batched plain start")
+    b.plain_start(mu, z)
+    torch.cuda.synchronize()
+    zb = b.unpack(z)
+    for i, c in enumerate(insts):
+        ref = np.concatenate([c["w0"], c["tau0"]])
+        assert rel(zb[i], ref) < 1e-13
+        w = torch.full((c["n"],), np.nan, dtype=torch.float64, device=dev)
+        tau = torch.full((c["m"],), np.nan, dtype=torch.float64, device=dev)
+        c["rom"].plain_start(c["mu"], w, tau)
+        torch.cuda.synchronize()
+        assert rel(w.cpu().numpy(), c["w0"]) < 1e-13 and np.all(tau.cpu().numpy() == 0.0)

@@ -278,3 +278,17 @@ def test_full_size_euler_samples(dev):
     assert rel(gg["dRdx"].reshape(Ne, p.nue, p.nxe)[el], o["dRdx"]) < 1e-12
     del gg
     torch.cuda.empty_cache()
+
+
+def test_plain_start_burgers_matches_oracle(tiny_case):
+    import torch
+    from oracle.eq import plain_start
+    case = tiny_case
+    wl, r, d = case.wl, case.rom, case.dev
+    for mu in (wl.mus[0], np.array([0.9, 0.0])):
+        _say(f"plain start burgers mu={mu}")
+        w, tau = _z(r.n, d), _z(r.m, d)
+        r.plain_start(mu, w, tau)
+        torch.cuda.synchronize()
+        w0, t0 = plain_start(wl, mu)
+        assert rel(w.cpu().numpy(), w0) < 1e-13 and np.all(tau.cpu().numpy() == t0)
