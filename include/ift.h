@@ -71,8 +71,18 @@ typedef enum {
 
 typedef enum { IFT_BURGERS2D = 0, IFT_EULER2D = 1 } ift_pde;
 
-/* Element arithmetic precision (the boundary is always FP64). */
-typedef enum { IFT_FP64 = 0, IFT_FP32_ELEM = 1 } ift_precision;
+/* Internal precision (the boundary is always FP64):
+ *   IFT_FP64        everything in FP64;
+ *   IFT_FP32_ELEM   element fluxes and point Jacobians in FP32, projection,
+ *                   Gram and solves in FP64;
+ *   IFT_MIXED_BF16  element fluxes and point Jacobians in FP32, the
+ *                   projection Phi_e^T J_e [Phi_e Psi_e] on BF16 matrix cores
+ *                   with FP32 accumulation; the Gram matrix, gradient and
+ *                   objective are accumulated and the normal equations
+ *                   solved in FP64.  The batched solver finishes such
+ *                   instances with FP64 refinement rounds (see
+ *                   rom_gauss_newton_solve_batched). */
+typedef enum { IFT_FP64 = 0, IFT_FP32_ELEM = 1, IFT_MIXED_BF16 = 2 } ift_precision;
 
 typedef struct ift_problem ift_problem;
 typedef struct ift_rom ift_rom;

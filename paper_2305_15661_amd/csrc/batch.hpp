@@ -33,6 +33,8 @@ struct BatchInst {
   double* g;          // [D]
   double* part;       // fused partials [nblk][NH][256]
   int* part_bad;      // [nblk][2]
+  const short* Bw16;  // BF16 point bases (mixed-precision instances), else null
+  const short* Bx16;
   int nblk;           // fused blocks of this instance
   int nt;             // fused column tiles (1..FUSED_MAXNT)
 };
@@ -40,11 +42,13 @@ struct BatchInst {
 struct BatchState {
   int state, it, n_bt, status;
   int flag_or, n_bad, converged, n_bt_total;
+  int prec, pad_;     // 1: mixed-precision rounds, 0: FP64 rounds
   double J, J0, Jtrial, alpha, slope, nS, nT, alpha_acc;
 };
 
 struct BatchParams {
   double lambda, c1, tol;
+  double tol_mix;     // gradient norms at which a mixed-precision instance switches to FP64
   int max_backtrack, max_it;
 };
 
@@ -69,17 +73,22 @@ IFT_DEV int batch_owner(const int* off, int n_inst, int item) {
 
 constexpr int BC_THR = 1024;
 
-// Exclusive sums of the active instances' element and block counts (one
-// block, fixed order).  with_blocks = 0 leaves the block lists empty.
+// Exclusive sums of the element and block counts of the instances in state
+// `want` (and, if want_prec >= 0, in that precision phase); one block,
+// fixed order.  with_blocks = 0 leaves the block lists empty.
+IFT_DEV bool batch_active(const BatchState& st, int want, int want_prec) {
+  return st.state == want && (want_prec < 0 || st.prec == want_prec);
+}
+
 __global__ __launch_bounds__(BC_THR) void k_batch_compact(const BatchInst* I, const BatchState* S, BatchLists L,
-                                                          int n_inst, int want, int with_blocks) {
+                                                          int n_inst, int want, int want_prec, int with_blocks) {
   __shared__ int sc[4][BC_THR];
   const int t = threadIdx.x;
   const int chunk = (n_inst + BC_THR - 1) / BC_THR;
   const int beg = min(n_inst, t * chunk), end = min(n_inst, beg + chunk);
   int c[4] = {0, 0, 0, 0};
   for (int i = beg; i < end; ++i) {
-    if (S[i].state != want) continue;
+    if (!batch_active(S[i], want, want_prec)) continue;
     c[0] += I[i].a.n_s;
     if (with_blocks) c[I[i].nt] += I[i].nblk;
   }
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(BC_THR) void k_batch_compact(const BatchInst* I, co
   int run[4];
   for (int q = 0; q < 4; ++q) run[q] = sc[q][t] - c[q];
   for (int i = beg; i < end; ++i) {
-    const bool act = S[i].state == want;
+    const bool act = batch_active(S[i], want, want_prec);
     for (int q = 0; q < 4; ++q) L.off[q * (n_inst + 1) + i] = run[q];
     if (act) {
       run[0] += I[i].a.n_s;
@@ -111,8 +120,10 @@ __global__ __launch_bounds__(BC_THR) void k_batch_compact(const BatchInst* I, co
 }
 
 // Point physics of every sampled element of the JAC instances.
+// (At least two waves per SIMD: the tangent point physics sits just above
+// the register budget of that occupancy once inside the persistent loop.)
 template <class D, class R>
-__global__ __launch_bounds__(NTHR_PTS) void k_points_batch(const BatchInst* I, BatchLists L, int n_inst) {
+__global__ __launch_bounds__(NTHR_PTS, 2) void k_points_batch(const BatchInst* I, BatchLists L, int n_inst) {
   __shared__ ElemLDS<D, R> s;
   const int total = L.cnt[0];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
@@ -180,10 +191,13 @@ __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState*
   }
   lm_solve_body(bi.H, bi.g, D, n, p.lambda, bi.dz, out, L, y, fail);
   if (threadIdx.x == 0) {
-    if (st.it == 0) st.J0 = J;
+    if (st.it == 0 && st.prec == 1) st.J0 = J;
+    if (st.it == 0 && st.prec == 0 && st.J0 == 0.0) st.J0 = J;
     st.nS = out[1];
     st.nT = out[2];
-    if (out[1] <= p.tol && out[2] <= p.tol) {
+    if (st.prec == 1 && out[1] <= p.tol_mix && out[2] <= p.tol_mix) {
+      st.prec = 0;   // refine in FP64 from here; the state stays JAC
+    } else if (out[1] <= p.tol && out[2] <= p.tol && st.prec == 0) {
       st.converged = 1;
       st.status = IFT_OK;
       st.state = BS_DONE;
@@ -268,6 +282,11 @@ __global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState
       st.alpha_acc = st.alpha;
       st.n_bt_total += st.n_bt;
       st.state = BS_JAC;
+    } else if (st.n_bt >= p.max_backtrack && st.prec == 1) {
+      st.n_bt += 1;
+      st.n_bt_total += st.n_bt;
+      st.prec = 0;        // no decrease at mixed precision: continue in FP64
+      st.state = BS_JAC;
     } else if (st.n_bt >= p.max_backtrack) {
       st.n_bt += 1;
       st.n_bt_total += st.n_bt;
@@ -295,7 +314,7 @@ __global__ __launch_bounds__(256) void k_batch_remaining(const BatchState* S, in
 }
 
 // Fresh state for every instance.
-__global__ void k_batch_init(BatchState* S, int n_inst) {
+__global__ void k_batch_init(BatchState* S, int n_inst, int mixed) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_inst) return;
   BatchState st;
@@ -307,9 +326,12 @@ __global__ void k_batch_init(BatchState* S, int n_inst) {
   st.n_bad = 0;
   st.converged = 0;
   st.n_bt_total = 0;
+  st.prec = mixed;
+  st.pad_ = 0;
   st.J = st.J0 = st.Jtrial = 0.0;
   st.alpha = st.slope = st.nS = st.nT = st.alpha_acc = 0.0;
   S[i] = st;
 }
 
 }  // namespace ift
+

@@ -75,6 +75,8 @@ struct Pts {
   int pad_;
 };
 
+constexpr int ELEM_STAGE = 2048;   // doubles of lift staging per element block
+
 template <class D, class R>
 struct ElemLDS {
   RefTab tab;
@@ -85,7 +87,10 @@ struct ElemLDS {
   int face[3];
   Pts<D, R> p;
   R Re[D::NUE];
-  R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
+  union {
+    R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
+    double stage[ELEM_STAGE];   // staging of the lift (Jacobian not yet formed)
+  };
 };
 
 template <class D, class R>

@@ -7,11 +7,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ift.h"
 #include "kernels.hpp"
 #include "batch.hpp"
+#include "mixed.hpp"
 
 namespace ift {
 __constant__ RefTab c_tab[2];
@@ -56,6 +58,8 @@ struct ift_rom {
   double* d_X_s = nullptr;
   double* d_Bw = nullptr;   // reduced state basis at the quadrature points [n_s][KWP][n]
   double* d_Bx = nullptr;   // mapping-basis geometry derivatives [n_s][KXP][m]
+  short* d_Bw16 = nullptr;  // BF16 copies, column-major per element (mixed precision)
+  short* d_Bx16 = nullptr;
   // workspaces
   long long nrows = 0;
   int n_gram_blk = 0;
@@ -548,6 +552,8 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   if (r->d_pts) (void)hipFree(r->d_pts);
   dfree(r->d_Bw);
   dfree(r->d_Bx);
+  dfree(r->d_Bw16);
+  dfree(r->d_Bx16);
   delete r;
 }
 
@@ -567,6 +573,17 @@ struct PointBases {
     hipLaunchKernelGGL((k_point_bases<D>), dim3(r->n_s), dim3(256), 0, 0, (const double*)r->d_Phi_s,
                        (const double*)r->d_Phin_s, (const double*)r->d_Psi_s, r->n, r->m, r->d_Bw, r->d_Bx);
     ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    if (ok && r->precision == IFT_MIXED_BF16) {
+      using Q = EqOp16<D>;
+      if (dalloc(&r->d_Bw16, (size_t)r->n_s * (r->n + 1) * Q::KW16) != IFT_OK ||
+          dalloc(&r->d_Bx16, (size_t)r->n_s * (r->m + 1) * Q::KX16) != IFT_OK) {
+        ok = false;
+        return;
+      }
+      hipLaunchKernelGGL((k_point_bases16<D>), dim3(r->n_s), dim3(256), 0, 0, (const double*)r->d_Bw,
+                         (const double*)r->d_Bx, r->n, r->m, r->d_Bw16, r->d_Bx16);
+      ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
   }
 };
 
@@ -658,7 +675,7 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   if (!pr || !out || !Phi || (m > 0 && !Psi) || !eq_elem || !eq_rho) return IFT_EINVAL;
   *out = nullptr;
   if (n < 1 || m < 0 || n + m > 64 || n_s < 1) return IFT_EINVAL;
-  if (precision != IFT_FP64 && precision != IFT_FP32_ELEM) return IFT_EINVAL;
+  if (precision != IFT_FP64 && precision != IFT_FP32_ELEM && precision != IFT_MIXED_BF16) return IFT_EINVAL;
   for (int k = 0; k < n_s; ++k) {
     if (eq_elem[k] < 0 || eq_elem[k] >= pr->n_elem) return IFT_EINVAL;
     if (!(eq_rho[k] >= 0.0) || !std::isfinite(eq_rho[k])) return IFT_EINVAL;
@@ -803,8 +820,16 @@ struct EqLaunch {
   const double* Bx;
   const FusedArgs* fa;   // fused assembly + Gram, or null
   int nt;
+  const short* Bw16;     // non-null: projection on BF16 matrix cores (R = float)
+  const short* Bx16;
   template <class D, int NT>
   void fused() {
+    if constexpr (std::is_same<R, float>::value) {
+      if (Bw16) {
+        hipLaunchKernelGGL((k_eq_fused_mixed<D, NT>), dim3(fa->nblk, n_pts), dim3(NTHR), 0, st, a, Bw16, Bx16, *fa);
+        return;
+      }
+    }
     hipLaunchKernelGGL((k_eq_fused<D, R, NT>), dim3(fa->nblk, n_pts), dim3(NTHR), 0, st, a, Bw, Bx, *fa);
   }
   template <class D>
@@ -828,10 +853,10 @@ struct EqLaunch {
 
 static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, int n_pts, hipStream_t st,
                               const FusedArgs* fa = nullptr) {
-  if (r->precision == IFT_FP32_ELEM)
-    with_disc(r->prob, EqLaunch<float>{a, jac, n_pts, st, r->d_Bw, r->d_Bx, fa, r->fused_nt});
+  if (r->precision != IFT_FP64)
+    with_disc(r->prob, EqLaunch<float>{a, jac, n_pts, st, r->d_Bw, r->d_Bx, fa, r->fused_nt, r->d_Bw16, r->d_Bx16});
   else
-    with_disc(r->prob, EqLaunch<double>{a, jac, n_pts, st, r->d_Bw, r->d_Bx, fa, r->fused_nt});
+    with_disc(r->prob, EqLaunch<double>{a, jac, n_pts, st, r->d_Bw, r->d_Bx, fa, r->fused_nt, nullptr, nullptr});
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }
 
@@ -1050,6 +1075,7 @@ struct ift_batch {
 static constexpr int BATCH_E_CAND[] = {4, 8, 16, 32};
 static constexpr int BATCH_T = 2;           // line-search trials per round
 static constexpr int BATCH_ROUNDS = 4;      // rounds per graph replay (one completion check each)
+static constexpr double BATCH_TOL_MIX = 1e-5;   // gradient norms that end the mixed-precision rounds
 static constexpr int BATCH_GRID_PTS = 2048, BATCH_GRID_RES = 2048, BATCH_GRID_FUSED = 1024;
 
 static int batch_nblk(int n_s, int E) { return (n_s + 4 * E - 1) / (4 * E); }
@@ -1076,6 +1102,8 @@ static ift_status batch_upload(ift_batch* b) {
     bi.a = a;
     bi.Bw = r->d_Bw;
     bi.Bx = r->d_Bx;
+    bi.Bw16 = r->d_Bw16;
+    bi.Bx16 = r->d_Bx16;
     bi.z = b->d_z + b->zoff[i];
     bi.zt = b->d_zt + b->zoff[i];
     bi.dz = b->d_dz + b->zoff[i];
@@ -1186,49 +1214,71 @@ extern "C" ift_status ift_batch_layout(const ift_batch* b, int* zoff, int* hoff)
   return IFT_OK;
 }
 
-// Kernels of one phase for the batch's discretisation and precision.
-template <class R>
+// Kernels of one phase for the batch's discretisation.  A mixed-precision
+// batch runs each phase twice: for its instances still in mixed rounds
+// (FP32 points, BF16 projection, FP32 element residuals) and for those in
+// FP64 rounds.
 struct BatchLaunch {
   ift_batch* b;
   hipStream_t st;
   int phase;   // 0: Jacobian assembly of the JAC instances, 1: trial residuals of the SEARCH instances
-  template <class D, int NT>
-  void fused(const BatchLists& L) {
-    if (b->has_nt[NT])
-      hipLaunchKernelGGL((k_fused_batch<D, R, NT>), dim3(BATCH_GRID_FUSED), dim3(NTHR), 0, st,
-                         (const BatchInst*)b->d_inst, L, b->n_inst, b->E);
+  template <class D, class R, int NT>
+  void fused(const BatchLists& L, bool mixed) {
+    if (!b->has_nt[NT]) return;
+    if constexpr (std::is_same<R, float>::value) {
+      if (mixed) {
+        hipLaunchKernelGGL((k_fused_batch_mixed<D, NT>), dim3(BATCH_GRID_FUSED), dim3(NTHR), 0, st,
+                           (const BatchInst*)b->d_inst, L, b->n_inst, b->E);
+        return;
+      }
+    }
+    hipLaunchKernelGGL((k_fused_batch<D, R, NT>), dim3(BATCH_GRID_FUSED), dim3(NTHR), 0, st,
+                       (const BatchInst*)b->d_inst, L, b->n_inst, b->E);
   }
-  template <class D>
-  void run() {
+  // the instances of one precision phase (want_prec: 1 mixed, 0 FP64, -1 all)
+  template <class D, class R>
+  void group(int want_prec, bool mixed) {
     BatchLists L{b->d_off, b->d_cnt};
     const int ni = b->n_inst;
     if (phase == 0) {
       hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
-                         (const BatchState*)b->d_state, L, ni, (int)BS_JAC, 1);
+                         (const BatchState*)b->d_state, L, ni, (int)BS_JAC, want_prec, 1);
       hipLaunchKernelGGL((k_points_batch<D, R>), dim3(BATCH_GRID_PTS), dim3(NTHR_PTS), 0, st,
                          (const BatchInst*)b->d_inst, L, ni);
-      fused<D, 1>(L);
-      fused<D, 2>(L);
-      fused<D, 3>(L);
-      hipLaunchKernelGGL(k_final_batch, dim3(b->nbe_max + 1, ni), dim3(256), 0, st, (const BatchInst*)b->d_inst,
-                         b->d_state);
+      fused<D, R, 1>(L, mixed);
+      fused<D, R, 2>(L, mixed);
+      fused<D, R, 3>(L, mixed);
     } else {
       hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
-                         (const BatchState*)b->d_state, L, ni, (int)BS_SEARCH, 0);
-      hipLaunchKernelGGL(k_trial_batch, dim3(ni), dim3(64), 0, st, (const BatchInst*)b->d_inst,
-                         (const BatchState*)b->d_state);
+                         (const BatchState*)b->d_state, L, ni, (int)BS_SEARCH, want_prec, 0);
       hipLaunchKernelGGL((k_res_batch<D, R>), dim3(BATCH_GRID_RES), dim3(NTHR), 0, st, (const BatchInst*)b->d_inst,
                          L, ni);
+    }
+  }
+  template <class D>
+  void run() {
+    const int ni = b->n_inst;
+    if (phase == 1)
+      hipLaunchKernelGGL(k_trial_batch, dim3(ni), dim3(64), 0, st, (const BatchInst*)b->d_inst,
+                         (const BatchState*)b->d_state);
+    if (b->precision == IFT_MIXED_BF16) {
+      group<D, float>(1, true);
+      group<D, double>(0, false);
+    } else if (b->precision == IFT_FP32_ELEM) {
+      group<D, float>(-1, false);
+    } else {
+      group<D, double>(-1, false);
+    }
+    if (phase == 0)
+      hipLaunchKernelGGL(k_final_batch, dim3(b->nbe_max + 1, ni), dim3(256), 0, st, (const BatchInst*)b->d_inst,
+                         b->d_state);
+    else
       hipLaunchKernelGGL(k_ls_batch, dim3(ni), dim3(256), 0, st, (const BatchInst*)b->d_inst, b->d_state,
                          (const BatchParams*)b->d_params);
-    }
   }
 };
 
-static void batch_phase(ift_batch* b, int phase, hipStream_t st) {
-  if (b->precision == IFT_FP32_ELEM) with_disc(b->prob, BatchLaunch<float>{b, st, phase});
-  else with_disc(b->prob, BatchLaunch<double>{b, st, phase});
-}
+static void batch_phase(ift_batch* b, int phase, hipStream_t st) { with_disc(b->prob, BatchLaunch{b, st, phase}); }
 
 // `rounds` rounds of the solve: the Jacobian phase of the JAC instances,
 // their LM step (or stop), then BATCH_T line-search trials of the SEARCH
@@ -1270,7 +1320,8 @@ extern "C" ift_status eq_assemble_jacobian_batched(ift_batch* b, const double* m
   if (!b || !mu || !z || !Jobj || !g || !H) return IFT_EINVAL;
   ift_status s = batch_inputs(b, mu, z, stream);
   if (s != IFT_OK) return s;
-  hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst);
+  hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
+                     b->precision == IFT_MIXED_BF16 ? 1 : 0);
   {
     ProfScope ps(IFT_PROF_EQ_JAC, stream);
     batch_phase(b, 0, stream);
@@ -1302,7 +1353,8 @@ extern "C" ift_status ift_batch_autotune(ift_batch* b, const double* mu, const d
     if ((s = batch_upload(b)) != IFT_OK) break;
     float tot = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
-      hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst);
+      hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
+                     b->precision == IFT_MIXED_BF16 ? 1 : 0);
       HIP_TRY(hipEventRecord(e0, stream));
       batch_phase(b, 0, stream);
       HIP_TRY(hipEventRecord(e1, stream));
@@ -1334,7 +1386,7 @@ extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double*
   if (!b || !mu || !z || !prm || !info || max_it < 0) return IFT_EINVAL;
   if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
     return IFT_EINVAL;
-  BatchParams bp{prm->lambda, prm->c1, prm->tol, prm->max_backtrack, max_it};
+  BatchParams bp{prm->lambda, prm->c1, prm->tol, std::max(prm->tol, BATCH_TOL_MIX), prm->max_backtrack, max_it};
   HIP_TRY(hipMemcpyAsync(b->d_params, &bp, sizeof(bp), hipMemcpyHostToDevice, stream));
   ift_status s = batch_inputs(b, mu, z, stream);
   if (s != IFT_OK) return s;
@@ -1356,7 +1408,8 @@ extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double*
       return IFT_EDEVICE;
     }
   }
-  hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst);
+  hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
+                     b->precision == IFT_MIXED_BF16 ? 1 : 0);
   // every instance finishes within (max_it + 1) Jacobian rounds, each
   // followed by at most ceil((max_backtrack + 1) / T) rounds of trials
   const long long cap = (long long)(max_it + 1) * (2 + (prm->max_backtrack + 1 + BATCH_T - 1) / BATCH_T);

@@ -22,7 +22,7 @@ IFT_EBADMESH, IFT_ENONPHYS, IFT_ESINGULAR, IFT_ELINESEARCH, IFT_ENOTCONV = -4, -
 STATUS_NAMES = {0: "IFT_OK", -1: "IFT_EINVAL", -2: "IFT_ENOMEM", -3: "IFT_EDEVICE", -4: "IFT_EBADMESH",
                 -5: "IFT_ENONPHYS", -6: "IFT_ESINGULAR", -7: "IFT_ELINESEARCH", -8: "IFT_ENOTCONV"}
 PDE = {"burgers": 0, "euler": 1}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 
 
 class IftError(RuntimeError):
