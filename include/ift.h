@@ -198,6 +198,8 @@ typedef struct {
   int converged;       /* input point meets tol; no step taken              */
   int status;          /* an ift_status                                     */
   int iterations;      /* LM steps taken (batched solve; 0 or 1 for a step) */
+  int fallback;        /* batched solve with a warm start: 1 if the plain
+                          start was used instead                           */
 } ift_gn_info;
 
 /* One Levenberg-Marquardt step from z_n = (w, tau) (device, in/out):
@@ -254,6 +256,10 @@ ift_status eq_assemble_jacobian_batched(ift_batch* batch, const double* mu, cons
  * (max_it reached), IFT_ELINESEARCH, IFT_ESINGULAR, IFT_EBADMESH or
  * IFT_ENONPHYS (invalid iterate).  flags bit 0 = 1: launch the kernels
  * directly instead of replaying the captured HIP graph (same results).
+ * flags bit 1 = 1: z holds warm starts (e.g. from ift_mlp_predict); J~ is
+ * evaluated (FP64) at each warm start and at the plain start, and an
+ * instance starts from the plain start unless its warm start has the
+ * smaller J~ (info.fallback = 1 then).
  * The rounds (Jacobian assembly, LM step, two line-search trials) run in
  * replays of four captured rounds; after each replay the stream is
  * synchronised to read how many instances are still running.  Returns
@@ -268,6 +274,44 @@ ift_status rom_gauss_newton_solve_batched(ift_batch* batch, const double* mu, do
  * rom_plain_start_batched: mu DEVICE [n_inst][2], z DEVICE packed. */
 ift_status rom_plain_start(ift_rom* rom, const double* mu, double* w, double* tau, hipStream_t stream);
 ift_status rom_plain_start_batched(ift_batch* batch, const double* mu, double* z, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Warm-start network: z0 = y_mean + y_scale * f((mu - x_mean) / x_scale),
+ * f = W3 gelu(W2 gelu(W1 x + b1) + b2) + b3 with gelu(t) = t Phi(t), a map
+ * from the parameters mu to the reduced coordinates (w, tau) of converged
+ * solves, used to seed rom_gauss_newton_solve_batched.  Parameters are one
+ * flat FP32 DEVICE array: for each layer W [out][in] row-major, then b.
+ * Training (ift_mlp_train) runs full-batch Adam (beta 0.9, 0.999, eps 1e-8)
+ * on the mean squared error of the normalised outputs, all in FP32 on the
+ * device with fixed-order reductions; inference runs in FP32 or with BF16
+ * weights and activations on matrix cores (FP32 accumulation).
+ * Limits: n_in <= 8, hidden <= 256, n_out <= 64.
+ * ------------------------------------------------------------------------ */
+typedef struct ift_mlp ift_mlp;
+
+/* Weights W_l ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a splitmix64 stream
+ * seeded with `seed`, biases 0, identity normalisation. */
+ift_status ift_mlp_create(int n_in, int hidden, int n_out, unsigned long long seed, ift_mlp** out);
+void ift_mlp_destroy(ift_mlp* mlp);
+ift_status ift_mlp_num_params(const ift_mlp* mlp, int* n);
+ift_status ift_mlp_set_params(ift_mlp* mlp, const float* params, hipStream_t stream);   /* resets Adam */
+ift_status ift_mlp_get_params(const ift_mlp* mlp, float* params, hipStream_t stream);
+/* HOST arrays x_mean, x_scale [n_in], y_mean, y_scale [n_out] (scales > 0). */
+ift_status ift_mlp_set_normalization(ift_mlp* mlp, const double* x_mean, const double* x_scale, const double* y_mean,
+                                     const double* y_scale);
+/* Loss (mean squared error over samples and outputs) and its gradient at
+ * the current parameters for normalised data X [N][n_in], T [N][n_out]
+ * (DEVICE, FP32); grad DEVICE [n_params] (may be null), loss HOST (may be
+ * null; then the call does not synchronise). */
+ift_status ift_mlp_loss_grad(ift_mlp* mlp, const float* X, const float* T, int N, float* grad, double* loss,
+                             hipStream_t stream);
+/* `steps` Adam steps with learning rate lr on mu [N][n_in], z [N][n_out]
+ * (DEVICE, FP64, normalised internally); loss_hist HOST [steps] or null.
+ * Synchronises the stream. */
+ift_status ift_mlp_train(ift_mlp* mlp, const double* mu, const double* z, int N, int steps, double lr,
+                         double* loss_hist, hipStream_t stream);
+/* z [N][n_out] (DEVICE, FP64) from mu [N][n_in]; bf16 != 0: BF16 matrix cores. */
+ift_status ift_mlp_predict(ift_mlp* mlp, const double* mu, int N, double* z, int bf16, hipStream_t stream);
 
 /* Kernel timing.  While enabled, every launch of the library's element
  * kernels and reductions is bracketed by HIP events on the caller's stream

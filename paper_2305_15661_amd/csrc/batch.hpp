@@ -33,6 +33,7 @@ struct BatchInst {
   double* g;          // [D]
   double* part;       // fused partials [nblk][NH][256]
   int* part_bad;      // [nblk][2]
+  const double* phisum;  // [n_c][n] column sums of Phi per component (plain start)
   const short* Bw16;  // BF16 point bases (mixed-precision instances), else null
   const short* Bx16;
   int nblk;           // fused blocks of this instance
@@ -42,7 +43,8 @@ struct BatchInst {
 struct BatchState {
   int state, it, n_bt, status;
   int flag_or, n_bad, converged, n_bt_total;
-  int prec, pad_;     // 1: mixed-precision rounds, 0: FP64 rounds
+  int prec;           // 1: mixed-precision rounds, 0: FP64 rounds
+  int fallback;       // warm start replaced by the plain start
   double J, J0, Jtrial, alpha, slope, nS, nT, alpha_acc;
 };
 
@@ -313,6 +315,82 @@ __global__ __launch_bounds__(256) void k_batch_remaining(const BatchState* S, in
   if (threadIdx.x == 0) *out = sc[0];
 }
 
+// Plain start w0 = Phi^T U_fs(mu_i), tau0 = 0 of every instance into out
+// (one block per instance).
+__global__ __launch_bounds__(64) void k_plain_batch(const BatchInst* I, int pde, int nc, double* const* outp,
+                                                     int which) {
+  const int inst = blockIdx.x;
+  const BatchInst& bi = I[inst];
+  const PhysConst q = phys_from_mu(bi.a.pc, pde, bi.a.bc_mu_scale, bi.a.mu);
+  double* out = which == 0 ? bi.z : (which == 1 ? bi.zt : bi.dz);
+  (void)outp;
+  const int n = bi.a.n, D = bi.a.D;
+  for (int j = threadIdx.x; j < D; j += 64) {
+    double v = 0.0;
+    if (j < n)
+      for (int c = 0; c < nc; ++c) v += q.uinf[c] * bi.phisum[c * n + j];
+    out[j] = v;
+  }
+}
+
+// Start selection: stage a candidate start in zt (which 0: the warm start
+// z, 1: the plain start held in dz) and mark every instance SEARCH.
+__global__ __launch_bounds__(64) void k_start_stage(const BatchInst* I, BatchState* S, int which) {
+  const int inst = blockIdx.x;
+  const BatchInst& bi = I[inst];
+  const double* src = which == 0 ? bi.z : bi.dz;
+  for (int j = threadIdx.x; j < bi.a.D; j += 64) bi.zt[j] = src[j];
+  if (threadIdx.x == 0) S[inst].state = BS_SEARCH;
+}
+
+// Objective at the staged start (fixed-order sum; +inf if invalid) into
+// Jtrial (which 0) or alpha (which 1, used as scratch before the solve).
+__global__ __launch_bounds__(256) void k_start_obj(const BatchInst* I, BatchState* S, int which) {
+  __shared__ double sj[256];
+  __shared__ int so[256];
+  const int inst = blockIdx.x;
+  const BatchInst& bi = I[inst];
+  const int t = threadIdx.x;
+  double v = 0.0;
+  int o = 0;
+  for (int k = t; k < bi.a.n_s; k += 256) {
+    v += bi.a.Jpart[k];
+    o |= bi.a.flags[k];
+  }
+  sj[t] = v;
+  so[t] = o;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (t < d) {
+      sj[t] += sj[t + d];
+      so[t] |= so[t + d];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double J = so[0] ? __builtin_inf() : sj[0];
+    if (which == 0) S[inst].Jtrial = J;
+    else S[inst].alpha = J;
+  }
+}
+
+// Keep the warm start only if its objective is the smaller one.
+__global__ __launch_bounds__(64) void k_start_select(const BatchInst* I, BatchState* S) {
+  const int inst = blockIdx.x;
+  const BatchInst& bi = I[inst];
+  BatchState& st = S[inst];
+  const bool warm = st.Jtrial < st.alpha;   // false for NaN or +inf warm objectives
+  if (!warm)
+    for (int j = threadIdx.x; j < bi.a.D; j += 64) bi.z[j] = bi.dz[j];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st.fallback = warm ? 0 : 1;
+    st.state = BS_JAC;
+    st.Jtrial = 0.0;
+    st.alpha = 0.0;
+  }
+}
+
 // Fresh state for every instance.
 __global__ void k_batch_init(BatchState* S, int n_inst, int mixed) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,7 +405,7 @@ __global__ void k_batch_init(BatchState* S, int n_inst, int mixed) {
   st.converged = 0;
   st.n_bt_total = 0;
   st.prec = mixed;
-  st.pad_ = 0;
+  st.fallback = 0;
   st.J = st.J0 = st.Jtrial = 0.0;
   st.alpha = st.slope = st.nS = st.nT = st.alpha_acc = 0.0;
   S[i] = st;

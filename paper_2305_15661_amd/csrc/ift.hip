@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "batch.hpp"
 #include "mixed.hpp"
+#include "mlp.hpp"
 
 namespace ift {
 __constant__ RefTab c_tab[2];
@@ -1104,6 +1105,7 @@ static ift_status batch_upload(ift_batch* b) {
     bi.Bx = r->d_Bx;
     bi.Bw16 = r->d_Bw16;
     bi.Bx16 = r->d_Bx16;
+    bi.phisum = r->d_phisum;
     bi.z = b->d_z + b->zoff[i];
     bi.zt = b->d_zt + b->zoff[i];
     bi.dz = b->d_dz + b->zoff[i];
@@ -1306,6 +1308,7 @@ __global__ void k_batch_info(const BatchState* S, int n_inst, ift_gn_info* info)
   o.converged = st.converged;
   o.status = st.state == BS_DONE ? st.status : IFT_ENOTCONV;   // (round cap reached; not expected)
   o.iterations = st.it;
+  o.fallback = st.fallback;
   info[i] = o;
 }
 
@@ -1380,6 +1383,34 @@ extern "C" ift_status ift_batch_autotune(ift_batch* b, const double* mu, const d
   return s;
 }
 
+// FP64 residual phase over the SEARCH instances (objective parts at zt).
+struct BatchResidual64 {
+  ift_batch* b;
+  hipStream_t st;
+  template <class D>
+  void run() {
+    BatchLists L{b->d_off, b->d_cnt};
+    hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
+                       (const BatchState*)b->d_state, L, b->n_inst, (int)BS_SEARCH, -1, 0);
+    hipLaunchKernelGGL((k_res_batch<D, double>), dim3(BATCH_GRID_RES), dim3(NTHR), 0, st,
+                       (const BatchInst*)b->d_inst, L, b->n_inst);
+  }
+};
+
+// Warm start or plain start per instance: J~ (FP64) at both, keep the smaller.
+static void batch_select_start(ift_batch* b, hipStream_t st) {
+  const ift_problem* pr = b->prob;
+  const int ni = b->n_inst;
+  hipLaunchKernelGGL(k_plain_batch, dim3(ni), dim3(64), 0, st, (const BatchInst*)b->d_inst,
+                     pr->pde == IFT_BURGERS2D ? (int)PDE_BURGERS : (int)PDE_EULER, pr->nc, (double* const*)nullptr, 2);
+  for (int which = 0; which < 2; ++which) {
+    hipLaunchKernelGGL(k_start_stage, dim3(ni), dim3(64), 0, st, (const BatchInst*)b->d_inst, b->d_state, which);
+    with_disc(pr, BatchResidual64{b, st});
+    hipLaunchKernelGGL(k_start_obj, dim3(ni), dim3(256), 0, st, (const BatchInst*)b->d_inst, b->d_state, which);
+  }
+  hipLaunchKernelGGL(k_start_select, dim3(ni), dim3(64), 0, st, (const BatchInst*)b->d_inst, b->d_state);
+}
+
 extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double* mu, double* z,
                                                      const ift_gn_params* prm, int max_it, ift_gn_info* info,
                                                      int flags, hipStream_t stream) {
@@ -1410,6 +1441,7 @@ extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double*
   }
   hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
                      b->precision == IFT_MIXED_BF16 ? 1 : 0);
+  if (flags & 2) batch_select_start(b, stream);
   // every instance finishes within (max_it + 1) Jacobian rounds, each
   // followed by at most ceil((max_backtrack + 1) / T) rounds of trials
   const long long cap = (long long)(max_it + 1) * (2 + (prm->max_backtrack + 1 + BATCH_T - 1) / BATCH_T);
@@ -1457,15 +1489,288 @@ extern "C" ift_status rom_plain_start(ift_rom* r, const double* mu, double* w, d
 
 extern "C" ift_status rom_plain_start_batched(ift_batch* b, const double* mu, double* z, hipStream_t stream) {
   if (!b || !mu || !z) return IFT_EINVAL;
+  ift_status s = batch_inputs(b, mu, z, stream);   // mu into the batch; z is overwritten below
+  if (s != IFT_OK) return s;
   const ift_problem* pr = b->prob;
-  const double mu0[2] = {1.0, 0.0};
-  const PhysConst pc = phys_const(pr, mu0);
-  const int pde = pr->pde == IFT_BURGERS2D ? (int)PDE_BURGERS : (int)PDE_EULER;
-  for (int i = 0; i < b->n_inst; ++i) {
-    const ift_rom* r = b->roms[i];
-    double* zi = z + b->zoff[i];
-    hipLaunchKernelGGL(k_plain_start, dim3((r->D + 63) / 64), dim3(64), 0, stream, (const double*)r->d_phisum,
-                       pr->nc, r->n, r->m, pc, pde, pr->bc_mu_scale, mu + 2 * i, zi, zi + r->n);
+  hipLaunchKernelGGL(k_plain_batch, dim3(b->n_inst), dim3(64), 0, stream, (const BatchInst*)b->d_inst,
+                     pr->pde == IFT_BURGERS2D ? (int)PDE_BURGERS : (int)PDE_EULER, pr->nc, (double* const*)nullptr, 0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(z, b->d_z, (size_t)b->zoff[b->n_inst] * sizeof(double), hipMemcpyDeviceToDevice, stream));
+  return IFT_OK;
+}
+
+// ============================================================ warm-start network
+struct ift_mlp {
+  int n_in = 0, hidden = 0, n_out = 0;
+  int n_par = 0;
+  float* d_par = nullptr;     // flat parameters
+  float* d_grad = nullptr;
+  float* d_m = nullptr;       // Adam moments
+  float* d_v = nullptr;
+  long long adam_t = 0;
+  double* d_norm = nullptr;   // x_mean[n_in], x_scale[n_in], y_mean[n_out], y_scale[n_out]
+  // activations for up to cap samples
+  int cap = 0;
+  float *d_X = nullptr, *d_T = nullptr, *d_A1 = nullptr, *d_H1 = nullptr, *d_A2 = nullptr, *d_H2 = nullptr,
+        *d_Y = nullptr, *d_dY = nullptr, *d_d1 = nullptr, *d_d2 = nullptr;
+  double* d_lpart = nullptr;
+  double* d_loss = nullptr;
+};
+
+static constexpr int MLP_LOSS_BLOCKS = 64;
+
+static int mlp_offsets(const ift_mlp* p, int layer, int* in, int* out) {
+  const int dims[3][2] = {{p->hidden, p->n_in}, {p->hidden, p->hidden}, {p->n_out, p->hidden}};
+  int o = 0;
+  for (int l = 0; l < layer; ++l) o += dims[l][0] * dims[l][1] + dims[l][0];
+  *out = dims[layer][0];
+  *in = dims[layer][1];
+  return o;
+}
+
+static ift_status mlp_reserve(ift_mlp* p, int N) {
+  if (N <= p->cap) return IFT_OK;
+  dfree(p->d_X);
+  dfree(p->d_T);
+  dfree(p->d_A1);
+  dfree(p->d_H1);
+  dfree(p->d_A2);
+  dfree(p->d_H2);
+  dfree(p->d_Y);
+  dfree(p->d_dY);
+  dfree(p->d_d1);
+  dfree(p->d_d2);
+  p->cap = 0;
+  const size_t n = N, h = p->hidden;
+  ift_status st;
+  if ((st = dalloc(&p->d_X, n * p->n_in)) != IFT_OK || (st = dalloc(&p->d_T, n * p->n_out)) != IFT_OK ||
+      (st = dalloc(&p->d_A1, n * h)) != IFT_OK || (st = dalloc(&p->d_H1, n * h)) != IFT_OK ||
+      (st = dalloc(&p->d_A2, n * h)) != IFT_OK || (st = dalloc(&p->d_H2, n * h)) != IFT_OK ||
+      (st = dalloc(&p->d_Y, n * p->n_out)) != IFT_OK || (st = dalloc(&p->d_dY, n * p->n_out)) != IFT_OK ||
+      (st = dalloc(&p->d_d1, n * h)) != IFT_OK || (st = dalloc(&p->d_d2, n * h)) != IFT_OK)
+    return st;
+  p->cap = N;
+  return IFT_OK;
+}
+
+extern "C" void ift_mlp_destroy(ift_mlp* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  dfree(p->d_par);
+  dfree(p->d_grad);
+  dfree(p->d_m);
+  dfree(p->d_v);
+  dfree(p->d_norm);
+  dfree(p->d_X);
+  dfree(p->d_T);
+  dfree(p->d_A1);
+  dfree(p->d_H1);
+  dfree(p->d_A2);
+  dfree(p->d_H2);
+  dfree(p->d_Y);
+  dfree(p->d_dY);
+  dfree(p->d_d1);
+  dfree(p->d_d2);
+  dfree(p->d_lpart);
+  dfree(p->d_loss);
+  delete p;
+}
+
+// splitmix64 (Steele, Lea and Flood 2014): the initialisation stream.
+static unsigned long long splitmix64(unsigned long long& s) {
+  unsigned long long z = (s += 0x9e3779b97f4a7c15ULL);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+extern "C" ift_status ift_mlp_create(int n_in, int hidden, int n_out, unsigned long long seed, ift_mlp** out) {
+  if (!out || n_in < 1 || n_in > 8 || hidden < 1 || hidden > 256 || n_out < 1 || n_out > 64) return IFT_EINVAL;
+  *out = nullptr;
+  ift_mlp* p = new ift_mlp;
+  p->n_in = n_in;
+  p->hidden = hidden;
+  p->n_out = n_out;
+  p->n_par = hidden * n_in + hidden + hidden * hidden + hidden + n_out * hidden + n_out;
+  // W ~ U(-1/sqrt(fan_in), 1/sqrt(fan_in)), b = 0; unit normalisation
+  std::vector<float> h(p->n_par, 0.f);
+  unsigned long long st = seed;
+  for (int l = 0; l < 3; ++l) {
+    int in, o;
+    const int off = mlp_offsets(p, l, &in, &o);
+    const double lim = 1.0 / std::sqrt((double)in);
+    for (int i = 0; i < o * in; ++i)
+      h[off + i] = float(lim * (2.0 * (double)(splitmix64(st) >> 11) * 0x1.0p-53 - 1.0));
   }
+  std::vector<double> nrm(2 * n_in + 2 * n_out, 0.0);
+  for (int i = 0; i < n_in; ++i) nrm[n_in + i] = 1.0;
+  for (int o = 0; o < n_out; ++o) nrm[2 * n_in + n_out + o] = 1.0;
+  if (dalloc(&p->d_par, p->n_par) != IFT_OK || dalloc(&p->d_grad, p->n_par) != IFT_OK ||
+      dalloc(&p->d_m, p->n_par) != IFT_OK || dalloc(&p->d_v, p->n_par) != IFT_OK ||
+      dalloc(&p->d_norm, nrm.size()) != IFT_OK || dalloc(&p->d_lpart, MLP_LOSS_BLOCKS) != IFT_OK ||
+      dalloc(&p->d_loss, 1) != IFT_OK ||
+      hipMemcpy(p->d_par, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_norm, nrm.data(), nrm.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(p->d_m, 0, p->n_par * sizeof(float)) != hipSuccess ||
+      hipMemset(p->d_v, 0, p->n_par * sizeof(float)) != hipSuccess) {
+    ift_mlp_destroy(p);
+    return IFT_ENOMEM;
+  }
+  *out = p;
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_mlp_num_params(const ift_mlp* p, int* n) {
+  if (!p || !n) return IFT_EINVAL;
+  *n = p->n_par;
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_mlp_set_params(ift_mlp* p, const float* params, hipStream_t stream) {
+  if (!p || !params) return IFT_EINVAL;
+  HIP_TRY(hipMemcpyAsync(p->d_par, params, p->n_par * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemsetAsync(p->d_m, 0, p->n_par * sizeof(float), stream));
+  HIP_TRY(hipMemsetAsync(p->d_v, 0, p->n_par * sizeof(float), stream));
+  p->adam_t = 0;
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_mlp_get_params(const ift_mlp* p, float* params, hipStream_t stream) {
+  if (!p || !params) return IFT_EINVAL;
+  HIP_TRY(hipMemcpyAsync(params, p->d_par, p->n_par * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_mlp_set_normalization(ift_mlp* p, const double* x_mean, const double* x_scale,
+                                                const double* y_mean, const double* y_scale) {
+  if (!p || !x_mean || !x_scale || !y_mean || !y_scale) return IFT_EINVAL;
+  std::vector<double> nrm;
+  nrm.insert(nrm.end(), x_mean, x_mean + p->n_in);
+  nrm.insert(nrm.end(), x_scale, x_scale + p->n_in);
+  nrm.insert(nrm.end(), y_mean, y_mean + p->n_out);
+  nrm.insert(nrm.end(), y_scale, y_scale + p->n_out);
+  for (int i = 0; i < p->n_in; ++i)
+    if (!(x_scale[i] > 0.0) || !std::isfinite(x_mean[i])) return IFT_EINVAL;
+  for (int o = 0; o < p->n_out; ++o)
+    if (!(y_scale[o] > 0.0) || !std::isfinite(y_mean[o])) return IFT_EINVAL;
+  HIP_TRY(hipMemcpy(p->d_norm, nrm.data(), nrm.size() * sizeof(double), hipMemcpyHostToDevice));
+  return IFT_OK;
+}
+
+static inline unsigned nblk(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Forward pass on d_X (FP32) for N samples into d_Y; keeps pre-activations.
+static void mlp_forward(ift_mlp* p, int N, hipStream_t st) {
+  int in, o;
+  const float* par = p->d_par;
+  int off = mlp_offsets(p, 0, &in, &o);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk((long long)N * o, 256)), dim3(256), 0, st, (const float*)p->d_X, in,
+                     par + off, par + off + o * in, o, N, p->d_A1, p->d_H1, 1);
+  off = mlp_offsets(p, 1, &in, &o);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk((long long)N * o, 256)), dim3(256), 0, st, (const float*)p->d_H1, in,
+                     par + off, par + off + o * in, o, N, p->d_A2, p->d_H2, 1);
+  off = mlp_offsets(p, 2, &in, &o);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3(nblk((long long)N * o, 256)), dim3(256), 0, st, (const float*)p->d_H2, in,
+                     par + off, par + off + o * in, o, N, (float*)nullptr, p->d_Y, 0);
+}
+
+// Loss of d_Y against d_T and the gradient into d_grad.
+static void mlp_backward(ift_mlp* p, int N, hipStream_t st) {
+  const long long cnt = (long long)N * p->n_out;
+  hipLaunchKernelGGL(k_mlp_loss, dim3(MLP_LOSS_BLOCKS), dim3(256), 0, st, (const float*)p->d_Y, (const float*)p->d_T,
+                     cnt, float(1.0 / (double)cnt), p->d_dY, p->d_lpart);
+  hipLaunchKernelGGL(k_mlp_loss_final, dim3(1), dim3(64), 0, st, (const double*)p->d_lpart, MLP_LOSS_BLOCKS,
+                     1.0 / (double)cnt, p->d_loss);
+  const float* par = p->d_par;
+  float* gr = p->d_grad;
+  int in, o;
+  // layer 3: dY -> dW3, db3, dH2
+  int off = mlp_offsets(p, 2, &in, &o);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st, (const float*)p->d_dY,
+                     (const float*)p->d_H2, in, o, N, gr + off, gr + off + o * in);
+  hipLaunchKernelGGL(k_mlp_xgrad, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_dY,
+                     par + off, in, o, N, p->d_d2);
+  hipLaunchKernelGGL(k_mlp_act_bwd, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_A2,
+                     p->d_d2, (long long)N * in);
+  // layer 2
+  off = mlp_offsets(p, 1, &in, &o);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st, (const float*)p->d_d2,
+                     (const float*)p->d_H1, in, o, N, gr + off, gr + off + o * in);
+  hipLaunchKernelGGL(k_mlp_xgrad, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_d2,
+                     par + off, in, o, N, p->d_d1);
+  hipLaunchKernelGGL(k_mlp_act_bwd, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_A1,
+                     p->d_d1, (long long)N * in);
+  // layer 1
+  off = mlp_offsets(p, 0, &in, &o);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st, (const float*)p->d_d1,
+                     (const float*)p->d_X, in, o, N, gr + off, gr + off + o * in);
+}
+
+extern "C" ift_status ift_mlp_loss_grad(ift_mlp* p, const float* X, const float* T, int N, float* grad, double* loss,
+                                        hipStream_t stream) {
+  if (!p || !X || !T || N < 1) return IFT_EINVAL;
+  ift_status s = mlp_reserve(p, N);
+  if (s != IFT_OK) return s;
+  HIP_TRY(hipMemcpyAsync(p->d_X, X, (size_t)N * p->n_in * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->d_T, T, (size_t)N * p->n_out * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  mlp_forward(p, N, stream);
+  mlp_backward(p, N, stream);
+  HIP_TRY(hipGetLastError());
+  if (grad) HIP_TRY(hipMemcpyAsync(grad, p->d_grad, p->n_par * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  if (loss) {
+    HIP_TRY(hipMemcpyAsync(loss, p->d_loss, sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_mlp_train(ift_mlp* p, const double* mu, const double* z, int N, int steps, double lr,
+                                    double* loss_hist, hipStream_t stream) {
+  if (!p || !mu || !z || N < 1 || steps < 0 || !(lr > 0.0)) return IFT_EINVAL;
+  ift_status s = mlp_reserve(p, N);
+  if (s != IFT_OK) return s;
+  const double* nm = p->d_norm;
+  const int ni = p->n_in, no = p->n_out;
+  hipLaunchKernelGGL(k_mlp_normalize, dim3(nblk((long long)N * std::max(ni, no), 256)), dim3(256), 0, stream, mu, z, N,
+                     ni, no, nm, nm + ni, nm + 2 * ni, nm + 2 * ni + no, p->d_X, p->d_T);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int it = 0; it < steps; ++it) {
+    mlp_forward(p, N, stream);
+    mlp_backward(p, N, stream);
+    p->adam_t += 1;
+    const float c1 = float(1.0 - std::pow(0.9, (double)p->adam_t));
+    const float c2 = float(1.0 - std::pow(0.999, (double)p->adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(p->n_par, 256)), dim3(256), 0, stream, p->d_par, (const float*)p->d_grad,
+                       p->d_m, p->d_v, p->n_par, float(lr), b1, b2, eps, c1, c2);
+    if (loss_hist) HIP_TRY(hipMemcpyAsync(loss_hist + it, p->d_loss, sizeof(double), hipMemcpyDeviceToHost, stream));
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(stream));
+  return IFT_OK;
+}
+
+extern "C" ift_status ift_mlp_predict(ift_mlp* p, const double* mu, int N, double* z, int bf16, hipStream_t stream) {
+  if (!p || !mu || !z || N < 1) return IFT_EINVAL;
+  ift_status s = mlp_reserve(p, N);
+  if (s != IFT_OK) return s;
+  const double* nm = p->d_norm;
+  const int ni = p->n_in, no = p->n_out;
+  hipLaunchKernelGGL(k_mlp_normalize, dim3(nblk((long long)N * ni, 256)), dim3(256), 0, stream, mu,
+                     (const double*)nullptr, N, ni, no, nm, nm + ni, nm + 2 * ni, nm + 2 * ni + no, p->d_X, p->d_T);
+  if (bf16) {
+    const float* par = p->d_par;
+    const float* H[4] = {p->d_X, p->d_H1, p->d_H2, nullptr};
+    float* Ho[3] = {p->d_H1, p->d_H2, p->d_Y};
+    for (int l = 0; l < 3; ++l) {
+      int in, o;
+      const int off = mlp_offsets(p, l, &in, &o);
+      hipLaunchKernelGGL(k_mlp_fwd_bf16, dim3(nblk(N, 16), nblk(o, 16)), dim3(64), 0, stream, H[l], in, par + off,
+                         par + off + o * in, o, N, Ho[l], l < 2 ? 1 : 0);
+    }
+  } else {
+    mlp_forward(p, N, stream);
+  }
+  hipLaunchKernelGGL(k_mlp_denormalize, dim3(nblk((long long)N * no, 256)), dim3(256), 0, stream, (const float*)p->d_Y,
+                     N, no, nm + 2 * ni, nm + 2 * ni + no, z);
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }

@@ -46,7 +46,8 @@ class GNParams(ctypes.Structure):
 class GNInfo(ctypes.Structure):
     _fields_ = [("J_old", ctypes.c_double), ("J_new", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("norm_S", ctypes.c_double), ("norm_T", ctypes.c_double), ("n_backtrack", ctypes.c_int),
-                ("converged", ctypes.c_int), ("status", ctypes.c_int), ("iterations", ctypes.c_int)]
+                ("converged", ctypes.c_int), ("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("fallback", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +81,16 @@ EXPORTS = {
                                                       ctypes.c_int, _P]),
     "rom_plain_start": (ctypes.c_int, [_P, _D, _P, _P, _P]),
     "rom_plain_start_batched": (ctypes.c_int, [_P, _P, _P, _P]),
+    "ift_mlp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_ulonglong,
+                                      ctypes.POINTER(_P)]),
+    "ift_mlp_destroy": (None, [_P]),
+    "ift_mlp_num_params": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "ift_mlp_set_params": (ctypes.c_int, [_P, _P, _P]),
+    "ift_mlp_get_params": (ctypes.c_int, [_P, _P, _P]),
+    "ift_mlp_set_normalization": (ctypes.c_int, [_P, _D, _D, _D, _D]),
+    "ift_mlp_loss_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "ift_mlp_train": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, _P]),
+    "ift_mlp_predict": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, ctypes.c_int, _P]),
     "ift_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "ift_profile_reset": (ctypes.c_int, []),
     "ift_profile_read": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
@@ -284,7 +295,7 @@ class ROM:
 # numpy view of a device array of ift_gn_info records
 GN_INFO_DTYPE = np.dtype([("J_old", "<f8"), ("J_new", "<f8"), ("alpha", "<f8"), ("norm_S", "<f8"),
                           ("norm_T", "<f8"), ("n_backtrack", "<i4"), ("converged", "<i4"), ("status", "<i4"),
-                          ("iterations", "<i4")])
+                          ("iterations", "<i4"), ("fallback", "<i4"), ("_pad", "<i4")])
 assert GN_INFO_DTYPE.itemsize == ctypes.sizeof(GNInfo)
 
 
@@ -348,7 +359,7 @@ class Batch:
         _check(st, "eq_assemble_jacobian_batched")
 
     def solve(self, mu, z, info, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, max_it=50, graph=True,
-              stream=None):
+              warm=False, stream=None):
         """rom_gauss_newton_solve_batched; info: device uint8 tensor of
         n_inst * GN_INFO_DTYPE.itemsize bytes (see info_array)."""
         import torch
@@ -357,8 +368,8 @@ class Batch:
             raise ValueError("info has the wrong size")
         st = lib().rom_gauss_newton_solve_batched(self.handle, _ptr(mu, 2 * self.n_inst, torch.float64),
                                                   _ptr(z, self.nz, torch.float64), ctypes.byref(prm), int(max_it),
-                                                  ctypes.c_void_p(info.data_ptr()), 0 if graph else 1,
-                                                  _stream(stream))
+                                                  ctypes.c_void_p(info.data_ptr()),
+                                                  (0 if graph else 1) | (2 if warm else 0), _stream(stream))
         _check(st, "rom_gauss_newton_solve_batched")
 
     def info_buffer(self, device=None):
@@ -368,6 +379,66 @@ class Batch:
     @staticmethod
     def info_array(buf):
         return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=GN_INFO_DTYPE)
+
+
+class MLP:
+    """Warm-start network (ift_mlp_*): n_in -> hidden -> hidden -> n_out, GELU."""
+
+    def __init__(self, n_in=2, hidden=128, n_out=30, seed=1):
+        h = _P()
+        _check(lib().ift_mlp_create(int(n_in), int(hidden), int(n_out), int(seed), ctypes.byref(h)), "ift_mlp_create")
+        self.handle = h
+        self.n_in, self.hidden, self.n_out = n_in, hidden, n_out
+        c = ctypes.c_int()
+        _check(lib().ift_mlp_num_params(h, ctypes.byref(c)), "ift_mlp_num_params")
+        self.n_params = c.value
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            _lib.ift_mlp_destroy(h)
+            self.handle = None
+
+    def set_params(self, params, stream=None):
+        import torch
+        _check(lib().ift_mlp_set_params(self.handle, _ptr(params, self.n_params, torch.float32), _stream(stream)),
+               "ift_mlp_set_params")
+
+    def get_params(self, params, stream=None):
+        import torch
+        _check(lib().ift_mlp_get_params(self.handle, _ptr(params, self.n_params, torch.float32), _stream(stream)),
+               "ift_mlp_get_params")
+
+    def set_normalization(self, x_mean, x_scale, y_mean, y_scale):
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x_mean, x_scale, y_mean, y_scale)]
+        _check(lib().ift_mlp_set_normalization(self.handle, *[v.ctypes.data_as(_D) for v in a]),
+               "ift_mlp_set_normalization")
+
+    def loss_grad(self, X, T, grad=None, stream=None):
+        import torch
+        N = int(X.shape[0])
+        loss = ctypes.c_double()
+        _check(lib().ift_mlp_loss_grad(self.handle, _ptr(X, N * self.n_in, torch.float32),
+                                       _ptr(T, N * self.n_out, torch.float32), N,
+                                       _ptr(grad, self.n_params, torch.float32), ctypes.byref(loss),
+                                       _stream(stream)), "ift_mlp_loss_grad")
+        return loss.value
+
+    def train(self, mu, z, steps, lr=1e-3, stream=None):
+        import torch
+        N = int(mu.shape[0])
+        hist = np.zeros(max(steps, 1))
+        _check(lib().ift_mlp_train(self.handle, _ptr(mu, N * self.n_in, torch.float64),
+                                   _ptr(z, N * self.n_out, torch.float64), N, int(steps), float(lr),
+                                   hist.ctypes.data_as(_D), _stream(stream)), "ift_mlp_train")
+        return hist[:steps]
+
+    def predict(self, mu, z, bf16=True, stream=None):
+        import torch
+        N = int(mu.shape[0])
+        _check(lib().ift_mlp_predict(self.handle, _ptr(mu, N * self.n_in, torch.float64), N,
+                                     _ptr(z, N * self.n_out, torch.float64), int(bool(bf16)), _stream(stream)),
+               "ift_mlp_predict")
 
 
 def profile_enable(on: bool = True):

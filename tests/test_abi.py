@@ -95,3 +95,14 @@ def test_batch_arguments_rejected():
     prm = ift.GNParams(0.0, 1e-4, 30, 1e-8)
     assert L.rom_gauss_newton_solve_batched(None, None, None, ctypes.byref(prm), 10, None, 0, None) == ift.IFT_EINVAL
     L.ift_batch_destroy(None)
+
+
+def test_mlp_arguments_rejected():
+    ift, L = _lib()
+    h = ctypes.c_void_p()
+    for args in ((0, 16, 4), (2, 0, 4), (2, 16, 0), (9, 16, 4), (2, 300, 4), (2, 16, 65)):
+        assert L.ift_mlp_create(*args, 1, ctypes.byref(h)) == ift.IFT_EINVAL
+        assert not h.value
+    assert L.ift_mlp_train(None, None, None, 1, 1, 1e-3, None, None) == ift.IFT_EINVAL
+    assert L.ift_mlp_predict(None, None, 1, None, 0, None) == ift.IFT_EINVAL
+    L.ift_mlp_destroy(None)

@@ -1,0 +1,142 @@
+"""Warm-start network (ift_mlp_*) and warm-started batched solves on the GPU.
+
+The network's forward pass, loss and gradient are compared with the FP64
+oracle (oracle/mlp.py, itself pinned to finite differences): the GPU runs
+in FP32, so values agree to a few FP32 roundoffs (bounds 1e-5 relative for
+outputs and loss, 1e-4 for the gradient, whose entries are sums over the
+samples).  BF16 inference rounds weights and activations to 8 significant
+bits: outputs within 3e-2 (relative, Frobenius) of FP32 inference.
+"""
+import numpy as np
+import pytest
+
+import synth
+from conftest import rel
+from oracle import mlp as omlp
+from oracle.eq import plain_start
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _setup_net(ift, dev, n_in=2, hidden=32, n_out=5, seed=3):
+    import torch
+    net = ift.MLP(n_in, hidden, n_out, seed=7)
+    params = omlp.init_params(n_in, hidden, n_out, seed=seed)
+    rng = np.random.default_rng(seed)
+    params = [(W, 0.1 * rng.normal(size=b.shape)) for W, b in params]
+    flat32 = omlp.flatten(params).astype(np.float32)
+    net.set_params(torch.tensor(flat32, device=dev))
+    # the oracle uses the same FP32-rounded parameters
+    return net, omlp.unflatten(flat32.astype(np.float64), n_in, hidden, n_out)
+
+
+def test_mlp_gradient_matches_oracle():
+    import torch
+    from paper_2305_15661_amd import ift
+    dev = torch.device("cuda:0")
+    net, params = _setup_net(ift, dev)
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(257, 2)).astype(np.float32)
+    T = rng.normal(size=(257, 5)).astype(np.float32)
+    g = torch.zeros(net.n_params, dtype=torch.float32, device=dev)
+    _say("mlp loss and gradient")
+    L = net.loss_grad(torch.tensor(X, device=dev), torch.tensor(T, device=dev), g)
+    Lo, go = omlp.loss_and_grad(params, X.astype(np.float64), T.astype(np.float64))
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert rel(g.cpu().numpy().astype(np.float64), omlp.flatten(go)) < 1e-4
+
+
+def test_mlp_training_and_inference():
+    import torch
+    from paper_2305_15661_amd import ift
+    dev = torch.device("cuda:0")
+    net = ift.MLP(2, 64, 4, seed=5)
+    rng = np.random.default_rng(12)
+    mu = np.stack([rng.uniform(2, 3, 512), rng.uniform(-5, 5, 512)], axis=1)
+    z = np.stack([np.sin(mu[:, 0]), mu[:, 1] ** 2 / 25.0, mu[:, 0] * mu[:, 1], np.cos(mu[:, 1] / 3)], axis=1)
+    net.set_normalization(mu.mean(0), mu.std(0), z.mean(0), z.std(0))
+    _say("mlp training")
+    hist = net.train(torch.tensor(mu, device=dev), torch.tensor(z, device=dev), steps=600, lr=3e-3)
+    assert hist[-1] < 0.05 * hist[0]
+    assert np.all(np.isfinite(hist))
+    # FP32 inference against the oracle forward with the trained parameters
+    p = torch.zeros(net.n_params, dtype=torch.float32, device=dev)
+    net.get_params(p)
+    params = omlp.unflatten(p.cpu().numpy().astype(np.float64), 2, 64, 4)
+    zf = torch.zeros(512 * 4, dtype=torch.float64, device=dev)
+    zb = torch.zeros(512 * 4, dtype=torch.float64, device=dev)
+    net.predict(torch.tensor(mu, device=dev), zf, bf16=False)
+    net.predict(torch.tensor(mu, device=dev), zb, bf16=True)
+    torch.cuda.synchronize()
+    y, _ = omlp.forward(params, (mu - mu.mean(0)) / mu.std(0))
+    zo = z.mean(0) + z.std(0) * y
+    zf, zb = zf.cpu().numpy().reshape(512, 4), zb.cpu().numpy().reshape(512, 4)
+    assert rel(zf, zo) < 1e-5
+    assert rel(zb, zf) < 3e-2
+
+
+def _batch(ift, dev, base, rng, shapes):
+    import torch
+    prob = ift.Problem.from_workload(base)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), device=dev)
+    roms, mus, starts = [], [], []
+    for i, (n, m, ns) in enumerate(shapes):
+        el = synth.eq_set_with_inflow(base.mesh, ns, rng)
+        rho = rng.lognormal(0.0, 0.5, size=el.size)
+        roms.append(ift.ROM(prob, t(base.Phi[:, :n]), t(base.Psi[:, :m]), el, rho))
+        mu = np.array([2.1 + 0.15 * i, -3.0 + 1.5 * i])
+        w0, tau0 = plain_start(base, mu)
+        mus.append(mu)
+        starts.append(np.concatenate([w0[:n], tau0[:m]]))
+    return prob, roms, ift.Batch(roms), mus, starts
+
+
+def test_warm_start_selection_and_fallback():
+    import torch
+    from paper_2305_15661_amd import ift
+    dev = torch.device("cuda:0")
+    base = synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=1)
+    rng = np.random.default_rng(31)
+    prob, roms, b, mus, starts = _batch(ift, dev, base, rng, [(20, 10, 40), (20, 10, 70), (20, 5, 55), (10, 10, 25)])
+    mu = torch.tensor(np.stack(mus), dtype=torch.float64, device=dev)
+    # plain-start solve
+    z = b.pack(starts, dev)
+    info = b.info_buffer(dev)
+    _say("plain solve")
+    b.solve(mu, z, info, lam=1e-10, max_it=80)
+    torch.cuda.synchronize()
+    plain = b.info_array(info).copy()
+    zsol = z.clone()
+    # warm start at the converged iterates: no fallback, converged at once
+    zw = zsol.clone()
+    _say("warm solve from the solutions")
+    b.solve(mu, zw, info, lam=1e-10, max_it=80, warm=True)
+    torch.cuda.synchronize()
+    w = b.info_array(info).copy()
+    assert np.sum(plain["iterations"] > 0) >= 2
+    for i in range(b.n_inst):
+        if plain["converged"][i]:
+            assert w["iterations"][i] == 0 and w["converged"][i] == 1
+            # a warm start equal to the plain start (solved at once) is not
+            # strictly better and falls back; otherwise it is kept
+            if plain["iterations"][i] > 0:
+                assert w["fallback"][i] == 0
+    # garbage warm starts (non-physical): every instance falls back to the
+    # plain start and reproduces the plain solve (the device's plain start,
+    # w0 from column sums of Phi, differs from the host's Phi^T U_fs only by
+    # rounding, ~1e-14, in coordinates that vanish exactly)
+    bad = [s.copy() for s in starts]
+    for s in bad:
+        s[:4] *= -3.0
+    zg = b.pack(bad, dev)
+    _say("warm solve from invalid starts")
+    b.solve(mu, zg, info, lam=1e-10, max_it=80, warm=True)
+    torch.cuda.synchronize()
+    g = b.info_array(info).copy()
+    assert np.all(g["fallback"] == 1)
+    assert np.array_equal(g["iterations"], plain["iterations"])
+    assert rel(zg.cpu().numpy(), zsol.cpu().numpy()) < 1e-10
