@@ -150,8 +150,40 @@ def batched_leg(n_inst: int, n_loop: int, dev):
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t
     o = ift.Batch.info_array(info)
+    z64 = b.unpack(z)
     conv = int(o["converged"].sum())
     st, cnt = np.unique(o["status"], return_counts=True)
+    # mixed precision on the same instances: FP32 physics, BF16 projection,
+    # FP64 Gram and solves, FP64 refinement rounds
+    romsm = [ift.ROM(prob, *pool[bw.inst_pool[i]], bw.inst_elem[i], bw.inst_rho[i], "mixed") for i in range(n_inst)]
+    bm = ift.Batch(romsm)
+    bm.autotune(mu, z0)
+    infom = bm.info_buffer(dev)
+    zm = z0.clone()
+    bm.solve(mu, zm, infom, lam=BATCH_LAMBDA, max_it=BATCH_MAX_IT)
+    torch.cuda.synchronize()
+    zm = z0.clone()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    bm.solve(mu, zm, infom, lam=BATCH_LAMBDA, max_it=BATCH_MAX_IT)
+    torch.cuda.synchronize()
+    t_mixed = time.perf_counter() - t
+    om = ift.Batch.info_array(infom)
+    convm = int(om["converged"].sum())
+    zmu = bm.unpack(zm)
+    both = [i for i in range(n_inst) if o["converged"][i] and om["converged"][i]]
+    errs = np.array([np.linalg.norm(zmu[i] - z64[i]) / np.linalg.norm(z64[i]) for i in both])
+    mixed = {"solves_per_s": convm / t_mixed, "converged": convm, "seconds": t_mixed,
+             "mean_gn_iterations": float(om["iterations"].mean()),
+             "speedup_vs_fp64_batch": (convm / t_mixed) / (conv / t_solve) if conv else None,
+             "state_error_vs_fp64": {"instances": len(both), "median": float(np.median(errs)) if both else None,
+                                     "max": float(errs.max()) if both else None,
+                                     "fraction_le_1e-6": float(np.mean(errs <= 1e-6)) if both else None},
+             "note": "both solves stop at |S~|,|T~| <= 1e-8; two such iterates can differ by up to "
+                     "|H^-1| * 2e-8, so the state error reflects the conditioning of H as well as precision"}
+    log(f"mixed: {convm} converged in {t_mixed:.3f} s ({convm / t_mixed:.1f} solves/s); state error median "
+        f"{mixed['state_error_vs_fp64']['median']}, max {mixed['state_error_vs_fp64']['max']}")
+    del bm, romsm
     log(f"batched: {n_inst} instances, {conv} converged in {t_solve:.3f} s ({conv / t_solve:.1f} solves/s), "
         f"jacobian {t_jac * 1e3:.2f} ms ({ns / t_jac:.3e} evals/s), E={E}")
     # per-instance loop of the same FP64 path on the first n_loop instances
@@ -186,7 +218,84 @@ def batched_leg(n_inst: int, n_loop: int, dev):
             "jacobian_evals_per_s": ns / t_jac, "jacobian_ms": t_jac * 1e3,
             "loop": {"instances": min(n_loop, n_inst), "converged": lconv, "seconds": t_loop,
                      "solves_per_s": loop_rate, "mean_gn_iterations": float(np.mean(lits))},
-            "speedup_vs_loop": (conv / t_solve) / loop_rate if loop_rate > 0 else None}
+            "speedup_vs_loop": (conv / t_solve) / loop_rate if loop_rate > 0 else None,
+            "mixed_precision": mixed}
+
+
+def warm_start_leg(dev, n_train: int = 4096, n_test: int = 1024, train_steps: int = 3000):
+    """Learned warm start on the 16384-element ROM (n = 20, m = 10, 819 EQ
+    elements): FP64 batched solves at n_train Sobol mu (seed 1005) give the
+    targets; the network 2 -> 128 -> 128 -> 30 is trained on the converged
+    ones; n_test held-out Sobol mu (seed 1007) are then solved in the
+    mixed-precision batched pipeline from the plain start and from the
+    network's start (BF16 inference, plain-start fallback)."""
+    import torch
+    from scipy.stats import qmc
+    import synth
+    from paper_2305_15661_amd import ift
+    wl = synth.euler_p2(n_eval=1)
+    prob = ift.Problem.from_workload(wl)
+    Phi = torch.tensor(wl.Phi, device=dev)
+    Psi = torch.tensor(wl.Psi, device=dev)
+    rom64 = ift.ROM(prob, Phi, Psi, wl.eq_elem, wl.eq_rho)
+    romm = ift.ROM(prob, Phi, Psi, wl.eq_elem, wl.eq_rho, "mixed")
+
+    def sobol(seed, n):
+        s = qmc.Sobol(d=2, scramble=True, seed=seed).random(n)
+        return np.stack([2.0 + s[:, 0], -5.0 + 10.0 * s[:, 1]], axis=1)
+
+    def solve(batch, mu, warm_z=None, reps=1):
+        mu_t = torch.tensor(mu, device=dev)
+        z0 = torch.zeros(batch.nz, dtype=torch.float64, device=dev)
+        batch.plain_start(mu_t, z0)
+        info = batch.info_buffer(dev)
+        out = None
+        for rep in range(reps + 1):   # first run captures the graph
+            z = (warm_z if warm_z is not None else z0).clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            batch.solve(mu_t, z, info, lam=BATCH_LAMBDA, max_it=BATCH_MAX_IT, warm=warm_z is not None)
+            torch.cuda.synchronize()
+            out = (z, ift.Batch.info_array(info), time.perf_counter() - t)
+        return out
+
+    t0 = time.perf_counter()
+    mu_tr = sobol(1005, n_train)
+    btr = ift.Batch([rom64] * n_train)
+    ztr, itr, t_gen = solve(btr, mu_tr)
+    ok = itr["converged"] == 1
+    Z = ztr.reshape(n_train, 30)[torch.tensor(ok, device=dev)]
+    M = torch.tensor(mu_tr[ok], device=dev)
+    del btr
+    log(f"warm start: {int(ok.sum())}/{n_train} training solves converged in {t_gen:.2f} s")
+    net = ift.MLP(2, 128, 30, seed=1)
+    Zc = Z.cpu().numpy()
+    net.set_normalization(mu_tr[ok].mean(0), mu_tr[ok].std(0), Zc.mean(0), np.maximum(Zc.std(0), 1e-12))
+    t = time.perf_counter()
+    hist = net.train(M, Z, steps=train_steps, lr=1e-3)
+    t_train = time.perf_counter() - t
+    log(f"warm start: trained {train_steps} steps in {t_train:.2f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    mu_te = sobol(1007, n_test)
+    bte = ift.Batch([romm] * n_test)
+    mu_t = torch.tensor(mu_te, device=dev)
+    zw = torch.zeros(bte.nz, dtype=torch.float64, device=dev)
+    net.predict(mu_t, zw, bf16=True)
+    zp_, ip, tp = solve(bte, mu_te)
+    zw_, iw, tw = solve(bte, mu_te, warm_z=zw)
+    cp, cw = int(ip["converged"].sum()), int(iw["converged"].sum())
+    log(f"warm start: plain {cp} converged, {ip['iterations'].mean():.1f} its, {tp:.3f} s; warm {cw} converged, "
+        f"{iw['iterations'].mean():.1f} its, {tw:.3f} s, {int(iw['fallback'].sum())} fallbacks")
+    return {"workload": "16384-element P2 Euler ROM, n=20, m=10, 819 EQ elements; mu Sobol on [2,3] x [-5,5] deg",
+            "train": {"instances": n_train, "converged": int(ok.sum()), "solve_seconds": t_gen,
+                      "steps": train_steps, "train_seconds": t_train, "loss_first": float(hist[0]),
+                      "loss_last": float(hist[-1])},
+            "test_instances": n_test, "pipeline": "batched, mixed precision (BF16 projection) + FP64 refinement",
+            "plain": {"converged": cp, "mean_gn_iterations": float(ip["iterations"].mean()), "seconds": tp,
+                      "solves_per_s": cp / tp},
+            "warm": {"converged": cw, "mean_gn_iterations": float(iw["iterations"].mean()), "seconds": tw,
+                     "solves_per_s": cw / tw, "fallbacks": int(iw["fallback"].sum())},
+            "speedup_warm_vs_plain": (cw / tw) / (cp / tp) if cp and tp > 0 else None,
+            "setup_seconds": time.perf_counter() - t0}
 
 
 def main():
@@ -201,6 +310,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve leg")
     ap.add_argument("--batch-inst", type=int, default=1024, help="instances of the batched-solve leg")
     ap.add_argument("--batch-loop", type=int, default=64, help="instances timed in the per-instance loop")
+    ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (traffic-counter calibration)")
     args = ap.parse_args()
@@ -319,6 +429,9 @@ def main():
     # ------------------------------------------------------- batched solves
     if not args.no_batch:
         out["batched"] = batched_leg(args.batch_inst, args.batch_loop, dev)
+
+    if not args.no_warm:
+        out["warm_start"] = warm_start_leg(dev)
 
     # ---------------------------------------------------------- full order
     if not args.no_hdm:
