@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NTHR_PTS, 2) void k_points_batch(const BatchInst* I
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int inst = __builtin_amdgcn_readfirstlane(batch_owner(L.off, n_inst, item));
     const int k = item - L.off[inst];
-    points_eq_body<D, R>(s, I[inst].a, k, 0, threadIdx.x);
+    points_eq_body<D, R, true>(s, I[inst].a, k, 0, threadIdx.x);
     __syncthreads();
   }
 }
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(NTHR) void k_res_batch(const BatchInst* I, BatchLis
     a.tau = I[inst].zt + a.n;
     a.Ft = nullptr;
     a.PTR = nullptr;
-    eq_res_body<D, R>(s, a, k, 0, threadIdx.x);
+    eq_res_body<D, R, true>(s, a, k, 0, threadIdx.x);
     __syncthreads();
   }
 }

@@ -1515,6 +1515,7 @@ struct ift_mlp {
         *d_Y = nullptr, *d_dY = nullptr, *d_d1 = nullptr, *d_d2 = nullptr;
   double* d_lpart = nullptr;
   double* d_loss = nullptr;
+  float* d_wpart = nullptr;   // [MLP_WCHUNKS][out][in + 1] weight-gradient partials
 };
 
 static constexpr int MLP_LOSS_BLOCKS = 64;
@@ -1573,6 +1574,7 @@ extern "C" void ift_mlp_destroy(ift_mlp* p) {
   dfree(p->d_d2);
   dfree(p->d_lpart);
   dfree(p->d_loss);
+  dfree(p->d_wpart);
   delete p;
 }
 
@@ -1609,6 +1611,7 @@ extern "C" ift_status ift_mlp_create(int n_in, int hidden, int n_out, unsigned l
       dalloc(&p->d_m, p->n_par) != IFT_OK || dalloc(&p->d_v, p->n_par) != IFT_OK ||
       dalloc(&p->d_norm, nrm.size()) != IFT_OK || dalloc(&p->d_lpart, MLP_LOSS_BLOCKS) != IFT_OK ||
       dalloc(&p->d_loss, 1) != IFT_OK ||
+      dalloc(&p->d_wpart, (size_t)MLP_WCHUNKS * std::max(hidden, n_out) * (std::max(hidden, n_in) + 1)) != IFT_OK ||
       hipMemcpy(p->d_par, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->d_norm, nrm.data(), nrm.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(p->d_m, 0, p->n_par * sizeof(float)) != hipSuccess ||
@@ -1686,24 +1689,30 @@ static void mlp_backward(ift_mlp* p, int N, hipStream_t st) {
   int in, o;
   // layer 3: dY -> dW3, db3, dH2
   int off = mlp_offsets(p, 2, &in, &o);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st, (const float*)p->d_dY,
-                     (const float*)p->d_H2, in, o, N, gr + off, gr + off + o * in);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256), MLP_WCHUNKS), dim3(256), 0, st,
+                     (const float*)p->d_dY, (const float*)p->d_H2, in, o, N, p->d_wpart);
+  hipLaunchKernelGGL(k_mlp_wgrad_sum, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st,
+                     (const float*)p->d_wpart, in, o, gr + off, gr + off + o * in);
   hipLaunchKernelGGL(k_mlp_xgrad, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_dY,
                      par + off, in, o, N, p->d_d2);
   hipLaunchKernelGGL(k_mlp_act_bwd, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_A2,
                      p->d_d2, (long long)N * in);
   // layer 2
   off = mlp_offsets(p, 1, &in, &o);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st, (const float*)p->d_d2,
-                     (const float*)p->d_H1, in, o, N, gr + off, gr + off + o * in);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256), MLP_WCHUNKS), dim3(256), 0, st,
+                     (const float*)p->d_d2, (const float*)p->d_H1, in, o, N, p->d_wpart);
+  hipLaunchKernelGGL(k_mlp_wgrad_sum, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st,
+                     (const float*)p->d_wpart, in, o, gr + off, gr + off + o * in);
   hipLaunchKernelGGL(k_mlp_xgrad, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_d2,
                      par + off, in, o, N, p->d_d1);
   hipLaunchKernelGGL(k_mlp_act_bwd, dim3(nblk((long long)N * in, 256)), dim3(256), 0, st, (const float*)p->d_A1,
                      p->d_d1, (long long)N * in);
   // layer 1
   off = mlp_offsets(p, 0, &in, &o);
-  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st, (const float*)p->d_d1,
-                     (const float*)p->d_X, in, o, N, gr + off, gr + off + o * in);
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(nblk((long long)o * (in + 1), 256), MLP_WCHUNKS), dim3(256), 0, st,
+                     (const float*)p->d_d1, (const float*)p->d_X, in, o, N, p->d_wpart);
+  hipLaunchKernelGGL(k_mlp_wgrad_sum, dim3(nblk((long long)o * (in + 1), 256)), dim3(256), 0, st,
+                     (const float*)p->d_wpart, in, o, gr + off, gr + off + o * in);
 }
 
 extern "C" ift_status ift_mlp_loss_grad(ift_mlp* p, const float* X, const float* T, int N, float* grad, double* loss,

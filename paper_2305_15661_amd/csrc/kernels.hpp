@@ -139,7 +139,12 @@ IFT_DEV void lift_rows(ElemLDS<D, R>& s, const double* M, const double* v, int r
 // Lift U_e = Phi_e w, U_e' = Phi_e' w, x_e = X_e + Psi_e tau from the
 // gathered bases (rows are contiguous in global memory).  Ends with a
 // barrier: everything it wrote is visible to the block.
-template <class D, class R>
+// STAGED = false: one thread per row, a serial dot product from global
+// memory (best when the gathered bases are L2-resident, as when several
+// evaluation points share an element); STAGED = true: the products go
+// through LDS with independent coalesced loads (best when they come from
+// HBM, as in the batched solver).  Both end with a barrier.
+template <class D, class R, bool STAGED>
 IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid, int nthr) {
   const int n = a.n, m = a.m;
   const double* w = a.w + (long long)pt * n;
@@ -150,6 +155,25 @@ IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid, 
   const double* Xs = a.X_s + (long long)k * D::NXE;
   if (tid < 3) s.face[tid] = a.face[a.eq_elem[k] * 3 + tid];
   if (tid == 0) s.p.bad = 0;
+  if constexpr (!STAGED) {
+    for (int t = tid; t < D::NUE + D::NUN + D::NXE; t += nthr) {
+      if (t < D::NUE + D::NUN) {
+        const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += row[j] * w[j];
+        if (t < D::NUE) s.U[t] = R(acc);
+        else s.Un[t - D::NUE] = R(acc);
+      } else {
+        const int q = t - D::NUE - D::NUN;
+        double acc = Xs[q];
+        for (int j = 0; j < m; ++j) acc += Ps[(long long)q * m + j] * tau[j];
+        s.x[q] = R(acc);
+        s.X[q] = R(Xs[q]);
+      }
+    }
+    __syncthreads();
+    return;
+  }
   const int c1 = D::NUE * n, c2 = c1 + D::NUN * n, c3 = c2 + D::NXE * m;
   if (c3 <= ELEM_STAGE) {
     // one pass: every product of the three blocks, then every row sum
@@ -229,10 +253,10 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
 }
 
 // Point data of sampled element k at evaluation point pt (one block).
-template <class D, class R>
+template <class D, class R, bool STAGED = false>
 IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R>(s, tid, NTHR_PTS);
-  load_eq<D, R>(s, a, k, pt, tid, NTHR_PTS);
+  load_eq<D, R, STAGED>(s, a, k, pt, tid, NTHR_PTS);
   __syncthreads();
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
@@ -283,10 +307,10 @@ __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
 // ------------------------------------------------------------- EQ kernels
 // Residual and objective parts of sampled element k at evaluation point pt
 // (values only, one block).
-template <class D, class R>
+template <class D, class R, bool STAGED = false>
 IFT_DEV void eq_res_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R>(s, tid, NTHR);
-  load_eq<D, R>(s, a, k, pt, tid, NTHR);
+  load_eq<D, R, STAGED>(s, a, k, pt, tid, NTHR);
   __syncthreads();
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   phase_points<D, R, false>(s, tid, pc, R(a.kappa), R(a.eps));

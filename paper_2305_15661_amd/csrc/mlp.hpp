@@ -61,16 +61,34 @@ __global__ void k_mlp_act_bwd(const float* A, float* dH, long long cnt) {
   if (t < cnt) dH[t] *= gelu_prime_f(A[t]);
 }
 
-// dW[o][i] = sum_n dA[n][o] H[n][i] (i = in: db[o] = sum_n dA[n][o]), fixed order.
-__global__ void k_mlp_wgrad(const float* dA, const float* H, int in, int out, int N, float* dW, float* db) {
+// dW[o][i] = sum_n dA[n][o] H[n][i] (i = in: db[o] = sum_n dA[n][o]) in two
+// fixed-order stages: block (x, c) sums the samples of chunk c into
+// part[c][o][i]; k_mlp_wgrad_sum adds the chunks in order.
+constexpr int MLP_WCHUNKS = 32;
+
+__global__ void k_mlp_wgrad(const float* dA, const float* H, int in, int out, int N, float* part) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= out * (in + 1)) return;
+  const int cols = out * (in + 1);
+  if (t >= cols) return;
   const int o = t / (in + 1), i = t % (in + 1);
+  const int c = blockIdx.y;
+  const int per = (N + MLP_WCHUNKS - 1) / MLP_WCHUNKS;
+  const int n0 = c * per, n1 = min(N, n0 + per);
   float s = 0.f;
   if (i < in)
-    for (int n = 0; n < N; ++n) s += dA[(long long)n * out + o] * H[(long long)n * in + i];
+    for (int n = n0; n < n1; ++n) s += dA[(long long)n * out + o] * H[(long long)n * in + i];
   else
-    for (int n = 0; n < N; ++n) s += dA[(long long)n * out + o];
+    for (int n = n0; n < n1; ++n) s += dA[(long long)n * out + o];
+  part[(long long)c * cols + t] = s;
+}
+
+__global__ void k_mlp_wgrad_sum(const float* part, int in, int out, float* dW, float* db) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cols = out * (in + 1);
+  if (t >= cols) return;
+  float s = 0.f;
+  for (int c = 0; c < MLP_WCHUNKS; ++c) s += part[(long long)c * cols + t];
+  const int o = t / (in + 1), i = t % (in + 1);
   if (i < in) dW[(long long)o * in + i] = s;
   else db[o] = s;
 }
