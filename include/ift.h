@@ -190,6 +190,12 @@ typedef struct {
   double c1;           /* sufficient-decrease constant (1e-4)               */
   int max_backtrack;   /* step halvings (30)                                */
   double tol;          /* |S~| <= tol and |T~| <= tol (1e-8)                */
+  double tol_mix;      /* mixed-precision batches: gradient norms at which an
+                          instance continues in FP64 rounds (<= 0: the
+                          default max(tol, 1e-5))                          */
+  int max_backtrack_mixed; /* mixed-precision batches: halvings without
+                          decrease after which an instance continues in
+                          FP64 rounds (<= 0: the default 3)                 */
 } ift_gn_params;
 
 typedef struct {
@@ -199,7 +205,11 @@ typedef struct {
   int status;          /* an ift_status                                     */
   int iterations;      /* LM steps taken (batched solve; 0 or 1 for a step) */
   int fallback;        /* batched solve with a warm start: 1 if the plain
-                          start was used instead                           */
+                          start was used instead; 2 if the warm start was
+                          kept but its line search failed, so the solve
+                          restarted from the plain start                   */
+  int mixed_iterations; /* batched mixed-precision solve: LM steps taken in
+                          mixed-precision rounds (the rest ran in FP64)    */
 } ift_gn_info;
 
 /* One Levenberg-Marquardt step from z_n = (w, tau) (device, in/out):
@@ -259,7 +269,9 @@ ift_status eq_assemble_jacobian_batched(ift_batch* batch, const double* mu, cons
  * flags bit 1 = 1: z holds warm starts (e.g. from ift_mlp_predict); J~ is
  * evaluated (FP64) at each warm start and at the plain start, and an
  * instance starts from the plain start unless its warm start has the
- * smaller J~ (info.fallback = 1 then).
+ * smaller J~ (info.fallback = 1 then).  An instance that keeps its warm
+ * start and whose line search then fails restarts once from the plain start
+ * (info.fallback = 2; its iteration count continues).
  * The rounds (Jacobian assembly, LM step, two line-search trials) run in
  * replays of four captured rounds; after each replay the stream is
  * synchronised to read how many instances are still running.  Returns

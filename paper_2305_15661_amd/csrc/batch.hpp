@@ -29,6 +29,7 @@ struct BatchInst {
   double* z;          // [D]
   double* zt;         // [D] trial iterate
   double* dz;         // [D]
+  double* zp;         // [D] plain start kept for a restart (warm-started solves)
   double* H;          // [D * D]
   double* g;          // [D]
   double* part;       // fused partials [nblk][NH][256]
@@ -45,6 +46,9 @@ struct BatchState {
   int flag_or, n_bad, converged, n_bt_total;
   int prec;           // 1: mixed-precision rounds, 0: FP64 rounds
   int fallback;       // warm start replaced by the plain start
+  int it_mixed;       // LM steps taken in mixed-precision rounds
+  int restart;        // 1: a failed line search restarts from the plain start zp
+  int prec0;          // precision phase of a fresh start
   double J, J0, Jtrial, alpha, slope, nS, nT, alpha_acc;
 };
 
@@ -52,6 +56,7 @@ struct BatchParams {
   double lambda, c1, tol;
   double tol_mix;     // gradient norms at which a mixed-precision instance switches to FP64
   int max_backtrack, max_it;
+  int max_bt_mixed;   // halvings after which a mixed-precision instance switches to FP64
 };
 
 // Work lists of one phase.  off[q][i] = sum over active instances j < i of
@@ -214,6 +219,7 @@ __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState*
       st.alpha = 1.0;
       st.n_bt = 0;
       st.it += 1;
+      st.it_mixed += st.prec;
       st.state = BS_SEARCH;
     }
   }
@@ -228,21 +234,27 @@ __global__ __launch_bounds__(64) void k_trial_batch(const BatchInst* I, const Ba
   for (int i = threadIdx.x; i < bi.a.D; i += 64) bi.zt[i] = bi.z[i] + al * bi.dz[i];
 }
 
-// Residual and objective parts at the trial iterates (values only).
+// Residual and objective parts at the trial iterates (values only),
+// RV_SLOTS elements per block and pass, each lane group on its own item
+// (the items of one block may belong to different instances).
 template <class D, class R>
-__global__ __launch_bounds__(NTHR) void k_res_batch(const BatchInst* I, BatchLists L, int n_inst) {
-  __shared__ ElemLDS<D, R> s;
+__global__ __launch_bounds__(RV_THR) void k_res_batch(const BatchInst* I, BatchLists L, int n_inst) {
+  __shared__ ResShared<D, R> sh;
+  const int tid = threadIdx.x, g = tid / RV_LANES, j = tid % RV_LANES;
+  res_load_tab<D, R>(sh, tid);
+  __syncthreads();
   const int total = L.cnt[0];
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int inst = __builtin_amdgcn_readfirstlane(batch_owner(L.off, n_inst, item));
-    const int k = item - L.off[inst];
+  for (int base = blockIdx.x * RV_SLOTS; base < total; base += gridDim.x * RV_SLOTS) {
+    const int item = base + g;
+    const bool act = item < total;
+    const int inst = act ? batch_owner(L.off, n_inst, item) : 0;
+    const int k = act ? item - L.off[inst] : 0;
     EqArgs a = I[inst].a;
     a.w = I[inst].zt;
     a.tau = I[inst].zt + a.n;
     a.Ft = nullptr;
     a.PTR = nullptr;
-    eq_res_body<D, R, true>(s, a, k, 0, threadIdx.x);
-    __syncthreads();
+    res_group_body<D, R>(sh, sh.e[g], a, k, 0, act, j);
   }
 }
 
@@ -275,8 +287,14 @@ __global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState
   const BatchParams p = *P;
   const double Jt = so[0] ? __builtin_inf() : sj[0];
   const bool ok = Jt <= st.J + p.c1 * st.alpha * st.slope;
+  // the line search has failed for good: a warm-started instance restarts
+  // from the plain start instead of stopping
+  const bool fail = !ok && !(st.prec == 1 && st.n_bt >= p.max_bt_mixed) && st.n_bt >= p.max_backtrack;
+  const bool restart = fail && st.restart;
   if (ok)
     for (int i = t; i < bi.a.D; i += 256) bi.z[i] = bi.zt[i];
+  if (restart)
+    for (int i = t; i < bi.a.D; i += 256) bi.z[i] = bi.zp[i];
   __syncthreads();
   if (t == 0) {
     st.Jtrial = Jt;
@@ -284,10 +302,17 @@ __global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState
       st.alpha_acc = st.alpha;
       st.n_bt_total += st.n_bt;
       st.state = BS_JAC;
-    } else if (st.n_bt >= p.max_backtrack && st.prec == 1) {
+    } else if (st.prec == 1 && st.n_bt >= p.max_bt_mixed) {
       st.n_bt += 1;
       st.n_bt_total += st.n_bt;
       st.prec = 0;        // no decrease at mixed precision: continue in FP64
+      st.state = BS_JAC;
+    } else if (restart) {
+      st.n_bt += 1;
+      st.n_bt_total += st.n_bt;
+      st.restart = 0;
+      st.fallback = 2;
+      st.prec = st.prec0;
       st.state = BS_JAC;
     } else if (st.n_bt >= p.max_backtrack) {
       st.n_bt += 1;
@@ -380,11 +405,14 @@ __global__ __launch_bounds__(64) void k_start_select(const BatchInst* I, BatchSt
   const BatchInst& bi = I[inst];
   BatchState& st = S[inst];
   const bool warm = st.Jtrial < st.alpha;   // false for NaN or +inf warm objectives
-  if (!warm)
-    for (int j = threadIdx.x; j < bi.a.D; j += 64) bi.z[j] = bi.dz[j];
+  for (int j = threadIdx.x; j < bi.a.D; j += 64) {
+    if (warm) bi.zp[j] = bi.dz[j];
+    else bi.z[j] = bi.dz[j];
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     st.fallback = warm ? 0 : 1;
+    st.restart = warm ? 1 : 0;
     st.state = BS_JAC;
     st.Jtrial = 0.0;
     st.alpha = 0.0;
@@ -406,6 +434,9 @@ __global__ void k_batch_init(BatchState* S, int n_inst, int mixed) {
   st.n_bt_total = 0;
   st.prec = mixed;
   st.fallback = 0;
+  st.it_mixed = 0;
+  st.restart = 0;
+  st.prec0 = mixed;
   st.J = st.J0 = st.Jtrial = 0.0;
   st.alpha = st.slope = st.nS = st.nT = st.alpha_acc = 0.0;
   S[i] = st;

@@ -19,6 +19,8 @@
 //      element Jacobian [dR/dU_e | dR/dU_e' | dR/dx_e] (one thread per
 //      entry), assembled from the point Jacobians and the basis tables.
 #pragma once
+#include <type_traits>
+
 #include "physics.hpp"
 
 namespace ift {
@@ -171,9 +173,8 @@ IFT_DEV R eta_reference(const RefTab& t, const R* X) {
 
 // Volume point q: state, flux, cof(J) grad phi; seed = component seeded in
 // tangent mode (-1: none).  Returns the flux Jacobian column in Af.
-template <class D, class T, class R>
-IFT_DEV void vol_point(ElemLDS<D, R>& s, int q, int seed, const PhysConst& pc, R eps) {
-  const RefTab& t = s.tab;
+template <class D, class T, class R, class S>
+IFT_DEV void vol_point(const RefTab& t, S& s, int q, int seed, const PhysConst& pc, R eps) {
   T u[D::NC];
 #pragma unroll
   for (int c = 0; c < D::NC; ++c) {
@@ -205,27 +206,30 @@ IFT_DEV void vol_point(ElemLDS<D, R>& s, int q, int seed, const PhysConst& pc, R
       s.p.gp[q][i][1] = J00 * b - J01 * a;
     }
   }
-  if (seed >= 0) {
+  if constexpr (!std::is_same<T, R>::value) {
+    if (seed >= 0) {
 #pragma unroll
-    for (int c = 0; c < D::NC; ++c) {
-      s.p.Af[q][c][0][seed] = der(f[c][0]);
-      s.p.Af[q][c][1][seed] = der(f[c][1]);
+      for (int c = 0; c < D::NC; ++c) {
+        s.p.Af[q][c][0][seed] = der(f[c][0]);
+        s.p.Af[q][c][1][seed] = der(f[c][1]);
+      }
     }
   }
 }
 
 // Face point (f, q).  dir < 0: values only; dir in [0, NC): seed u-;
 // [NC, 2NC): seed u+ (interior faces); [2NC, 2NC+2): seed n~.
-template <class D, class T, class R>
-IFT_DEV void face_point(ElemLDS<D, R>& s, int f, int q, int dir, const PhysConst& pc) {
-  const RefTab& t = s.tab;
+template <class D, class T, class R, class S>
+IFT_DEV void face_point(const RefTab& t, S& s, int f, int q, int dir, const PhysConst& pc) {
   constexpr int NC = D::NC;
   constexpr int NE = D::NE;
   const int nb = s.face[f];
-  if (nb < 0 && dir >= NC && dir < 2 * NC) {
+  if constexpr (!std::is_same<T, R>::value) {
+    if (nb < 0 && dir >= NC && dir < 2 * NC) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s.p.dHp[f][q][c][dir - NC] = R(0);
-    return;
+      for (int c = 0; c < NC; ++c) s.p.dHp[f][q][c][dir - NC] = R(0);
+      return;
+    }
   }
   R tx = R(0), ty = R(0);
   T um[NC], up[NC];
@@ -256,13 +260,15 @@ IFT_DEV void face_point(ElemLDS<D, R>& s, int f, int q, int dir, const PhysConst
     if (!physical_state<D::PDE, T, R>(um, R(pc.gamma)) || !physical_state<D::PDE, T, R>(up, R(pc.gamma)))
       atomicOr(&s.p.bad, BAD_STATE);
   }
-  if (dir >= 0) {
+  if constexpr (!std::is_same<T, R>::value) {
+    if (dir >= 0) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      R d = der(H[c]);
-      if (dir < NC) s.p.dHm[f][q][c][dir] = d;
-      else if (dir < 2 * NC) s.p.dHp[f][q][c][dir - NC] = d;
-      else s.p.dHn[f][q][c][dir - 2 * NC] = d;
+      for (int c = 0; c < NC; ++c) {
+        R d = der(H[c]);
+        if (dir < NC) s.p.dHm[f][q][c][dir] = d;
+        else if (dir < 2 * NC) s.p.dHp[f][q][c][dir - NC] = d;
+        else s.p.dHn[f][q][c][dir - 2 * NC] = d;
+      }
     }
   }
 }
@@ -285,10 +291,10 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
     if (tid < ntask) {
       const int k = tid;
       if (k < D::NQV) {
-        vol_point<D, R, R>(s, k, -1, pc, eps);
+        vol_point<D, R, R>(s.tab, s, k, -1, pc, eps);
       } else if (k < D::NQV + 3 * D::NQF) {
         int r = k - D::NQV;
-        face_point<D, R, R>(s, r / D::NQF, r % D::NQF, -1, pc);
+        face_point<D, R, R>(s.tab, s, r / D::NQF, r % D::NQF, -1, pc);
       } else {
         Tan<R> eta = eta_elem<D, R>(s.tab, s.x, s.X, eps, -1);
         s.p.N = kappa * (eta.v - eta_reference<D, R>(s.tab, s.X));
@@ -304,10 +310,10 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
       if (k < nface) {
         int dir = k % (2 * D::NC + 2);
         int pt = k / (2 * D::NC + 2);
-        face_point<D, TT, R>(s, pt / D::NQF, pt % D::NQF, dir, pc);
+        face_point<D, TT, R>(s.tab, s, pt / D::NQF, pt % D::NQF, dir, pc);
       } else if (k < nface + nvol) {
         const int r = k - nface;
-        vol_point<D, TT, R>(s, r / D::NC, r % D::NC, pc, eps);
+        vol_point<D, TT, R>(s.tab, s, r / D::NC, r % D::NC, pc, eps);
       } else {
         int j = k - nvol - nface;
         TT eta = eta_elem<D, R>(s.tab, s.x, s.X, eps, j);
@@ -319,8 +325,8 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
 }
 
 // ----------------------------------------------------------------- phase C
-template <class D, class R>
-IFT_DEV R residual_entry_p(const Pts<D, R>& p, const RefTab& t, int r) {
+template <class D, class R, class P>
+IFT_DEV R residual_entry_p(const P& p, const RefTab& t, int r) {
   const int i = r / D::NC, c = r % D::NC;
   R v = R(0);
 #pragma unroll

@@ -847,7 +847,9 @@ struct EqLaunch {
       else fused<D, 3>();
     } else {
       ProfScope ps(IFT_PROF_EQ_RES, st);
-      hipLaunchKernelGGL((k_eq_res<D, R>), dim3(xcd_pad(a.n_s), n_pts), dim3(NTHR), 0, st, a);
+      const long long items = (long long)n_pts * a.n_s;
+      hipLaunchKernelGGL((k_eq_res16<D, R>), dim3((unsigned)((items + RV_SLOTS - 1) / RV_SLOTS)), dim3(RV_THR), 0, st,
+                         a, n_pts);
     }
   }
 };
@@ -1057,6 +1059,7 @@ struct ift_batch {
   int* d_cnt = nullptr;
   double* d_z = nullptr;
   double* d_zt = nullptr;
+  double* d_zp = nullptr;
   double* d_dz = nullptr;
   double* d_H = nullptr;
   double* d_g = nullptr;
@@ -1077,7 +1080,8 @@ static constexpr int BATCH_E_CAND[] = {4, 8, 16, 32};
 static constexpr int BATCH_T = 2;           // line-search trials per round
 static constexpr int BATCH_ROUNDS = 4;      // rounds per graph replay (one completion check each)
 static constexpr double BATCH_TOL_MIX = 1e-5;   // gradient norms that end the mixed-precision rounds
-static constexpr int BATCH_GRID_PTS = 2048, BATCH_GRID_RES = 2048, BATCH_GRID_FUSED = 1024;
+static constexpr int BATCH_BT_MIX = 3;          // mixed-precision halvings before the switch to FP64
+static constexpr int BATCH_GRID_PTS = 2048, BATCH_GRID_RES = 1024, BATCH_GRID_FUSED = 1024;
 
 static int batch_nblk(int n_s, int E) { return (n_s + 4 * E - 1) / (4 * E); }
 
@@ -1109,6 +1113,7 @@ static ift_status batch_upload(ift_batch* b) {
     bi.z = b->d_z + b->zoff[i];
     bi.zt = b->d_zt + b->zoff[i];
     bi.dz = b->d_dz + b->zoff[i];
+    bi.zp = b->d_zp + b->zoff[i];
     bi.H = b->d_H + b->hoff[i];
     bi.g = b->d_g + b->zoff[i];
     bi.nt = r->fused_nt;
@@ -1138,6 +1143,7 @@ extern "C" void ift_batch_destroy(ift_batch* b) {
   dfree(b->d_z);
   dfree(b->d_zt);
   dfree(b->d_dz);
+  dfree(b->d_zp);
   dfree(b->d_H);
   dfree(b->d_g);
   dfree(b->d_mu);
@@ -1185,6 +1191,7 @@ extern "C" ift_status ift_batch_create(int n_inst, ift_rom* const* roms, ift_bat
       (st = dalloc(&b->d_params, 1)) != IFT_OK || (st = dalloc(&b->d_off, 4 * (size_t)(n_inst + 1))) != IFT_OK ||
       (st = dalloc(&b->d_cnt, 4)) != IFT_OK || (st = dalloc(&b->d_z, Z)) != IFT_OK ||
       (st = dalloc(&b->d_zt, Z)) != IFT_OK || (st = dalloc(&b->d_dz, Z)) != IFT_OK ||
+      (st = dalloc(&b->d_zp, Z)) != IFT_OK ||
       (st = dalloc(&b->d_H, HH)) != IFT_OK || (st = dalloc(&b->d_g, Z)) != IFT_OK ||
       (st = dalloc(&b->d_mu, 2 * (size_t)n_inst)) != IFT_OK || (st = dalloc(&b->d_Jpart, NS)) != IFT_OK ||
       (st = dalloc(&b->d_flags, NS)) != IFT_OK || (st = dalloc(&b->d_part, part_max)) != IFT_OK ||
@@ -1253,7 +1260,7 @@ struct BatchLaunch {
     } else {
       hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
                          (const BatchState*)b->d_state, L, ni, (int)BS_SEARCH, want_prec, 0);
-      hipLaunchKernelGGL((k_res_batch<D, R>), dim3(BATCH_GRID_RES), dim3(NTHR), 0, st, (const BatchInst*)b->d_inst,
+      hipLaunchKernelGGL((k_res_batch<D, R>), dim3(BATCH_GRID_RES), dim3(RV_THR), 0, st, (const BatchInst*)b->d_inst,
                          L, ni);
     }
   }
@@ -1309,6 +1316,7 @@ __global__ void k_batch_info(const BatchState* S, int n_inst, ift_gn_info* info)
   o.status = st.state == BS_DONE ? st.status : IFT_ENOTCONV;   // (round cap reached; not expected)
   o.iterations = st.it;
   o.fallback = st.fallback;
+  o.mixed_iterations = st.it_mixed;
   info[i] = o;
 }
 
@@ -1392,7 +1400,7 @@ struct BatchResidual64 {
     BatchLists L{b->d_off, b->d_cnt};
     hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
                        (const BatchState*)b->d_state, L, b->n_inst, (int)BS_SEARCH, -1, 0);
-    hipLaunchKernelGGL((k_res_batch<D, double>), dim3(BATCH_GRID_RES), dim3(NTHR), 0, st,
+    hipLaunchKernelGGL((k_res_batch<D, double>), dim3(BATCH_GRID_RES), dim3(RV_THR), 0, st,
                        (const BatchInst*)b->d_inst, L, b->n_inst);
   }
 };
@@ -1417,7 +1425,10 @@ extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double*
   if (!b || !mu || !z || !prm || !info || max_it < 0) return IFT_EINVAL;
   if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
     return IFT_EINVAL;
-  BatchParams bp{prm->lambda, prm->c1, prm->tol, std::max(prm->tol, BATCH_TOL_MIX), prm->max_backtrack, max_it};
+  BatchParams bp{prm->lambda, prm->c1, prm->tol, prm->tol_mix > 0.0 ? std::max(prm->tol, prm->tol_mix)
+                                                                     : std::max(prm->tol, BATCH_TOL_MIX),
+                 prm->max_backtrack, max_it,
+                 std::min(prm->max_backtrack, prm->max_backtrack_mixed > 0 ? prm->max_backtrack_mixed : BATCH_BT_MIX)};
   HIP_TRY(hipMemcpyAsync(b->d_params, &bp, sizeof(bp), hipMemcpyHostToDevice, stream));
   ift_status s = batch_inputs(b, mu, z, stream);
   if (s != IFT_OK) return s;

@@ -1,7 +1,8 @@
 // Kernels of the element loop (full order and EQ-sampled), the deterministic
 // reductions, and the small dense solve of the Levenberg-Marquardt step.
 //
-// Values only (residual, objective): one fused kernel per element.
+// Values only (residual, objective): one fused kernel, sixteen lanes per
+// element.
 // With Jacobians: a point-physics kernel (one thread per quadrature point
 // and input direction, tangent arithmetic) writes each element's point
 // Jacobians to a workspace; an assembly kernel then builds the explicit
@@ -305,44 +306,143 @@ __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
 }
 
 // ------------------------------------------------------------- EQ kernels
-// Residual and objective parts of sampled element k at evaluation point pt
-// (values only, one block).
-template <class D, class R, bool STAGED = false>
-IFT_DEV void eq_res_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
-  load_tab<D, R>(s, tid, NTHR);
-  load_eq<D, R, STAGED>(s, a, k, pt, tid, NTHR);
-  __syncthreads();
-  const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
-  phase_points<D, R, false>(s, tid, pc, R(a.kappa), R(a.eps));
-  __syncthreads();
-  phase_assemble<D, R, false>(s, tid);
-  __syncthreads();
-  const double sq = a.srho[k];
-  const long long po = (long long)pt * a.nrows;
-  if (a.Ft && tid < D::NUE) a.Ft[po + (long long)k * D::NUE + tid] = sq * double(s.Re[tid]);
-  if (tid == 0) {
-    double acc = 0.0;
-    for (int r = 0; r < D::NUE; ++r) acc += double(s.Re[r]) * double(s.Re[r]);
-    acc += double(s.p.N) * double(s.p.N);
-    a.Jpart[(long long)pt * a.n_s + k] = 0.5 * a.rho[k] * acc;
-    a.flags[(long long)pt * a.n_s + k] = s.p.bad;
-    if (a.Ft) a.Ft[po + (long long)a.n_s * D::NUE + k] = sq * double(s.p.N);
-  }
-  if (a.PTR) {
-    for (int j = tid; j < a.n; j += NTHR) {
-      double acc = 0.0;
-      for (int r = 0; r < D::NUE; ++r) acc += a.Phi_s[((long long)k * D::NUE + r) * a.n + j] * double(s.Re[r]);
-      a.PTR[((long long)pt * a.n_s + k) * a.n + j] = a.rho[k] * acc;
-    }
-  }
-}
+// ------------------------------------------------------------------------
+// Values only, RV_LANES lanes per element: the 16 point tasks of an element
+// (volume points, face points, distortion) run on the lanes of one group,
+// so a block of RV_THR threads evaluates RV_SLOTS elements at once.  Each
+// element keeps only its lifted data, point values and residual in LDS.
+constexpr int RV_LANES = 16;
+constexpr int RV_THR = 256;
+constexpr int RV_SLOTS = RV_THR / RV_LANES;
 
 template <class D, class R>
-__global__ __launch_bounds__(NTHR) void k_eq_res(EqArgs a) {
-  __shared__ ElemLDS<D, R> s;
-  const int k = blockIdx.x, pt = blockIdx.y;
-  if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
-  eq_res_body<D, R>(s, a, k, pt, threadIdx.x);
+struct PtsVal {
+  R fv[D::NQV][D::NC][2];
+  R gp[D::NQV][D::NN][2];
+  R H[3][D::NQF][D::NC];
+  R N;
+  int bad;
+};
+
+template <class D, class R>
+struct ElemVal {
+  R U[D::NUE];
+  R Un[D::NUN];
+  R x[D::NXE];
+  R X[D::NXE];
+  int face[3];
+  PtsVal<D, R> p;
+  R Re[D::NUE];
+};
+
+template <class D, class R>
+struct ResShared {
+  RefTab tab;
+  ElemVal<D, R> e[RV_SLOTS];
+};
+
+template <class D, class R>
+IFT_DEV void res_load_tab(ResShared<D, R>& sh, int tid) {
+  const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
+  int* dst = reinterpret_cast<int*>(&sh.tab);
+  constexpr int nw = sizeof(RefTab) / sizeof(int);
+  for (int i = tid; i < nw; i += RV_THR) dst[i] = src[i];
+}
+
+// One element (k, pt) per lane group; `act` is false for the groups of a
+// block beyond the last item (they still reach every barrier).  j is the
+// lane within the group.  Writes Jpart, flags and, if requested, the Ft rows
+// and PTR, as the one-block-per-element kernel does.
+template <class D, class R>
+IFT_DEV void res_group_body(ResShared<D, R>& sh, ElemVal<D, R>& e, const EqArgs& a, int k, int pt, bool act,
+                            int j) {
+  static_assert(n_point_tasks<D, false>() <= RV_LANES, "one point task per lane");
+  const RefTab& tab = sh.tab;
+  const int n = a.n, m = a.m;
+  if (act) {
+    if (j < 3) e.face[j] = a.face[a.eq_elem[k] * 3 + j];
+    if (j == 0) e.p.bad = 0;
+    const double* w = a.w + (long long)pt * n;
+    const double* tau = a.tau + (long long)pt * m;
+    const double* Ph = a.Phi_s + (long long)k * D::NUE * n;
+    const double* Pn = a.Phin_s + (long long)k * D::NUN * n;
+    const double* Ps = a.Psi_s + (long long)k * D::NXE * m;
+    const double* Xs = a.X_s + (long long)k * D::NXE;
+    for (int t = j; t < D::NUE + D::NUN + D::NXE; t += RV_LANES) {
+      if (t < D::NUE + D::NUN) {
+        const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
+        double acc = 0.0;
+        for (int i = 0; i < n; ++i) acc += row[i] * w[i];
+        if (t < D::NUE) e.U[t] = R(acc);
+        else e.Un[t - D::NUE] = R(acc);
+      } else {
+        const int q = t - D::NUE - D::NUN;
+        double acc = Xs[q];
+        for (int i = 0; i < m; ++i) acc += Ps[(long long)q * m + i] * tau[i];
+        e.x[q] = R(acc);
+        e.X[q] = R(Xs[q]);
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
+    if (j < D::NQV) {
+      vol_point<D, R, R>(tab, e, j, -1, pc, R(a.eps));
+    } else if (j < D::NQV + 3 * D::NQF) {
+      const int r = j - D::NQV;
+      face_point<D, R, R>(tab, e, r / D::NQF, r % D::NQF, -1, pc);
+    } else if (j == D::NQV + 3 * D::NQF) {
+      const Tan<R> eta = eta_elem<D, R>(tab, e.x, e.X, R(a.eps), -1);
+      e.p.N = R(a.kappa) * (eta.v - eta_reference<D, R>(tab, e.X));
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const double sq = a.srho[k];
+    const long long po = (long long)pt * a.nrows;
+    double ss = 0.0;
+    for (int r = j; r < D::NUE; r += RV_LANES) {
+      const R v = residual_entry_p<D, R>(e.p, tab, r);
+      e.Re[r] = v;
+      ss += double(v) * double(v);
+      if (a.Ft) a.Ft[po + (long long)k * D::NUE + r] = sq * double(v);
+    }
+    // fixed-order tree over the group's lanes
+#pragma unroll
+    for (int o = RV_LANES / 2; o > 0; o >>= 1) ss += __shfl_xor(ss, o, RV_LANES);
+    if (j == 0) {
+      ss += double(e.p.N) * double(e.p.N);
+      a.Jpart[(long long)pt * a.n_s + k] = 0.5 * a.rho[k] * ss;
+      a.flags[(long long)pt * a.n_s + k] = e.p.bad;
+      if (a.Ft) a.Ft[po + (long long)a.n_s * D::NUE + k] = sq * double(e.p.N);
+    }
+  }
+  if (a.PTR) {
+    __syncthreads();
+    if (act) {
+      for (int c = j; c < n; c += RV_LANES) {
+        double acc = 0.0;
+        for (int r = 0; r < D::NUE; ++r) acc += a.Phi_s[((long long)k * D::NUE + r) * n + c] * double(e.Re[r]);
+        a.PTR[((long long)pt * a.n_s + k) * n + c] = a.rho[k] * acc;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Items pt * n_s + k over all evaluation points, RV_SLOTS per block.
+template <class D, class R>
+__global__ __launch_bounds__(RV_THR) void k_eq_res16(EqArgs a, int n_pts) {
+  __shared__ ResShared<D, R> sh;
+  const int tid = threadIdx.x, g = tid / RV_LANES, j = tid % RV_LANES;
+  res_load_tab<D, R>(sh, tid);
+  __syncthreads();
+  const long long total = (long long)n_pts * a.n_s;
+  const long long item = (long long)blockIdx.x * RV_SLOTS + g;
+  const bool act = item < total;
+  const int pt = act ? int(item / a.n_s) : 0, k = act ? int(item % a.n_s) : 0;
+  res_group_body<D, R>(sh, sh.e[g], a, k, pt, act, j);
 }
 
 // ------------------------------------------------------------------------

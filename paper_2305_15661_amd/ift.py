@@ -40,14 +40,14 @@ class ProblemDesc(ctypes.Structure):
 
 class GNParams(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("c1", ctypes.c_double), ("max_backtrack", ctypes.c_int),
-                ("tol", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("tol_mix", ctypes.c_double), ("max_backtrack_mixed", ctypes.c_int)]
 
 
 class GNInfo(ctypes.Structure):
     _fields_ = [("J_old", ctypes.c_double), ("J_new", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("norm_S", ctypes.c_double), ("norm_T", ctypes.c_double), ("n_backtrack", ctypes.c_int),
                 ("converged", ctypes.c_int), ("status", ctypes.c_int), ("iterations", ctypes.c_int),
-                ("fallback", ctypes.c_int)]
+                ("fallback", ctypes.c_int), ("mixed_iterations", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -295,7 +295,7 @@ class ROM:
 # numpy view of a device array of ift_gn_info records
 GN_INFO_DTYPE = np.dtype([("J_old", "<f8"), ("J_new", "<f8"), ("alpha", "<f8"), ("norm_S", "<f8"),
                           ("norm_T", "<f8"), ("n_backtrack", "<i4"), ("converged", "<i4"), ("status", "<i4"),
-                          ("iterations", "<i4"), ("fallback", "<i4"), ("_pad", "<i4")])
+                          ("iterations", "<i4"), ("fallback", "<i4"), ("mixed_iterations", "<i4")])
 assert GN_INFO_DTYPE.itemsize == ctypes.sizeof(GNInfo)
 
 
@@ -359,11 +359,14 @@ class Batch:
         _check(st, "eq_assemble_jacobian_batched")
 
     def solve(self, mu, z, info, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, max_it=50, graph=True,
-              warm=False, stream=None):
+              warm=False, tol_mix=0.0, max_backtrack_mixed=0, stream=None):
         """rom_gauss_newton_solve_batched; info: device uint8 tensor of
-        n_inst * GN_INFO_DTYPE.itemsize bytes (see info_array)."""
+        n_inst * GN_INFO_DTYPE.itemsize bytes (see info_array).  tol_mix and
+        max_backtrack_mixed (0: the library's defaults) steer the switch of
+        mixed-precision instances to FP64 rounds."""
         import torch
-        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol))
+        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol), float(tol_mix),
+                       int(max_backtrack_mixed))
         if info.numel() * info.element_size() != self.n_inst * GN_INFO_DTYPE.itemsize:
             raise ValueError("info has the wrong size")
         st = lib().rom_gauss_newton_solve_batched(self.handle, _ptr(mu, 2 * self.n_inst, torch.float64),

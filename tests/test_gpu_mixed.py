@@ -112,6 +112,11 @@ def test_mixed_batched_solve_within_1e6_of_fp64():
         out[p] = (b.unpack(z), b.info_array(info))
     zf, inf_f = out["fp64"]
     zm, inf_m = out["mixed"]
+    # an FP64 batch takes no mixed-precision steps; a mixed batch takes some,
+    # and at most as many as its iterations
+    assert np.all(inf_f["mixed_iterations"] == 0)
+    assert np.all(inf_m["mixed_iterations"] <= inf_m["iterations"])
+    assert np.sum(inf_m["mixed_iterations"]) > 0
     n_conv = 0
     for i in range(len(shapes)):
         _say(f"instance {i}: fp64 status {inf_f['status'][i]} its {inf_f['iterations'][i]}; "

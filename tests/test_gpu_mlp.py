@@ -140,3 +140,45 @@ def test_warm_start_selection_and_fallback():
     assert np.all(g["fallback"] == 1)
     assert np.array_equal(g["iterations"], plain["iterations"])
     assert rel(zg.cpu().numpy(), zsol.cpu().numpy()) < 1e-10
+
+
+def test_warm_start_restarts_from_plain_start_on_line_search_failure():
+    """With c1 = 0.9999 and three halvings no Gauss-Newton step passes the
+    sufficient-decrease test (for a quadratic model the full step achieves
+    half of the linear decrease, alpha = 1/8 achieves 15/16 of it), so every
+    line search fails: an instance that keeps its warm start restarts from
+    the plain start (fallback 2), fails again there and stops with
+    IFT_ELINESEARCH at the plain start after two steps."""
+    import torch
+    from paper_2305_15661_amd import ift
+    dev = torch.device("cuda:0")
+    base = synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=1)
+    rng = np.random.default_rng(32)
+    prob, roms, b, mus, starts = _batch(ift, dev, base, rng, [(20, 10, 40), (20, 10, 70), (20, 5, 55)])
+    mu = torch.tensor(np.stack(mus), dtype=torch.float64, device=dev)
+    z = b.pack(starts, dev)
+    info = b.info_buffer(dev)
+    _say("plain solve")
+    b.solve(mu, z, info, lam=1e-10, max_it=80)
+    torch.cuda.synchronize()
+    plain = b.info_array(info).copy()
+    # warm starts near the solutions: far lower objective than the plain start
+    zs = b.unpack(z)
+    warm = [zi * (1.0 + 1e-4 * rng.standard_normal(zi.size)) for zi in zs]
+    zw = b.pack(warm, dev)
+    _say("warm solve with a line search that always fails")
+    b.solve(mu, zw, info, lam=1e-10, c1=0.9999, max_backtrack=3, max_it=80, warm=True)
+    torch.cuda.synchronize()
+    o = b.info_array(info).copy()
+    out = b.unpack(zw)
+    checked = 0
+    for i in range(b.n_inst):
+        if not plain["converged"][i] or plain["iterations"][i] == 0:
+            continue
+        assert o["fallback"][i] == 2
+        assert o["status"][i] == -7          # IFT_ELINESEARCH
+        assert o["iterations"][i] == 2
+        assert o["n_backtrack"][i] == 8
+        assert rel(out[i], starts[i]) < 1e-10
+        checked += 1
+    assert checked >= 2
