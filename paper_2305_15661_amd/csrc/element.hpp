@@ -124,11 +124,12 @@ IFT_DEV T eta_point(const RefTab& t, int q, T J00, T J01, T J10, T J11, const R*
   R K00, K01, K10, K11;
   jac2<D, R, R>(t, q, X, K00, K01, K10, K11);
   R dK = K00 * K11 - K01 * K10;
-  R i00 = K11 / dK, i01 = -K01 / dK, i10 = -K10 / dK, i11 = K00 / dK;
+  const R idK = R(1) / dK;
+  R i00 = K11 * idK, i01 = -K01 * idK, i10 = -K10 * idK, i11 = K00 * idK;
   T G00 = J00 * i00 + J01 * i10, G01 = J00 * i01 + J01 * i11;
   T G10 = J10 * i00 + J11 * i10, G11 = J10 * i01 + J11 * i11;
   T nG2 = G00 * G00 + G01 * G01 + G10 * G10 + G11 * G11;
-  T g = (J00 * J11 - J01 * J10) / dK;
+  T g = (J00 * J11 - J01 * J10) * idK;
   T mx = val(g) >= eps ? g : mk<T, R>(eps);
   T r = nG2 / mx;
   return (R(t.wv[q]) * dK) * (r * r);

@@ -77,17 +77,19 @@ IFT_DEV void num_flux(const T* uL, const T* uR, T ntx, T nty, R gamma, T* H) {
     H[0] = R(0.5) * (fnL + fnR) - R(0.5) * a * (uR[0] - uL[0]);
   } else {
     const R gm1 = gamma - R(1);
-    T nmag = tsqrt(ntx * ntx + nty * nty);
-    T inm = R(1) / nmag;
+    T nmag, inm;
+    sqrt_rsqrt(ntx * ntx + nty * nty, nmag, inm);
     T nx = ntx * inm, ny = nty * inm;
     T rL = uL[0], rR = uR[0];
-    T irL = R(1) / rL, irR = R(1) / rR;
+    T sL, isL, sR, isR;
+    sqrt_rsqrt(rL, sL, isL);
+    sqrt_rsqrt(rR, sR, isR);
+    T irL = isL * isL, irR = isR * isR;
     T vxL = uL[1] * irL, vyL = uL[2] * irL, vxR = uR[1] * irR, vyR = uR[2] * irR;
     T pL = gm1 * (uL[3] - R(0.5) * rL * (vxL * vxL + vyL * vyL));
     T pR = gm1 * (uR[3] - R(0.5) * rR * (vxR * vxR + vyR * vyR));
     T qL = vxL * ntx + vyL * nty, qR = vxR * ntx + vyR * nty;   // v . n~
     T HL = (uL[3] + pL) * irL, HR = (uR[3] + pR) * irR;
-    T sL = tsqrt(rL), sR = tsqrt(rR);
     T iden = R(1) / (sL + sR);
     T rt = sL * sR;
     T ut = (sL * vxL + sR * vxR) * iden;
@@ -95,8 +97,9 @@ IFT_DEV void num_flux(const T* uL, const T* uR, T ntx, T nty, R gamma, T* H) {
     T Ht = (sL * HL + sR * HR) * iden;
     T q2 = ut * ut + vt * vt;
     T c2 = gm1 * (Ht - R(0.5) * q2);
-    T ct = tsqrt(c2);
-    T ic2 = R(1) / c2;
+    T ct, ict;
+    sqrt_rsqrt(c2, ct, ict);
+    T ic2 = ict * ict;
     T vn = ut * nx + vt * ny;
     T vtan = vt * nx - ut * ny;
     T dr = rR - rL, dp = pR - pL;
@@ -108,7 +111,7 @@ IFT_DEV void num_flux(const T* uL, const T* uR, T ntx, T nty, R gamma, T* H) {
     T a2 = dr - dp * ic2;
     T a3 = rt * dvt;
     T delta = R(0.1) * ct;
-    T i2d = R(0.5) / delta;
+    T i2d = R(5) * ict;   // 1 / (2 delta)
     T l1 = harten_abs<T, R>(vn - ct, delta, i2d) * a1;
     T l2 = harten_abs<T, R>(vn, delta, i2d);
     T l4 = harten_abs<T, R>(vn + ct, delta, i2d) * a4;
@@ -140,7 +143,8 @@ IFT_DEV void boundary_state(int tag, const T* um, T ntx, T nty, const PhysConst&
     } else if (tag == 2) {
       for (int c = 0; c < NC; ++c) up[c] = um[c];
     } else {
-      T inm = R(1) / tsqrt(ntx * ntx + nty * nty);
+      T nmag, inm;
+      sqrt_rsqrt(ntx * ntx + nty * nty, nmag, inm);
       T nx = ntx * inm, ny = nty * inm;
       T mn = um[1] * nx + um[2] * ny;
       up[0] = um[0];

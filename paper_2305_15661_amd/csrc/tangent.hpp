@@ -16,9 +16,12 @@ struct Tan {
 template <class R> IFT_DEV Tan<R> operator+(Tan<R> a, Tan<R> b) { return {a.v + b.v, a.d + b.d}; }
 template <class R> IFT_DEV Tan<R> operator-(Tan<R> a, Tan<R> b) { return {a.v - b.v, a.d - b.d}; }
 template <class R> IFT_DEV Tan<R> operator*(Tan<R> a, Tan<R> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+// Quotients take one reciprocal of the divisor (one division per quotient
+// and its derivative instead of two).
 template <class R> IFT_DEV Tan<R> operator/(Tan<R> a, Tan<R> b) {
-  R q = a.v / b.v;
-  return {q, (a.d - q * b.d) / b.v};
+  const R r = R(1) / b.v;
+  const R q = a.v * r;
+  return {q, (a.d - q * b.d) * r};
 }
 template <class R> IFT_DEV Tan<R> operator-(Tan<R> a) { return {-a.v, -a.d}; }
 template <class R> IFT_DEV Tan<R> operator+(Tan<R> a, R b) { return {a.v + b, a.d}; }
@@ -27,18 +30,39 @@ template <class R> IFT_DEV Tan<R> operator-(Tan<R> a, R b) { return {a.v - b, a.
 template <class R> IFT_DEV Tan<R> operator-(R a, Tan<R> b) { return {a - b.v, -b.d}; }
 template <class R> IFT_DEV Tan<R> operator*(Tan<R> a, R b) { return {a.v * b, a.d * b}; }
 template <class R> IFT_DEV Tan<R> operator*(R a, Tan<R> b) { return {a * b.v, a * b.d}; }
-template <class R> IFT_DEV Tan<R> operator/(Tan<R> a, R b) { return {a.v / b, a.d / b}; }
+template <class R> IFT_DEV Tan<R> operator/(Tan<R> a, R b) {
+  const R r = R(1) / b;
+  return {a.v * r, a.d * r};
+}
 template <class R> IFT_DEV Tan<R> operator/(R a, Tan<R> b) {
-  R q = a / b.v;
-  return {q, -q * b.d / b.v};
+  const R r = R(1) / b.v;
+  const R q = a * r;
+  return {q, -q * b.d * r};
 }
 
 template <class R> IFT_DEV Tan<R> tsqrt(Tan<R> a) {
-  R r = sqrt(a.v);
-  return {r, a.d / (R(2) * r)};
+  const R r = sqrt(a.v);
+  return {r, a.d * (R(0.5) / r)};
 }
 IFT_DEV double tsqrt(double a) { return sqrt(a); }
 IFT_DEV float tsqrt(float a) { return sqrtf(a); }
+
+// sqrt(x) and 1/sqrt(x) from one square root and one division:
+// d sqrt(x) = dx / (2 sqrt(x)), d x^(-1/2) = -(dx / (2 sqrt(x))) / x.
+template <class R> IFT_DEV void sqrt_rsqrt(Tan<R> x, Tan<R>& s, Tan<R>& is) {
+  const R r = R(1) / sqrt(x.v);
+  const R h = R(0.5) * x.d * r;
+  s = {x.v * r, h};
+  is = {r, -h * r * r};
+}
+IFT_DEV void sqrt_rsqrt(double x, double& s, double& is) {
+  is = 1.0 / sqrt(x);
+  s = x * is;
+}
+IFT_DEV void sqrt_rsqrt(float x, float& s, float& is) {
+  is = 1.0f / sqrtf(x);
+  s = x * is;
+}
 
 template <class R> IFT_DEV Tan<R> tabs(Tan<R> a) { return a.v >= R(0) ? a : Tan<R>{-a.v, -a.d}; }
 IFT_DEV double tabs(double a) { return a >= 0.0 ? a : -a; }
