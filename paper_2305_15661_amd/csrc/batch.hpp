@@ -67,9 +67,19 @@ struct BatchLists {
   int* cnt;   // [4]
 };
 
-// Instance that owns work item `item` of list q (upper bound search).
-IFT_DEV int batch_owner(const int* off, int n_inst, int item) {
-  int lo = 0, hi = n_inst;   // off[lo] <= item < off[hi]
+// Owner of `item` given the owner h of an earlier item of the same list:
+// probes h + 1, h + 2, h + 4, ... upwards, then bisects the bracket.
+IFT_DEV int batch_owner_from(const int* off, int n_inst, int item, int h) {
+  if (off[h + 1] > item) return h;
+  int lo = h + 1, hi = n_inst, step = 1;   // off[lo] <= item < off[hi]
+  while (lo + step < n_inst) {
+    if (off[lo + step] > item) {
+      hi = lo + step;
+      break;
+    }
+    lo += step;
+    step <<= 1;
+  }
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (off[mid] <= item) lo = mid;
@@ -133,8 +143,9 @@ template <class D, class R>
 __global__ __launch_bounds__(NTHR_PTS, 2) void k_points_batch(const BatchInst* I, BatchLists L, int n_inst) {
   __shared__ ElemLDS<D, R> s;
   const int total = L.cnt[0];
+  int inst = 0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int inst = __builtin_amdgcn_readfirstlane(batch_owner(L.off, n_inst, item));
+    inst = __builtin_amdgcn_readfirstlane(batch_owner_from(L.off, n_inst, item, inst));
     const int k = item - L.off[inst];
     points_eq_body<D, R, true>(s, I[inst].a, k, 0, threadIdx.x);
     __syncthreads();
@@ -148,8 +159,9 @@ __global__ __launch_bounds__(NTHR) void k_fused_batch(const BatchInst* I, BatchL
   fused_load_tab<D, R, NT>(sh, threadIdx.x);
   const int* off = L.off + NT * (n_inst + 1);
   const int total = L.cnt[NT];
+  int inst = 0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int inst = __builtin_amdgcn_readfirstlane(batch_owner(off, n_inst, item));
+    inst = __builtin_amdgcn_readfirstlane(batch_owner_from(off, n_inst, item, inst));
     const int blk = item - off[inst];
     const BatchInst& bi = I[inst];
     FusedArgs f;
@@ -244,10 +256,11 @@ __global__ __launch_bounds__(RV_THR) void k_res_batch(const BatchInst* I, BatchL
   res_load_tab<D, R>(sh, tid);
   __syncthreads();
   const int total = L.cnt[0];
+  int inst = 0;
   for (int base = blockIdx.x * RV_SLOTS; base < total; base += gridDim.x * RV_SLOTS) {
     const int item = base + g;
     const bool act = item < total;
-    const int inst = act ? batch_owner(L.off, n_inst, item) : 0;
+    if (act) inst = batch_owner_from(L.off, n_inst, item, inst);
     const int k = act ? item - L.off[inst] : 0;
     EqArgs a = I[inst].a;
     a.w = I[inst].zt;

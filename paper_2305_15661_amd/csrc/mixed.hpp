@@ -345,8 +345,9 @@ __global__ __launch_bounds__(NTHR) void k_fused_batch_mixed(const BatchInst* I, 
   fused_load_tab<D, float, NT>(sh, threadIdx.x);
   const int* off = L.off + NT * (n_inst + 1);
   const int total = L.cnt[NT];
+  int inst = 0;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
-    const int inst = __builtin_amdgcn_readfirstlane(batch_owner(off, n_inst, item));
+    inst = __builtin_amdgcn_readfirstlane(batch_owner_from(off, n_inst, item, inst));
     const int blk = item - off[inst];
     const BatchInst& bi = I[inst];
     FusedArgs f;
