@@ -196,6 +196,11 @@ typedef struct {
   int max_backtrack_mixed; /* mixed-precision batches: halvings without
                           decrease after which an instance continues in
                           FP64 rounds (<= 0: the default 3)                 */
+  int use_qr;          /* rom_gauss_newton_step: 1 solves the least-squares
+                          form of eq. (levmarq-step) by Householder QR of
+                          the stacked rows (needs n + m + 1 <= 48); 0 the
+                          normal equations (lmstep) by Cholesky.  Batched
+                          solves use the normal equations and reject 1.    */
 } ift_gn_params;
 
 typedef struct {
@@ -214,7 +219,9 @@ typedef struct {
 
 /* One Levenberg-Marquardt step from z_n = (w, tau) (device, in/out):
  * assemble at z_n; if |S~| <= tol and |T~| <= tol report convergence;
- * otherwise solve (H + lambda diag(0, I)) dz = -g (FP64 Cholesky) and
+ * otherwise solve (H + lambda diag(0, I)) dz = -g (FP64 Cholesky; with
+ * params->use_qr the equivalent least-squares problem by Householder QR of
+ * the stacked rows, whose workspace the first such call allocates) and
  * backtrack alpha = 1, 1/2, ... until J~(z + alpha dz) <= J~(z) +
  * c1 alpha g.dz, then overwrite (w, tau).  info is a HOST pointer.
  * Synchronises the stream. */

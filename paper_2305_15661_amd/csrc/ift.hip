@@ -83,6 +83,7 @@ struct ift_rom {
   double* d_Jtrial = nullptr;
   double* d_dz = nullptr;
   double* d_solve_out = nullptr;
+  double* d_qr[2] = {nullptr, nullptr};   // QR step: stacked triangles (allocated by the first QR step)
   double* d_wt = nullptr;
   double* d_tt = nullptr;
   int* d_nbad = nullptr;
@@ -546,6 +547,8 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   dfree(r->d_Jtrial);
   dfree(r->d_dz);
   dfree(r->d_solve_out);
+  dfree(r->d_qr[0]);
+  dfree(r->d_qr[1]);
   dfree(r->d_wt);
   dfree(r->d_tt);
   dfree(r->d_nbad);
@@ -633,6 +636,8 @@ static ift_status reserve_points(ift_rom* r, int max_pts) {
   dfree(r->d_Jtrial);
   dfree(r->d_dz);
   dfree(r->d_solve_out);
+  dfree(r->d_qr[0]);
+  dfree(r->d_qr[1]);
   dfree(r->d_wt);
   dfree(r->d_tt);
   dfree(r->d_nbad);
@@ -976,19 +981,72 @@ extern "C" ift_status eq_assemble_jacobian_batch(ift_rom* r, int n_pts, const do
   return gram(r, n_pts, H, g, Jobj, n_bad, stream);
 }
 
+// LM step of eq. (levmarq-step) by TSQR of the point-0 rows in d_Jt / d_Ft:
+// dz into d_dz and {failed, |S~|, |T~|, g . dz} into d_solve_out.  The
+// triangle buffers are allocated by the first call.
+static ift_status qr_step(ift_rom* r, double lambda, hipStream_t st) {
+  const int C = r->D + 1;
+  const long long rows1 = r->nrows + (lambda > 0.0 ? r->m : 0);
+  const long long nb1 = (rows1 + QR_RB - 1) / QR_RB;
+  if (!r->d_qr[0]) {
+    ift_status e;
+    if ((e = dalloc(&r->d_qr[0], (size_t)nb1 * C * C)) != IFT_OK || (e = dalloc(&r->d_qr[1], (size_t)nb1 * C * C)) != IFT_OK)
+      return e;
+  }
+  QrArgs q;
+  q.Jt = r->d_Jt;
+  q.Ft = r->d_Ft;
+  q.src = nullptr;
+  q.rows = (int)rows1;
+  q.nrows = (int)r->nrows;
+  q.D = r->D;
+  q.n = r->n;
+  q.C = C;
+  q.sqlam = std::sqrt(lambda);
+  q.g = r->d_g;
+  q.dz = r->d_dz;
+  q.out = r->d_solve_out;
+  long long nb = nb1;
+  for (int cur = 0;; cur ^= 1) {
+    q.dst = r->d_qr[cur];
+    hipLaunchKernelGGL(k_qr_rows, dim3((unsigned)nb), dim3(QR_RB), 0, st, q, nb == 1 ? 1 : 0);
+    HIP_TRY(hipGetLastError());
+    if (nb == 1) break;
+    q.src = r->d_qr[cur];
+    q.rows = (int)(nb * C);
+    nb = (q.rows + QR_RB - 1) / QR_RB;
+  }
+  return IFT_OK;
+}
+
 extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double* w, double* tau,
                                             const ift_gn_params* prm, ift_gn_info* info, hipStream_t stream) {
   if (!r || !w || (r->m > 0 && !tau) || !prm || !info || !finite_mu(r->prob, mu)) return IFT_EINVAL;
   if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
     return IFT_EINVAL;
+  if (prm->use_qr && r->D + 1 > QR_MAXC) return IFT_EINVAL;
   std::memset(info, 0, sizeof(*info));
   if (!lazy_points(r)) return IFT_ENOMEM;
   const int n = r->n, m = r->m, D = r->D;
-  ift_status s = eq_assemble_jacobian(r, mu, w, tau, r->d_J, r->d_g, r->d_H, nullptr, r->d_nbad, stream);
-  if (s != IFT_OK) return s;
-  hipLaunchKernelGGL(k_lm_solve, dim3(1), dim3(64), 0, stream, (const double*)r->d_H, (const double*)r->d_g, D, n,
-                     prm->lambda, r->d_dz, r->d_solve_out);
-  HIP_TRY(hipGetLastError());
+  ift_status s;
+  if (prm->use_qr) {
+    // the stacked rows of the point in the ROM's row workspace, then TSQR
+    EqArgs a = eq_args(r, mu, w, tau);
+    if (r->fused_nt > 0) {
+      s = eq_jacobian_fused(r, a, 1, r->d_H, r->d_g, r->d_J, r->d_nbad, true, stream);
+    } else {
+      s = dispatch_eq(r, a, true, 1, stream);
+      if (s == IFT_OK) s = gram(r, 1, r->d_H, r->d_g, r->d_J, r->d_nbad, stream);
+    }
+    if (s != IFT_OK) return s;
+    if ((s = qr_step(r, prm->lambda, stream)) != IFT_OK) return s;
+  } else {
+    s = eq_assemble_jacobian(r, mu, w, tau, r->d_J, r->d_g, r->d_H, nullptr, r->d_nbad, stream);
+    if (s != IFT_OK) return s;
+    hipLaunchKernelGGL(k_lm_solve, dim3(1), dim3(64), 0, stream, (const double*)r->d_H, (const double*)r->d_g, D, n,
+                       prm->lambda, r->d_dz, r->d_solve_out);
+    HIP_TRY(hipGetLastError());
+  }
   double so[4], J0;
   int fo;
   HIP_TRY(hipMemcpyAsync(so, r->d_solve_out, 4 * sizeof(double), hipMemcpyDeviceToHost, stream));
@@ -1422,7 +1480,7 @@ static void batch_select_start(ift_batch* b, hipStream_t st) {
 extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double* mu, double* z,
                                                      const ift_gn_params* prm, int max_it, ift_gn_info* info,
                                                      int flags, hipStream_t stream) {
-  if (!b || !mu || !z || !prm || !info || max_it < 0) return IFT_EINVAL;
+  if (!b || !mu || !z || !prm || !info || max_it < 0 || prm->use_qr) return IFT_EINVAL;
   if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
     return IFT_EINVAL;
   BatchParams bp{prm->lambda, prm->c1, prm->tol, prm->tol_mix > 0.0 ? std::max(prm->tol, prm->tol_mix)

@@ -1364,11 +1364,9 @@ __global__ void k_gather_rows(const double* src, int ncol, const long long* rows
 }
 
 // ------------------------------------------------- LM step (dense, FP64)
-// Solves (H + lambda diag(0_n, I_m)) dz = -g by Cholesky on one wavefront;
-// also returns |g_w|, |g_tau|, g.dz.  out: [0] status (0 ok, 1 not SPD),
-// [1] |S~|, [2] |T~|, [3] slope.
 // (H + lambda diag(0_n, I_m)) dz = -g by Cholesky in one wave (D <= 64);
-// out = {failed, |S~|, |T~|, g . dz}.  L holds 64 x 64 doubles of LDS.
+// out = {failed (H not SPD), |S~|, |T~|, g . dz}.  L holds 64 x 64 doubles
+// of LDS.
 IFT_DEV void lm_solve_body(const double* H, const double* g, int D, int n, double lambda, double* dz, double* out,
                            double* L, double* y, int& fail) {
   const int t = threadIdx.x;
@@ -1427,6 +1425,115 @@ __global__ __launch_bounds__(64) void k_lm_solve(const double* H, const double* 
   __shared__ double y[64];
   __shared__ int fail;
   lm_solve_body(H, g, D, n, lambda, dz, out, L, y, fail);
+}
+
+// ------------------------------------------ LM step by QR (TSQR, FP64)
+// The least-squares form of the step, eq. (levmarq-step):
+//   min | [J~_z; 0 sqrt(lambda) I] dz + [F~; 0] |,
+// by Householder QR of the stacked rows [J~_z | -F~] (nrows rows) and, for
+// lambda > 0, the m rows [0 .. sqrt(lambda) e_j .. | 0] of the mapping block.
+// Block b reduces rows [QR_RB b, QR_RB (b + 1)) (zero past the end) to the
+// C x C triangle R_b (C = D + 1: the columns of dz and the right-hand side);
+// the triangles are stacked and reduced again until one block remains, whose
+// triangle [R_z c; 0 rho] gives R_z dz = c by back substitution.  Every sum
+// runs in a fixed order.
+constexpr int QR_RB = 128;     // rows per block (one per thread)
+constexpr int QR_MAXC = 48;    // C = D + 1 <= QR_MAXC
+
+struct QrArgs {
+  const double* Jt;   // first level: J~_z [nrows][D] and F~ [nrows]
+  const double* Ft;
+  const double* src;  // later levels: stacked triangles [rows][C] (null on the first)
+  int rows;           // rows of this level
+  int nrows, D, n, C;
+  double sqlam;       // sqrt(lambda); the mapping rows exist when rows > nrows on the first level
+  double* dst;        // [gridDim.x][C][C] triangles
+  const double* g;    // last level: [D] gradient, for |S~|, |T~| and g . dz
+  double* dz;         // last level: [D]
+  double* out;        // last level: {failed, |S~|, |T~|, g . dz}
+};
+
+IFT_DEV double qr_wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(QR_RB) void k_qr_rows(QrArgs q, int last) {
+  __shared__ double A[QR_MAXC][QR_RB];         // column-major: A[c][row]
+  __shared__ double red[QR_RB / 64][QR_MAXC];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int C = q.C, D = q.D;
+  const long long r = (long long)blockIdx.x * QR_RB + t;
+  const bool in = r < q.rows;
+  if (q.src) {
+    for (int c = 0; c < C; ++c) A[c][t] = in ? q.src[r * C + c] : 0.0;
+  } else if (in && r < q.nrows) {
+    for (int c = 0; c < D; ++c) A[c][t] = q.Jt[r * D + c];
+    A[D][t] = -q.Ft[r];
+  } else {
+    const int j = in ? int(r - q.nrows) : -1;   // mapping row j: sqrt(lambda) in column n + j
+    for (int c = 0; c < C; ++c) A[c][t] = (j >= 0 && c == q.n + j) ? q.sqlam : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < C; ++j) {
+    // column j below the diagonal: sigma = |A[j:, j]|^2
+    const double x = A[j][t] * (t >= j ? 1.0 : 0.0);
+    const double s = qr_wave_sum(x * x);
+    if (lane == 0) red[wv][0] = s;
+    __syncthreads();
+    double sig = 0.0;
+    for (int w = 0; w < QR_RB / 64; ++w) sig += red[w][0];
+    const double ajj = A[j][j];
+    __syncthreads();
+    if (sig == 0.0) continue;   // already reduced (uniform)
+    // H = I - beta v v^T with v = A[j:, j] - alpha e_j, alpha = -sign(a_jj) sqrt(sigma),
+    // v^T v = 2 (sigma - a_jj alpha) > 0
+    const double al = -copysign(sqrt(sig), ajj);
+    const double beta = 1.0 / (sig - ajj * al);
+    const double v = A[j][t] * (t > j ? 1.0 : 0.0) + (ajj - al) * (t == j ? 1.0 : 0.0);
+    for (int c = j + 1; c < C; ++c) {
+      const double d = qr_wave_sum(v * A[c][t]);
+      if (lane == 0) red[wv][c] = d;
+    }
+    __syncthreads();
+    for (int c = j + 1; c < C; ++c) {
+      double d = 0.0;
+      for (int w = 0; w < QR_RB / 64; ++w) d += red[w][c];
+      A[c][t] -= beta * d * v;
+    }
+    if (t == j) A[j][j] = al;
+    __syncthreads();
+  }
+  if (!last) {
+    // row t of the block triangle: R[t][c] = A[c][t] for c >= t
+    if (t < C) {
+      double* o = q.dst + ((long long)blockIdx.x * C + t) * C;
+      for (int c = 0; c < C; ++c) o[c] = A[c][t] * (c >= t ? 1.0 : 0.0);
+    }
+    return;
+  }
+  if (t == 0) {
+    int fail = 0;
+    for (int i = D - 1; i >= 0; --i) {
+      double v = A[D][i];
+      for (int k = i + 1; k < D; ++k) v -= A[k][i] * q.dz[k];
+      const double rii = A[i][i];
+      if (!(fabs(rii) > 0.0)) fail = 1;
+      q.dz[i] = fail ? 0.0 : v / rii;
+    }
+    double sS = 0.0, sT = 0.0, sl = 0.0;
+    for (int i = 0; i < D; ++i) {
+      const double gi = q.g[i];
+      if (i < q.n) sS += gi * gi;
+      else sT += gi * gi;
+      sl += gi * q.dz[i];
+    }
+    q.out[0] = fail;
+    q.out[1] = sqrt(sS);
+    q.out[2] = sqrt(sT);
+    q.out[3] = sl;
+  }
 }
 
 __global__ void k_axpy2(const double* w, const double* tau, const double* dz, double alpha, int n, int m,

@@ -40,7 +40,8 @@ class ProblemDesc(ctypes.Structure):
 
 class GNParams(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("c1", ctypes.c_double), ("max_backtrack", ctypes.c_int),
-                ("tol", ctypes.c_double), ("tol_mix", ctypes.c_double), ("max_backtrack_mixed", ctypes.c_int)]
+                ("tol", ctypes.c_double), ("tol_mix", ctypes.c_double), ("max_backtrack_mixed", ctypes.c_int),
+                ("use_qr", ctypes.c_int)]
 
 
 class GNInfo(ctypes.Structure):
@@ -277,13 +278,14 @@ class ROM:
         _check(lib().rom_plain_start(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
                                      _stream(stream)), "rom_plain_start")
 
-    def gauss_newton_step(self, mu, w, tau, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, stream=None):
+    def gauss_newton_step(self, mu, w, tau, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, qr=False, stream=None):
         """rom_gauss_newton_step; returns (status, info dict).  Soft outcomes
         (converged / line-search failure / invalid point) are reported in the
-        status instead of raising."""
+        status instead of raising.  qr: solve the step by Householder QR of
+        the stacked rows instead of the normal equations."""
         import torch
         f64 = torch.float64
-        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol))
+        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol), 0.0, 0, int(bool(qr)))
         info = GNInfo()
         st = lib().rom_gauss_newton_step(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
                                          ctypes.byref(prm), ctypes.byref(info), _stream(stream))

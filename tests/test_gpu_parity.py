@@ -248,6 +248,49 @@ def test_gauss_newton_steps_parity(tiny_case):
         z = np.r_[wo, to]
 
 
+@pytest.mark.parametrize("which,lam", [("tiny_case", 0.0), ("euler_case", 1e-3)])
+def test_gauss_newton_qr_step_parity(which, lam, request):
+    """The least-squares form of the step (Householder QR of the stacked rows
+    [J~_z | -F~] and, for lambda > 0, the sqrt(lambda) rows of the mapping
+    block; the 20475-row benchmark case needs three reduction levels, these
+    cases one or two) against the oracle's lstsq step from the same z_n, and
+    against the normal-equation step of the GPU.  The two solvers agree to
+    about cond(H) * 1e-16 in the direction; the bound is 1e-13 cond(H)."""
+    import torch
+    from oracle import gn as ogn
+    case = request.getfixturevalue(which)
+    wl, d = case.wl, case.dev
+    n = wl.n
+    checked = 0
+    for k in range(4):
+        mu, w, tau = wl.mus[k], wl.w_eval[k], wl.tau_eval[k]
+        oj = case.orom.jacobian(mu, w, tau)
+        if not np.isfinite(oj["J"]):
+            continue
+        _say(f"qr step at point {k}")
+        wq, tq = _t(w, d), _t(tau, d)
+        st, info = case.rom.gauss_newton_step(mu, wq, tq, lam=lam, qr=True)
+        wc, tc = _t(w, d), _t(tau, d)
+        st_c, info_c = case.rom.gauss_newton_step(mu, wc, tc, lam=lam)
+        wo, to, oinfo = ogn.gn_step(case.orom, mu, w, tau, lam=lam, solver="qr")
+        assert oinfo["status"] in ("ok", "linesearch")
+        assert st == (0 if oinfo["status"] == "ok" else -7) and st_c == st
+        assert info["n_backtrack"] == oinfo["n_backtrack"] == info_c["n_backtrack"]
+        Hl = oj["H"].copy()
+        Hl[n:, n:] += lam * np.eye(Hl.shape[0] - n)
+        bound = max(1e-12, 1e-13 * np.linalg.cond(Hl))
+        z0 = np.r_[w, tau]
+        zo = np.r_[wo, to]
+        zq = np.r_[wq.cpu().numpy(), tq.cpu().numpy()]
+        zc = np.r_[wc.cpu().numpy(), tc.cpu().numpy()]
+        step = max(np.linalg.norm(zo - z0), 1e-300)
+        assert np.linalg.norm(zq - zo) <= bound * step + 1e-14 * np.linalg.norm(z0)
+        assert np.linalg.norm(zq - zc) <= bound * step + 1e-14 * np.linalg.norm(z0)
+        assert abs(info["norm_S"] - oinfo["norm_S"]) <= 1e-10 * max(oinfo["norm_S"], 1e-300)
+        checked += 1
+    assert checked >= 2
+
+
 def test_full_size_euler_samples(dev):
     """16384 P2 elements, 819 EQ elements, n = 20, m = 10 (the benchmark
     shape): full EQ assembly against the oracle, and the full-order residual
