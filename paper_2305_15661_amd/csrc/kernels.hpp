@@ -739,6 +739,48 @@ IFT_DEV void copy_pts_wave(Pts<D, R>* dst, const Pts<D, R>* src, int lane) {
   }
 }
 
+// One element's point data held in the registers of a wave (word i of the
+// array in lane i % 64), so that the next element's copy can be in flight
+// while the current element is assembled.  Words are 8 bytes where the
+// array size allows, else 4.
+template <class D, class R>
+struct PtsRegs {
+  using W = typename std::conditional<sizeof(Pts<D, R>) % 8 == 0, double, float>::type;
+  static constexpr int NW = sizeof(Pts<D, R>) / sizeof(W);
+  static constexpr int PER = (NW + 63) / 64;
+};
+
+template <class D, class R, class W, int PER>
+IFT_DEV void pts_regs_load(W (&r)[PER], const Pts<D, R>* src, int lane) {
+  constexpr int NW = PtsRegs<D, R>::NW;
+  static_assert(PER == PtsRegs<D, R>::PER, "one register array per element");
+  const W* s = reinterpret_cast<const W*>(src);
+#pragma unroll
+  for (int i = 0; i < PER - 1; ++i) r[i] = s[lane + 64 * i];
+  const int j = lane + 64 * (PER - 1);
+  r[PER - 1] = s[j < NW ? j : NW - 1];
+}
+
+template <class D, class R, class W, int PER>
+IFT_DEV void pts_regs_store(const W (&r)[PER], Pts<D, R>* dst, int lane) {
+  constexpr int NW = PtsRegs<D, R>::NW;
+  static_assert(PER == PtsRegs<D, R>::PER, "one register array per element");
+  W* d = reinterpret_cast<W*>(dst);
+#pragma unroll
+  for (int i = 0; i < PER - 1; ++i) d[lane + 64 * i] = r[i];
+  const int j = lane + 64 * (PER - 1);
+  if (j < NW) d[j] = r[PER - 1];
+}
+
+// Orders the LDS accesses of one wave around a hand-over between its lanes
+// (a wave's LDS instructions execute in order; this keeps the compiler from
+// moving accesses across the hand-over).
+IFT_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // LDS of the fused kernel: the reference table, one point-data slot per
 // wave (reused for the cross-wave reduction) and the flag counts.
 template <class D, class R, int NT>
@@ -783,12 +825,19 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
   const long long po = (long long)pt * a.nrows;
   const int kbeg = (blk * (NTHR / 64) + wave) * f.E;
   FusedSlot<D, R>& S = u.w[wave];
+  // each wave owns its slot: the point data of element k + 1 are loaded into
+  // registers while element k is assembled, and only the wave synchronises
+  const Pts<D, R>* pbase = reinterpret_cast<const Pts<D, R>*>(a.pts) + (long long)pt * a.n_s;
+  typename PtsRegs<D, R>::W pre[PtsRegs<D, R>::PER];
+  if (kbeg < a.n_s) pts_regs_load<D, R>(pre, pbase + kbeg, lane);
+  __syncthreads();   // the table is loaded
   for (int e = 0; e < f.E; ++e) {
     const int k = kbeg + e;
-    __syncthreads();   // the slot's previous contents are consumed; tab is loaded
-    if (k < a.n_s) copy_pts_wave<D, R>(&S.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), lane);
-    __syncthreads();
-    if (k >= a.n_s) continue;
+    if (k >= a.n_s) break;
+    wave_sync();     // the slot's previous contents are consumed
+    pts_regs_store<D, R>(pre, &S.p, lane);
+    if (e + 1 < f.E && k + 1 < a.n_s) pts_regs_load<D, R>(pre, pbase + k + 1, lane);
+    wave_sync();
     const Pts<D, R>& p = S.p;
     const double sq = a.srho[k];
     // residual entry of row `lane` (row nue: the distortion), distortion
@@ -1043,7 +1092,7 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
 }
 
 template <class D, class R, int NT>
-__global__ __launch_bounds__(NTHR) void k_eq_fused(EqArgs a, const double* Bw, const double* Bx, FusedArgs f) {
+__global__ __launch_bounds__(NTHR, NT == 1 ? 3 : (NT == 3 ? 2 : 1)) void k_eq_fused(EqArgs a, const double* Bw, const double* Bx, FusedArgs f) {
   __shared__ FusedShared<D, R, NT> sh;
   fused_load_tab<D, R, NT>(sh, threadIdx.x);
   fused_body<D, R, NT>(sh, a, Bw, Bx, f, blockIdx.x, blockIdx.y);
