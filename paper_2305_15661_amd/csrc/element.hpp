@@ -89,6 +89,7 @@ struct ElemLDS {
   int face[3];
   Pts<D, R> p;
   R Re[D::NUE];
+  R deta[D::NQV][5];   // per volume point: distortion integrand and its J-gradient
   union {
     R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
     double stage[ELEM_STAGE];   // staging of the lift (Jacobian not yet formed)
@@ -157,6 +158,37 @@ IFT_DEV Tan<R> eta_elem(const RefTab& t, const R* x, const R* X, R eps, int seed
     eta = eta + eta_point<D, TT, R>(t, q, a00, a01, a10, a11, X, eps);
   }
   return eta;
+}
+
+// Distortion integrand at volume point q and its gradient with respect to
+// J = dx/dxi, in plain arithmetic: out[0] = w_q det J0 (|G|_F^2 / max(g,
+// eps))^2 and out[1 + 2a + b] = its derivative along J[a][b].  With
+// r = |G|^2 / max(g, eps): d|G|^2/dJ = 2 G J0^{-T}, dg/dJ = cof(J) / det J0
+// (through the max only where g >= eps, as the tangent form).
+template <class D, class R>
+IFT_DEV void eta_point_grad(const RefTab& t, int q, const R* x, const R* X, R eps, R* out) {
+  R J00, J01, J10, J11, K00, K01, K10, K11;
+  jac2<D, R, R>(t, q, x, J00, J01, J10, J11);
+  jac2<D, R, R>(t, q, X, K00, K01, K10, K11);
+  const R dK = K00 * K11 - K01 * K10;
+  const R idK = R(1) / dK;
+  const R i00 = K11 * idK, i01 = -K01 * idK, i10 = -K10 * idK, i11 = K00 * idK;
+  const R G00 = J00 * i00 + J01 * i10, G01 = J00 * i01 + J01 * i11;
+  const R G10 = J10 * i00 + J11 * i10, G11 = J10 * i01 + J11 * i11;
+  const R nG2 = G00 * G00 + G01 * G01 + G10 * G10 + G11 * G11;
+  const R g = (J00 * J11 - J01 * J10) * idK;
+  const bool act = g >= eps;
+  const R mx = act ? g : eps;
+  const R imx = R(1) / mx;
+  const R r = nG2 * imx;
+  const R c = R(t.wv[q]) * dK;
+  out[0] = c * (r * r);
+  const R s = R(2) * c * r * imx;           // d eta / d |G|^2
+  const R sg = act ? -s * r * idK : R(0);   // d eta / d det J
+  out[1] = R(2) * s * (G00 * i00 + G01 * i01) + sg * J11;
+  out[2] = R(2) * s * (G00 * i10 + G01 * i11) - sg * J10;
+  out[3] = R(2) * s * (G10 * i00 + G11 * i01) - sg * J01;
+  out[4] = R(2) * s * (G10 * i10 + G11 * i11) + sg * J00;
 }
 
 template <class D, class R>
@@ -277,7 +309,7 @@ IFT_DEV void face_point(const RefTab& t, S& s, int f, int q, int dir, const Phys
 // Number of phase-B tasks per element.
 template <class D, bool JAC>
 constexpr int n_point_tasks() {
-  return JAC ? D::NQV * D::NC + 3 * D::NQF * (2 * D::NC + 2) + D::NXE : D::NQV + 3 * D::NQF + 1;
+  return JAC ? D::NQV * D::NC + 3 * D::NQF * (2 * D::NC + 2) + D::NQV : D::NQV + 3 * D::NQF + 1;
 }
 
 // Phase B: thread `tid` runs task `tid` (every launch has at least as many
@@ -316,12 +348,29 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
         const int r = k - nface;
         vol_point<D, TT, R>(s.tab, s, r / D::NC, r % D::NC, pc, eps);
       } else {
-        int j = k - nvol - nface;
-        TT eta = eta_elem<D, R>(s.tab, s.x, s.X, eps, j);
-        s.p.dN[j] = kappa * eta.d;
-        if (j == 0) s.p.N = kappa * (eta.v - eta_reference<D, R>(s.tab, s.X));
+        // distortion: one volume point per task, gathered by phase_distortion
+        eta_point_grad<D, R>(s.tab, k - nvol - nface, s.x, s.X, eps, s.deta[k - nvol - nface]);
       }
     }
+  }
+}
+
+// After phase B with Jacobians (and a barrier): N_e and dN_e/dx_e from the
+// per-point distortion terms, J = sum_k x_k grad_xi phi_k.
+template <class D, class R>
+IFT_DEV void phase_distortion(ElemLDS<D, R>& s, int tid, R kappa) {
+  if (tid < D::NXE) {
+    const int k = tid >> 1, a = tid & 1;
+    R v = R(0);
+#pragma unroll
+    for (int q = 0; q < D::NQV; ++q)
+      v += s.deta[q][1 + 2 * a] * R(s.tab.dphiv[q][k][0]) + s.deta[q][2 + 2 * a] * R(s.tab.dphiv[q][k][1]);
+    s.p.dN[tid] = kappa * v;
+  } else if (tid == D::NXE) {
+    R eta = R(0);
+#pragma unroll
+    for (int q = 0; q < D::NQV; ++q) eta += s.deta[q][0];
+    s.p.N = kappa * (eta - eta_reference<D, R>(s.tab, s.X));
   }
 }
 

@@ -250,6 +250,8 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
   phase_points<D, R, true>(s, tid, a.pc, R(a.kappa), R(a.eps));
   __syncthreads();
+  phase_distortion<D, R>(s, tid, R(a.kappa));
+  __syncthreads();
   copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + e, &s.p, tid, NTHR_PTS);
 }
 
@@ -262,6 +264,8 @@ IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, in
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
   phase_points<D, R, true>(s, tid, pc, R(a.kappa), R(a.eps));
+  __syncthreads();
+  phase_distortion<D, R>(s, tid, R(a.kappa));
   __syncthreads();
   copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s.p, tid, NTHR_PTS);
 }
