@@ -201,6 +201,10 @@ typedef struct {
                           the stacked rows (needs n + m + 1 <= 48); 0 the
                           normal equations (lmstep) by Cholesky.  Batched
                           solves use the normal equations and reject 1.    */
+  int w_only;          /* rom_gauss_newton_step: 1 steps in w with tau held
+                          (dz_tau = 0) and converges on |S~| <= tol alone:
+                          the iteration of the paper's initialisation
+                          w0 = argmin_w |R~(w, tau0)| (remark rem:solver)  */
 } ift_gn_params;
 
 typedef struct {
@@ -215,6 +219,8 @@ typedef struct {
                           restarted from the plain start                   */
   int mixed_iterations; /* batched mixed-precision solve: LM steps taken in
                           mixed-precision rounds (the rest ran in FP64)    */
+  int presolve_iterations; /* batched solve with the w-only initialisation:
+                          steps taken in w only                           */
 } ift_gn_info;
 
 /* One Levenberg-Marquardt step from z_n = (w, tau) (device, in/out):
@@ -279,6 +285,15 @@ ift_status eq_assemble_jacobian_batched(ift_batch* batch, const double* mu, cons
  * smaller J~ (info.fallback = 1 then).  An instance that keeps its warm
  * start and whose line search then fails restarts once from the plain start
  * (info.fallback = 2; its iteration count continues).
+ * flags bit 2 = 1: the paper's initialisation (remark rem:solver): each
+ * instance first takes steps in w with tau held at its start value (the
+ * w_only step of rom_gauss_newton_step) until |S~| <= tol (the mixed-phase
+ * tolerance in mixed rounds) or its line search fails, then full steps;
+ * all steps count towards max_it (info.presolve_iterations: the w steps).
+ * flags bit 3 = 1: adaptive lambda per instance, starting from
+ * params->lambda: lambda / 10 after a step accepted at alpha = 1 (0 below
+ * 1e-12), max(10 lambda, 1e-8) after a step accepted at alpha < 1.
+ * params->use_qr and params->w_only must be 0.
  * The rounds (Jacobian assembly, LM step, two line-search trials) run in
  * replays of four captured rounds; after each replay the stream is
  * synchronised to read how many instances are still running.  Returns

@@ -49,6 +49,9 @@ struct BatchState {
   int it_mixed;       // LM steps taken in mixed-precision rounds
   int restart;        // 1: a failed line search restarts from the plain start zp
   int prec0;          // precision phase of a fresh start
+  int wonly;          // 1: initialisation steps in w with tau held
+  int it_w;           // steps taken in w only
+  double lam;         // LM weight of the next step
   double J, J0, Jtrial, alpha, slope, nS, nT, alpha_acc;
 };
 
@@ -57,6 +60,7 @@ struct BatchParams {
   double tol_mix;     // gradient norms at which a mixed-precision instance switches to FP64
   int max_backtrack, max_it;
   int max_bt_mixed;   // halvings after which a mixed-precision instance switches to FP64
+  int adapt;          // 1: lambda / 10 after a full step, max(10 lambda, 1e-8) after a shortened one
 };
 
 // Work lists of one phase.  off[q][i] = sum over active instances j < i of
@@ -208,13 +212,40 @@ __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState*
     }
     return;
   }
-  lm_solve_body(bi.H, bi.g, D, n, p.lambda, bi.dz, out, L, y, fail);
+  // initialisation steps (remark rem:solver): w only, tau held, until
+  // |S~| meets the tolerance of the precision phase; then the full step at
+  // the same iterate
+  const int wonly = st.wonly;
+  const int prec = st.prec;
+  lm_solve_body(bi.H, bi.g, D, n, wonly ? n : D, st.lam, bi.dz, out, L, y, fail);
+  bool w_step = wonly != 0;
+  if (wonly && out[1] <= (prec == 1 ? p.tol_mix : p.tol)) {
+    lm_solve_body(bi.H, bi.g, D, n, D, st.lam, bi.dz, out, L, y, fail);
+    w_step = false;
+  }
   if (threadIdx.x == 0) {
     if (st.it == 0 && st.prec == 1) st.J0 = J;
     if (st.it == 0 && st.prec == 0 && st.J0 == 0.0) st.J0 = J;
     st.nS = out[1];
     st.nT = out[2];
-    if (st.prec == 1 && out[1] <= p.tol_mix && out[2] <= p.tol_mix) {
+    if (!w_step) st.wonly = 0;
+    if (w_step) {
+      if (st.it >= p.max_it) {
+        st.status = IFT_ENOTCONV;
+        st.state = BS_DONE;
+      } else if (out[0] != 0.0) {
+        st.status = IFT_ESINGULAR;
+        st.state = BS_DONE;
+      } else {
+        st.slope = out[3];
+        st.alpha = 1.0;
+        st.n_bt = 0;
+        st.it += 1;
+        st.it_w += 1;
+        st.it_mixed += st.prec;
+        st.state = BS_SEARCH;
+      }
+    } else if (st.prec == 1 && out[1] <= p.tol_mix && out[2] <= p.tol_mix) {
       st.prec = 0;   // refine in FP64 from here; the state stays JAC
     } else if (out[1] <= p.tol && out[2] <= p.tol && st.prec == 0) {
       st.converged = 1;
@@ -302,7 +333,7 @@ __global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState
   const bool ok = Jt <= st.J + p.c1 * st.alpha * st.slope;
   // the line search has failed for good: a warm-started instance restarts
   // from the plain start instead of stopping
-  const bool fail = !ok && !(st.prec == 1 && st.n_bt >= p.max_bt_mixed) && st.n_bt >= p.max_backtrack;
+  const bool fail = !ok && !st.wonly && !(st.prec == 1 && st.n_bt >= p.max_bt_mixed) && st.n_bt >= p.max_backtrack;
   const bool restart = fail && st.restart;
   if (ok)
     for (int i = t; i < bi.a.D; i += 256) bi.z[i] = bi.zt[i];
@@ -314,6 +345,15 @@ __global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState
     if (ok) {
       st.alpha_acc = st.alpha;
       st.n_bt_total += st.n_bt;
+      st.state = BS_JAC;
+      if (p.adapt) {
+        if (st.alpha == 1.0) st.lam = st.lam * 0.1 < 1e-12 ? 0.0 : st.lam * 0.1;
+        else st.lam = fmax(10.0 * st.lam, 1e-8);
+      }
+    } else if (st.wonly && st.n_bt >= p.max_backtrack) {
+      st.n_bt += 1;
+      st.n_bt_total += st.n_bt;
+      st.wonly = 0;       // the initialisation ends here; full steps from this iterate
       st.state = BS_JAC;
     } else if (st.prec == 1 && st.n_bt >= p.max_bt_mixed) {
       st.n_bt += 1;
@@ -433,7 +473,7 @@ __global__ __launch_bounds__(64) void k_start_select(const BatchInst* I, BatchSt
 }
 
 // Fresh state for every instance.
-__global__ void k_batch_init(BatchState* S, int n_inst, int mixed) {
+__global__ void k_batch_init(BatchState* S, int n_inst, int mixed, int presolve, double lambda) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_inst) return;
   BatchState st;
@@ -450,6 +490,9 @@ __global__ void k_batch_init(BatchState* S, int n_inst, int mixed) {
   st.it_mixed = 0;
   st.restart = 0;
   st.prec0 = mixed;
+  st.wonly = presolve;
+  st.it_w = 0;
+  st.lam = lambda;
   st.J = st.J0 = st.Jtrial = 0.0;
   st.alpha = st.slope = st.nS = st.nT = st.alpha_acc = 0.0;
   S[i] = st;

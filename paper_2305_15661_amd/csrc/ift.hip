@@ -984,14 +984,17 @@ extern "C" ift_status eq_assemble_jacobian_batch(ift_rom* r, int n_pts, const do
 // LM step of eq. (levmarq-step) by TSQR of the point-0 rows in d_Jt / d_Ft:
 // dz into d_dz and {failed, |S~|, |T~|, g . dz} into d_solve_out.  The
 // triangle buffers are allocated by the first call.
-static ift_status qr_step(ift_rom* r, double lambda, hipStream_t st) {
-  const int C = r->D + 1;
-  const long long rows1 = r->nrows + (lambda > 0.0 ? r->m : 0);
+static ift_status qr_step(ift_rom* r, double lambda, bool w_only, hipStream_t st) {
+  const int ns = w_only ? r->n : r->D;
+  const int C = ns + 1;
+  const long long rows1 = r->nrows + (lambda > 0.0 && !w_only ? r->m : 0);
   const long long nb1 = (rows1 + QR_RB - 1) / QR_RB;
   if (!r->d_qr[0]) {
+    // sized for the full step with mapping rows, the largest case
+    const long long nbmax = (r->nrows + r->m + QR_RB - 1) / QR_RB;
+    const size_t sz = (size_t)nbmax * (r->D + 1) * (r->D + 1);
     ift_status e;
-    if ((e = dalloc(&r->d_qr[0], (size_t)nb1 * C * C)) != IFT_OK || (e = dalloc(&r->d_qr[1], (size_t)nb1 * C * C)) != IFT_OK)
-      return e;
+    if ((e = dalloc(&r->d_qr[0], sz)) != IFT_OK || (e = dalloc(&r->d_qr[1], sz)) != IFT_OK) return e;
   }
   QrArgs q;
   q.Jt = r->d_Jt;
@@ -1001,6 +1004,7 @@ static ift_status qr_step(ift_rom* r, double lambda, hipStream_t st) {
   q.nrows = (int)r->nrows;
   q.D = r->D;
   q.n = r->n;
+  q.ns = ns;
   q.C = C;
   q.sqlam = std::sqrt(lambda);
   q.g = r->d_g;
@@ -1039,12 +1043,12 @@ extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double
       if (s == IFT_OK) s = gram(r, 1, r->d_H, r->d_g, r->d_J, r->d_nbad, stream);
     }
     if (s != IFT_OK) return s;
-    if ((s = qr_step(r, prm->lambda, stream)) != IFT_OK) return s;
+    if ((s = qr_step(r, prm->lambda, prm->w_only != 0, stream)) != IFT_OK) return s;
   } else {
     s = eq_assemble_jacobian(r, mu, w, tau, r->d_J, r->d_g, r->d_H, nullptr, r->d_nbad, stream);
     if (s != IFT_OK) return s;
     hipLaunchKernelGGL(k_lm_solve, dim3(1), dim3(64), 0, stream, (const double*)r->d_H, (const double*)r->d_g, D, n,
-                       prm->lambda, r->d_dz, r->d_solve_out);
+                       prm->w_only ? n : D, prm->lambda, r->d_dz, r->d_solve_out);
     HIP_TRY(hipGetLastError());
   }
   double so[4], J0;
@@ -1061,7 +1065,7 @@ extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double
     info->status = (fo & BAD_GEOM) ? IFT_EBADMESH : IFT_ENONPHYS;
     return (ift_status)info->status;
   }
-  if (so[1] <= prm->tol && so[2] <= prm->tol) {
+  if (so[1] <= prm->tol && (prm->w_only || so[2] <= prm->tol)) {
     info->converged = 1;
     info->status = IFT_OK;
     return IFT_OK;
@@ -1375,6 +1379,7 @@ __global__ void k_batch_info(const BatchState* S, int n_inst, ift_gn_info* info)
   o.iterations = st.it;
   o.fallback = st.fallback;
   o.mixed_iterations = st.it_mixed;
+  o.presolve_iterations = st.it_w;
   info[i] = o;
 }
 
@@ -1390,7 +1395,7 @@ extern "C" ift_status eq_assemble_jacobian_batched(ift_batch* b, const double* m
   ift_status s = batch_inputs(b, mu, z, stream);
   if (s != IFT_OK) return s;
   hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
-                     b->precision == IFT_MIXED_BF16 ? 1 : 0);
+                     b->precision == IFT_MIXED_BF16 ? 1 : 0, 0, 0.0);
   {
     ProfScope ps(IFT_PROF_EQ_JAC, stream);
     batch_phase(b, 0, stream);
@@ -1423,7 +1428,7 @@ extern "C" ift_status ift_batch_autotune(ift_batch* b, const double* mu, const d
     float tot = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
       hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
-                     b->precision == IFT_MIXED_BF16 ? 1 : 0);
+                         b->precision == IFT_MIXED_BF16 ? 1 : 0, 0, 0.0);
       HIP_TRY(hipEventRecord(e0, stream));
       batch_phase(b, 0, stream);
       HIP_TRY(hipEventRecord(e1, stream));
@@ -1480,13 +1485,14 @@ static void batch_select_start(ift_batch* b, hipStream_t st) {
 extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double* mu, double* z,
                                                      const ift_gn_params* prm, int max_it, ift_gn_info* info,
                                                      int flags, hipStream_t stream) {
-  if (!b || !mu || !z || !prm || !info || max_it < 0 || prm->use_qr) return IFT_EINVAL;
+  if (!b || !mu || !z || !prm || !info || max_it < 0 || prm->use_qr || prm->w_only) return IFT_EINVAL;
   if (!(prm->lambda >= 0.0) || !(prm->c1 > 0.0 && prm->c1 < 1.0) || prm->max_backtrack < 0 || !(prm->tol >= 0.0))
     return IFT_EINVAL;
   BatchParams bp{prm->lambda, prm->c1, prm->tol, prm->tol_mix > 0.0 ? std::max(prm->tol, prm->tol_mix)
                                                                      : std::max(prm->tol, BATCH_TOL_MIX),
                  prm->max_backtrack, max_it,
-                 std::min(prm->max_backtrack, prm->max_backtrack_mixed > 0 ? prm->max_backtrack_mixed : BATCH_BT_MIX)};
+                 std::min(prm->max_backtrack, prm->max_backtrack_mixed > 0 ? prm->max_backtrack_mixed : BATCH_BT_MIX),
+                 (flags & 8) ? 1 : 0};
   HIP_TRY(hipMemcpyAsync(b->d_params, &bp, sizeof(bp), hipMemcpyHostToDevice, stream));
   ift_status s = batch_inputs(b, mu, z, stream);
   if (s != IFT_OK) return s;
@@ -1509,11 +1515,13 @@ extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double*
     }
   }
   hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
-                     b->precision == IFT_MIXED_BF16 ? 1 : 0);
+                     b->precision == IFT_MIXED_BF16 ? 1 : 0, (flags & 4) ? 1 : 0, prm->lambda);
   if (flags & 2) batch_select_start(b, stream);
   // every instance finishes within (max_it + 1) Jacobian rounds, each
   // followed by at most ceil((max_backtrack + 1) / T) rounds of trials
-  const long long cap = (long long)(max_it + 1) * (2 + (prm->max_backtrack + 1 + BATCH_T - 1) / BATCH_T);
+  // (a few more for the rounds that take no step: the end of the w-only
+  // initialisation, the switch to FP64, a restart)
+  const long long cap = (long long)(max_it + 4) * (2 + (prm->max_backtrack + 1 + BATCH_T - 1) / BATCH_T);
   for (long long done = 0; done < cap; done += BATCH_ROUNDS) {
     if (graph) HIP_TRY(hipGraphLaunch(b->exec, stream));
     else batch_rounds(b, BATCH_ROUNDS, stream);

@@ -1417,21 +1417,22 @@ __global__ void k_gather_rows(const double* src, int ncol, const long long* rows
 }
 
 // ------------------------------------------------- LM step (dense, FP64)
-// (H + lambda diag(0_n, I_m)) dz = -g by Cholesky in one wave (D <= 64);
-// out = {failed (H not SPD), |S~|, |T~|, g . dz}.  L holds 64 x 64 doubles
-// of LDS.
-IFT_DEV void lm_solve_body(const double* H, const double* g, int D, int n, double lambda, double* dz, double* out,
-                           double* L, double* y, int& fail) {
+// (H + lambda diag(0_n, I_m)) dz = -g by Cholesky in one wave (D <= 64),
+// over the leading ns unknowns (ns = D: the full step; ns = n: a step in w
+// with tau fixed, dz_tau = 0); out = {failed (not SPD), |S~|, |T~|, g . dz}.
+// L holds 64 x 64 doubles of LDS.
+IFT_DEV void lm_solve_body(const double* H, const double* g, int D, int n, int ns, double lambda, double* dz,
+                           double* out, double* L, double* y, int& fail) {
   const int t = threadIdx.x;
-  for (int i = t; i < D * D; i += 64) {
-    const int r = i / D, c = i % D;
-    double v = H[i];
+  for (int i = t; i < ns * ns; i += 64) {
+    const int r = i / ns, c = i % ns;
+    double v = H[r * D + c];
     if (r == c && r >= n) v += lambda;
     L[r * 64 + c] = v;
   }
   if (t == 0) fail = 0;
   __syncthreads();
-  for (int j = 0; j < D; ++j) {
+  for (int j = 0; j < ns; ++j) {
     if (t == 0) {
       double s = L[j * 64 + j];
       for (int k = 0; k < j; ++k) s -= L[j * 64 + k] * L[j * 64 + k];
@@ -1439,7 +1440,7 @@ IFT_DEV void lm_solve_body(const double* H, const double* g, int D, int n, doubl
       L[j * 64 + j] = sqrt(s > 0.0 ? s : 1.0);
     }
     __syncthreads();
-    for (int i = j + 1 + t; i < D; i += 64) {
+    for (int i = j + 1 + t; i < ns; i += 64) {
       double s = L[i * 64 + j];
       for (int k = 0; k < j; ++k) s -= L[i * 64 + k] * L[j * 64 + k];
       L[i * 64 + j] = s / L[j * 64 + j];
@@ -1447,22 +1448,23 @@ IFT_DEV void lm_solve_body(const double* H, const double* g, int D, int n, doubl
     __syncthreads();
   }
   if (t == 0) {
-    for (int i = 0; i < D; ++i) {
+    for (int i = 0; i < ns; ++i) {
       double s = -g[i];
       for (int k = 0; k < i; ++k) s -= L[i * 64 + k] * y[k];
       y[i] = s / L[i * 64 + i];
     }
-    for (int i = D - 1; i >= 0; --i) {
+    for (int i = ns - 1; i >= 0; --i) {
       double s = y[i];
-      for (int k = i + 1; k < D; ++k) s -= L[k * 64 + i] * y[k];
+      for (int k = i + 1; k < ns; ++k) s -= L[k * 64 + i] * y[k];
       y[i] = s / L[i * 64 + i];
     }
     double nS = 0.0, nT = 0.0, sl = 0.0;
     for (int i = 0; i < D; ++i) {
+      const double yi = i < ns ? y[i] : 0.0;
       if (i < n) nS += g[i] * g[i];
       else nT += g[i] * g[i];
-      sl += g[i] * y[i];
-      dz[i] = y[i];
+      sl += g[i] * yi;
+      dz[i] = yi;
     }
     out[0] = fail;
     out[1] = sqrt(nS);
@@ -1472,12 +1474,12 @@ IFT_DEV void lm_solve_body(const double* H, const double* g, int D, int n, doubl
   __syncthreads();
 }
 
-__global__ __launch_bounds__(64) void k_lm_solve(const double* H, const double* g, int D, int n, double lambda,
+__global__ __launch_bounds__(64) void k_lm_solve(const double* H, const double* g, int D, int n, int ns, double lambda,
                                                  double* dz, double* out) {
   __shared__ double L[64 * 64];
   __shared__ double y[64];
   __shared__ int fail;
-  lm_solve_body(H, g, D, n, lambda, dz, out, L, y, fail);
+  lm_solve_body(H, g, D, n, ns, lambda, dz, out, L, y, fail);
 }
 
 // ------------------------------------------ LM step by QR (TSQR, FP64)
@@ -1485,8 +1487,10 @@ __global__ __launch_bounds__(64) void k_lm_solve(const double* H, const double* 
 //   min | [J~_z; 0 sqrt(lambda) I] dz + [F~; 0] |,
 // by Householder QR of the stacked rows [J~_z | -F~] (nrows rows) and, for
 // lambda > 0, the m rows [0 .. sqrt(lambda) e_j .. | 0] of the mapping block.
+// Only the leading ns unknowns are solved for (ns = D, or ns = n for a step
+// in w with tau fixed and dz_tau = 0).
 // Block b reduces rows [QR_RB b, QR_RB (b + 1)) (zero past the end) to the
-// C x C triangle R_b (C = D + 1: the columns of dz and the right-hand side);
+// C x C triangle R_b (C = ns + 1: the unknowns and the right-hand side);
 // the triangles are stacked and reduced again until one block remains, whose
 // triangle [R_z c; 0 rho] gives R_z dz = c by back substitution.  Every sum
 // runs in a fixed order.
@@ -1498,7 +1502,7 @@ struct QrArgs {
   const double* Ft;
   const double* src;  // later levels: stacked triangles [rows][C] (null on the first)
   int rows;           // rows of this level
-  int nrows, D, n, C;
+  int nrows, D, n, ns, C;   // D: row length of J~_z, ns: unknowns solved for, C = ns + 1
   double sqlam;       // sqrt(lambda); the mapping rows exist when rows > nrows on the first level
   double* dst;        // [gridDim.x][C][C] triangles
   const double* g;    // last level: [D] gradient, for |S~|, |T~| and g . dz
@@ -1516,14 +1520,14 @@ __global__ __launch_bounds__(QR_RB) void k_qr_rows(QrArgs q, int last) {
   __shared__ double A[QR_MAXC][QR_RB];         // column-major: A[c][row]
   __shared__ double red[QR_RB / 64][QR_MAXC];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int C = q.C, D = q.D;
+  const int C = q.C, D = q.D, ns = q.ns;
   const long long r = (long long)blockIdx.x * QR_RB + t;
   const bool in = r < q.rows;
   if (q.src) {
     for (int c = 0; c < C; ++c) A[c][t] = in ? q.src[r * C + c] : 0.0;
   } else if (in && r < q.nrows) {
-    for (int c = 0; c < D; ++c) A[c][t] = q.Jt[r * D + c];
-    A[D][t] = -q.Ft[r];
+    for (int c = 0; c < ns; ++c) A[c][t] = q.Jt[r * D + c];
+    A[ns][t] = -q.Ft[r];
   } else {
     const int j = in ? int(r - q.nrows) : -1;   // mapping row j: sqrt(lambda) in column n + j
     for (int c = 0; c < C; ++c) A[c][t] = (j >= 0 && c == q.n + j) ? q.sqlam : 0.0;
@@ -1568,9 +1572,10 @@ __global__ __launch_bounds__(QR_RB) void k_qr_rows(QrArgs q, int last) {
   }
   if (t == 0) {
     int fail = 0;
-    for (int i = D - 1; i >= 0; --i) {
-      double v = A[D][i];
-      for (int k = i + 1; k < D; ++k) v -= A[k][i] * q.dz[k];
+    for (int i = D - 1; i >= ns; --i) q.dz[i] = 0.0;
+    for (int i = ns - 1; i >= 0; --i) {
+      double v = A[ns][i];
+      for (int k = i + 1; k < ns; ++k) v -= A[k][i] * q.dz[k];
       const double rii = A[i][i];
       if (!(fabs(rii) > 0.0)) fail = 1;
       q.dz[i] = fail ? 0.0 : v / rii;

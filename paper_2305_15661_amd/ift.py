@@ -41,14 +41,15 @@ class ProblemDesc(ctypes.Structure):
 class GNParams(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("c1", ctypes.c_double), ("max_backtrack", ctypes.c_int),
                 ("tol", ctypes.c_double), ("tol_mix", ctypes.c_double), ("max_backtrack_mixed", ctypes.c_int),
-                ("use_qr", ctypes.c_int)]
+                ("use_qr", ctypes.c_int), ("w_only", ctypes.c_int)]
 
 
 class GNInfo(ctypes.Structure):
     _fields_ = [("J_old", ctypes.c_double), ("J_new", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("norm_S", ctypes.c_double), ("norm_T", ctypes.c_double), ("n_backtrack", ctypes.c_int),
                 ("converged", ctypes.c_int), ("status", ctypes.c_int), ("iterations", ctypes.c_int),
-                ("fallback", ctypes.c_int), ("mixed_iterations", ctypes.c_int)]
+                ("fallback", ctypes.c_int), ("mixed_iterations", ctypes.c_int),
+                ("presolve_iterations", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -278,14 +279,17 @@ class ROM:
         _check(lib().rom_plain_start(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
                                      _stream(stream)), "rom_plain_start")
 
-    def gauss_newton_step(self, mu, w, tau, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, qr=False, stream=None):
+    def gauss_newton_step(self, mu, w, tau, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, qr=False, w_only=False,
+                          stream=None):
         """rom_gauss_newton_step; returns (status, info dict).  Soft outcomes
         (converged / line-search failure / invalid point) are reported in the
         status instead of raising.  qr: solve the step by Householder QR of
-        the stacked rows instead of the normal equations."""
+        the stacked rows instead of the normal equations; w_only: step in w
+        with tau held, converged on |S~| alone."""
         import torch
         f64 = torch.float64
-        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol), 0.0, 0, int(bool(qr)))
+        prm = GNParams(float(lam), float(c1), int(max_backtrack), float(tol), 0.0, 0, int(bool(qr)),
+                       int(bool(w_only)))
         info = GNInfo()
         st = lib().rom_gauss_newton_step(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
                                          ctypes.byref(prm), ctypes.byref(info), _stream(stream))
@@ -297,7 +301,8 @@ class ROM:
 # numpy view of a device array of ift_gn_info records
 GN_INFO_DTYPE = np.dtype([("J_old", "<f8"), ("J_new", "<f8"), ("alpha", "<f8"), ("norm_S", "<f8"),
                           ("norm_T", "<f8"), ("n_backtrack", "<i4"), ("converged", "<i4"), ("status", "<i4"),
-                          ("iterations", "<i4"), ("fallback", "<i4"), ("mixed_iterations", "<i4")])
+                          ("iterations", "<i4"), ("fallback", "<i4"), ("mixed_iterations", "<i4"),
+                          ("presolve_iterations", "<i4"), ("_pad", "<i4")])
 assert GN_INFO_DTYPE.itemsize == ctypes.sizeof(GNInfo)
 
 
@@ -361,7 +366,7 @@ class Batch:
         _check(st, "eq_assemble_jacobian_batched")
 
     def solve(self, mu, z, info, lam=0.0, c1=1e-4, max_backtrack=30, tol=1e-8, max_it=50, graph=True,
-              warm=False, tol_mix=0.0, max_backtrack_mixed=0, stream=None):
+              warm=False, tol_mix=0.0, max_backtrack_mixed=0, presolve=False, adaptive_lambda=False, stream=None):
         """rom_gauss_newton_solve_batched; info: device uint8 tensor of
         n_inst * GN_INFO_DTYPE.itemsize bytes (see info_array).  tol_mix and
         max_backtrack_mixed (0: the library's defaults) steer the switch of
@@ -374,7 +379,8 @@ class Batch:
         st = lib().rom_gauss_newton_solve_batched(self.handle, _ptr(mu, 2 * self.n_inst, torch.float64),
                                                   _ptr(z, self.nz, torch.float64), ctypes.byref(prm), int(max_it),
                                                   ctypes.c_void_p(info.data_ptr()),
-                                                  (0 if graph else 1) | (2 if warm else 0), _stream(stream))
+                                                  (0 if graph else 1) | (2 if warm else 0) | (4 if presolve else 0)
+                                                  | (8 if adaptive_lambda else 0), _stream(stream))
         _check(st, "rom_gauss_newton_solve_batched")
 
     def info_buffer(self, device=None):

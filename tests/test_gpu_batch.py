@@ -186,6 +186,82 @@ def test_batched_solve_matches_per_instance_loop(setup):
     assert np.max(out["iterations"]) >= 2   # the solves take real steps
 
 
+def _loop_solve_opts(S, c, max_it, presolve, adaptive, lam0, tol=1e-8):
+    """The batched state machine with the paper's initialisation (w steps
+    with tau held until |S~| <= tol; a failed w line search ends them) and
+    adaptive lambda, written out with rom_gauss_newton_step calls; a call at
+    the step limit only tests convergence."""
+    import torch
+    from oracle.gn import adapt_lambda
+    ift = S["ift"]
+    dev, r = S["dev"], c["rom"]
+    w, tau = torch.tensor(c["w0"], device=dev), torch.tensor(c["tau0"], device=dev)
+    lam, wonly, steps, wsteps = lam0, presolve, 0, 0
+    while True:
+        last = steps == max_it
+        if wonly:
+            wc, tc = (w.clone(), tau.clone()) if last else (w, tau)
+            st, info = r.gauss_newton_step(c["mu"], wc, tc, lam=lam, tol=tol, w_only=True)
+            if info["converged"]:
+                wonly = False          # the full step at the same iterate follows
+            elif st in (ift.IFT_EBADMESH, ift.IFT_ENONPHYS):
+                return w, tau, steps, wsteps, st
+            elif last:
+                return w, tau, steps, wsteps, ift.IFT_ENOTCONV
+            elif st == ift.IFT_ELINESEARCH:
+                steps, wsteps, wonly = steps + 1, wsteps + 1, False
+                continue
+            elif st != 0:
+                return w, tau, steps, wsteps, st
+            else:
+                steps, wsteps = steps + 1, wsteps + 1
+                if adaptive:
+                    lam = adapt_lambda(lam, info["alpha"])
+                continue
+        wc, tc = (w.clone(), tau.clone()) if last else (w, tau)
+        st, info = r.gauss_newton_step(c["mu"], wc, tc, lam=lam, tol=tol)
+        if info["converged"]:
+            return w, tau, steps, wsteps, ift.IFT_OK
+        if st in (ift.IFT_EBADMESH, ift.IFT_ENONPHYS):
+            return w, tau, steps, wsteps, st
+        if last:
+            return w, tau, steps, wsteps, ift.IFT_ENOTCONV
+        if st != 0:
+            return w, tau, steps, wsteps, st
+        steps += 1
+        if adaptive:
+            lam = adapt_lambda(lam, info["alpha"])
+
+
+@pytest.mark.parametrize("presolve,adaptive", [(True, False), (True, True), (False, True)])
+def test_batched_presolve_and_adaptive_lambda_match_loop(setup, presolve, adaptive):
+    import torch
+    S = setup
+    b, insts, ift = S["batch"], S["insts"], S["ift"]
+    mu, z = _inputs(S, plain=True)
+    info = b.info_buffer(S["dev"])
+    lam0 = 1e-3 if adaptive else LAM
+    _say(f"batched solve presolve={presolve} adaptive={adaptive}")
+    b.solve(mu, z, info, lam=lam0, max_it=30, presolve=presolve, adaptive_lambda=adaptive)
+    torch.cuda.synchronize()
+    out = b.info_array(info)
+    zb = b.unpack(z)
+    n_conv = 0
+    for i, c in enumerate(insts):
+        w, tau, steps, wsteps, st = _loop_solve_opts(S, c, 30, presolve, adaptive, lam0)
+        _say(f"  instance {i}: batched status {out['status'][i]} steps {out['iterations'][i]} "
+             f"w-steps {out['presolve_iterations'][i]}; loop status {st} steps {steps} w-steps {wsteps}")
+        assert out["status"][i] == st
+        assert out["iterations"][i] == steps and out["presolve_iterations"][i] == wsteps
+        if st == ift.IFT_OK:
+            n_conv += 1
+            zl = np.concatenate([w.cpu().numpy(), tau.cpu().numpy()])
+            assert rel(zb[i], zl) < 1e-6
+    assert n_conv >= 3
+    if presolve:
+        assert np.sum(out["presolve_iterations"]) > 0
+
+
 def test_graph_replays_match_eager(setup):
     import torch
     S = setup

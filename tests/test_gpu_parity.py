@@ -291,6 +291,38 @@ def test_gauss_newton_qr_step_parity(which, lam, request):
     assert checked >= 2
 
 
+@pytest.mark.parametrize("qr", [False, True])
+def test_gauss_newton_w_only_step_parity(tiny_case, qr):
+    """Steps of the paper's initialisation (w with tau held, converged on
+    |S~| alone) from the plain start, each compared with the oracle's w-only
+    step from the same w_n (bound as for the full step, with cond(H_ww))."""
+    from oracle import eq as oeq
+    from oracle import gn as ogn
+    case = tiny_case
+    wl, d = case.wl, case.dev
+    mu = wl.mus[0]
+    w, tau0 = oeq.plain_start(wl, mu)
+    n = wl.n
+    for it in range(12):
+        _say(f"w-only step {it} (qr={qr})")
+        wg, tg = _t(w, d), _t(tau0, d)
+        st, info = case.rom.gauss_newton_step(mu, wg, tg, qr=qr, w_only=True)
+        wo, to, oinfo = ogn.gn_step(case.orom, mu, w, tau0, solver="qr" if qr else "normal", w_only=True)
+        assert np.array_equal(tg.cpu().numpy(), tau0) and np.array_equal(to, tau0)
+        if oinfo["status"] == "converged":
+            assert st == 0 and info["converged"] == 1
+            break
+        assert st == 0 and oinfo["status"] == "ok"
+        assert info["n_backtrack"] == oinfo["n_backtrack"]
+        H = case.orom.jacobian(mu, w, tau0)["H"][:n, :n]
+        bound = max(1e-12, 1e-13 * np.linalg.cond(H))
+        step = max(np.linalg.norm(wo - w), 1e-300)
+        assert np.linalg.norm(wg.cpu().numpy() - wo) <= bound * step + 1e-14 * np.linalg.norm(w)
+        w = wo
+    else:
+        raise AssertionError("the w-only iteration did not converge in 12 steps")
+
+
 def test_full_size_euler_samples(dev):
     """16384 P2 elements, 819 EQ elements, n = 20, m = 10 (the benchmark
     shape): full EQ assembly against the oracle, and the full-order residual

@@ -82,3 +82,54 @@ def test_linesearch_rejects_invalid_trial(tiny):
     mu, w = wl.mus[0], wl.w_eval[0]
     r = rom.residual(mu, w, 80.0 * wl.tau_eval[0])
     assert r["invalid"] and np.isinf(r["J"])
+
+
+def test_w_only_step_equals_bruteforce_lstsq(tiny):
+    """The initialisation step (w with tau held): least squares in the w
+    columns of a finite-difference Jacobian of F~, dtau = 0 exactly."""
+    wl = tiny
+    rom = _rom(wl)
+    mu, w, tau = wl.mus[0], wl.w_eval[5], wl.tau_eval[5]
+    n = wl.n
+    F0 = rom.residual(mu, w, tau)["Ft"]
+    Jfd = np.zeros((F0.size, n))
+    for i in range(n):
+        h = 1e-6 * max(1.0, abs(w[i]))
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        Jfd[:, i] = (rom.residual(mu, wp, tau)["Ft"] - rom.residual(mu, wm, tau)["Ft"]) / (2 * h)
+    dw_bf = np.linalg.lstsq(Jfd, -F0, rcond=None)[0]
+    jac = rom.jacobian(mu, w, tau)
+    for solver in ("normal", "qr"):
+        dz = gn.lm_direction(jac, n, 0.7, solver, w_only=True)   # lambda plays no part
+        assert rel(dz[:n], dw_bf) < 1e-6
+        assert np.all(dz[n:] == 0.0)
+
+
+def test_presolve_holds_tau_and_meets_tolerance(tiny):
+    """The paper's initialisation from tau0 = 0 ends at |S~(w0, 0)| <= tol
+    with tau untouched; the full iteration then converges."""
+    wl = tiny
+    rom = _rom(wl)
+    mu = wl.mus[0]
+    w0, t0 = eq.plain_start(wl, mu)
+    w, tau = w0.copy(), t0.copy()
+    for _ in range(40):
+        w, tau, info = gn.gn_step(rom, mu, w, tau, w_only=True)
+        assert np.array_equal(tau, t0)
+        if info["status"] != "ok":
+            break
+    assert info["status"] == "converged" and info["norm_S"] <= 1e-8
+    # the same through lm_solve: the w steps end where the loop above ends
+    w2, tau2, res = gn.lm_solve(rom, mu, w0, t0, presolve=True, max_it=80)
+    assert res["status"] == "converged" and res["w_iterations"] >= 1
+    J = rom.jacobian(mu, w2, tau2)
+    assert np.linalg.norm(J["g"][:wl.n]) <= 1e-8 and np.linalg.norm(J["g"][wl.n:]) <= 1e-8
+
+
+def test_adaptive_lambda_rule():
+    assert gn.adapt_lambda(1e-3, 1.0) == 1e-4
+    assert gn.adapt_lambda(5e-12, 1.0) == 0.0
+    assert gn.adapt_lambda(1e-3, 0.5) == 1e-2
+    assert gn.adapt_lambda(0.0, 0.25) == 1e-8
