@@ -888,13 +888,14 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
           acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
     };
     if constexpr (D::NC == 4) {
-      // One k-loop over the w steps (a quadrature point, or a (face, point)
-      // pair, per step; the lane's column component is kl) and then the x
-      // steps (volume: entry ab = kl of J at point q; faces: column 4 ks' +
-      // kl of the (face, point, direction) block).  The B values of step
-      // s + 1 are loaded before the A values and MFMAs of step s, so their
-      // latency overlaps a step of work.  Tiles without w (x) columns skip
-      // the MFMAs of w (x) steps; the loads are issued for every tile.
+      // The w steps (a quadrature point, or a (face, point) pair, per step;
+      // the lane's column component is kl), then the x steps (volume: entry
+      // ab = kl of J at point q; faces: column 4 ks' + kl of the (face,
+      // point, direction) block), one loop per kind of step.  Each step
+      // issues its MFMAs with the B values in bc and then reloads bc with
+      // the B values of the next step (across the loops too), so those loads
+      // overlap the A values of the next step.  Tiles without w (x) columns
+      // skip the MFMAs of w (x) steps; the loads are issued for every tile.
       static_assert(O::KW == O::KWP, "w steps are whole points");
       constexpr int KWS = O::KWP / 4, KXS = O::KXP / 4;
       const int KS = KWS + (m > 0 ? KXS : 0);
@@ -909,56 +910,68 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
         won[nt] = 16 * nt < n;
         xon[nt] = 16 * nt + 16 > n && 16 * nt < n + m;
       }
-      auto bload = [&](int st, double* bv) {
+      double bc[NT];
+      auto bload = [&](int st) {
+        st = st < KS ? st : KS - 1;
         const bool xs = st >= KWS;
         const int r = 4 * (xs ? st - KWS : st) + kl;
         const double* base = xs ? bx + (long long)r * (m + 1) : bw + (long long)r * (n + 1);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) bv[nt] = base[xs ? cx[nt] : cw[nt]];
+        for (int nt = 0; nt < NT; ++nt) bc[nt] = base[xs ? cx[nt] : cw[nt]];
       };
-      // one k-step: MFMAs with the B values bc of step st while the loads of
-      // step st + 1 go to bn (two register sets used in turn, so that no
-      // register copy waits for a load in flight)
-      auto kstep = [&](int st, const double* bc, double* bn) {
-        bload(st + 1 < KS ? st + 1 : st, bn);
-        double av[MT];
-        if (st < D::NQV) {
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) av[mt] = aw_vol<D, R>(tab, p, ri[mt], rc[mt], st, kl) * rm[mt];
-        } else if (st < KWS) {
-          const int f2 = st - D::NQV;
-          const int pl = f2 / (3 * D::NQF), fq = f2 % (3 * D::NQF);
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-            av[mt] = aw_face<D, R>(tab, p, ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl) * rm[mt];
-        } else if (st < KWS + D::NQV) {
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) av[mt] = ax_vol<D, R>(tab, p, ri[mt], rc[mt], st - KWS, kl) * rm[mt];
-        } else {
-          const int cf0 = 4 * (st - KWS - D::NQV) + kl;
-          const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
-          const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-            av[mt] = ax_face<D, R>(tab, p, ri[mt], rc[mt], cf / (2 * D::NQF), (cf >> 1) % D::NQF, cf & 1) *
-                     (rm[mt] * cm);
-        }
-        const bool xs = st >= KWS;
+      auto mfmas = [&](const double* av, const bool* on) {
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          if (xs ? xon[nt] : won[nt]) {
+          if (on[nt]) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
               acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bc[nt], acc[mt][nt], 0, 0, 0);
           }
         }
       };
-      double b0[NT], b1[NT];
-      bload(0, b0);
+      bload(0);
 #pragma unroll 1
-      for (int st = 0; st < KS; st += 2) {
-        kstep(st, b0, b1);
-        if (st + 1 < KS) kstep(st + 1, b1, b0);
+      for (int q = 0; q < D::NQV; ++q) {
+        double av[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) av[mt] = aw_vol<D, R>(tab, p, ri[mt], rc[mt], q, kl) * rm[mt];
+        mfmas(av, won);
+        bload(q + 1);
+      }
+#pragma unroll 1
+      for (int pl = 0; pl < 2; ++pl) {
+#pragma unroll 1
+        for (int fq = 0; fq < 3 * D::NQF; ++fq) {
+          double av[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            av[mt] = aw_face<D, R>(tab, p, ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl) * rm[mt];
+          mfmas(av, won);
+          bload(D::NQV + 3 * D::NQF * pl + fq + 1);
+        }
+      }
+      if (m > 0) {
+#pragma unroll 1
+        for (int q = 0; q < D::NQV; ++q) {
+          double av[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) av[mt] = ax_vol<D, R>(tab, p, ri[mt], rc[mt], q, kl) * rm[mt];
+          mfmas(av, xon);
+          bload(KWS + q + 1);
+        }
+#pragma unroll 1
+        for (int ks = 0; ks < KXS - D::NQV; ++ks) {
+          const int cf0 = 4 * ks + kl;
+          const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
+          const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
+          double av[MT];
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            av[mt] = ax_face<D, R>(tab, p, ri[mt], rc[mt], cf / (2 * D::NQF), (cf >> 1) % D::NQF, cf & 1) *
+                     (rm[mt] * cm);
+          mfmas(av, xon);
+          bload(KWS + D::NQV + ks + 1);
+        }
       }
     } else {
 #pragma unroll 4
