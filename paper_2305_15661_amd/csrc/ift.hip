@@ -604,7 +604,7 @@ static bool build_point_bases(ift_rom* r) {
 struct FusedLayout {
   int E, nblk;
 };
-static constexpr long long FUSED_TARGET_WAVES = 4096;
+static constexpr long long FUSED_TARGET_WAVES = 2048;   // waves resident at two per SIMD
 static FusedLayout fused_layout(const ift_rom* r, int n_pts) {
   const long long ns = r->n_s;
   int E = (int)std::max<long long>(1, (ns * n_pts + FUSED_TARGET_WAVES - 1) / FUSED_TARGET_WAVES);
