@@ -95,8 +95,11 @@ namespace {
 struct ProfRec {
   int kind;
   hipEvent_t a, b;
+  bool own_a;   // false: a is the end event of the preceding record
 };
 bool g_prof_on = false;
+hipEvent_t g_prof_tail = nullptr;     // end event of the last record
+hipStream_t g_prof_tail_st = nullptr;
 std::vector<ProfRec> g_prof_live;     // recorded, not yet read
 std::vector<hipEvent_t> g_prof_pool;  // idle events
 int g_prof_count[IFT_PROF_NKIND] = {};
@@ -113,21 +116,32 @@ hipEvent_t prof_event() {
   return e;
 }
 
-// Brackets one launch: call begin before and end after enqueueing it.
+// Brackets one launch: events recorded before and after enqueueing it.  A
+// chained scope directly follows the previous scope on the same stream and
+// starts at that scope's end event (fewer events between back-to-back
+// kernels).
 struct ProfScope {
   int kind;
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(int k, hipStream_t s) : kind(k), st(s) {
+  bool own_a = true;
+  ProfScope(int k, hipStream_t s, bool chain = false) : kind(k), st(s) {
     if (!g_prof_on) return;
-    a = prof_event();
+    if (chain && g_prof_tail && g_prof_tail_st == s) {
+      a = g_prof_tail;
+      own_a = false;
+    } else {
+      a = prof_event();
+      if (a) (void)hipEventRecord(a, st);
+    }
     b = prof_event();
-    if (a) (void)hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (!g_prof_on || !a || !b) return;
     (void)hipEventRecord(b, st);
-    g_prof_live.push_back({kind, a, b});
+    g_prof_live.push_back({kind, a, b, own_a});
+    g_prof_tail = b;
+    g_prof_tail_st = st;
   }
 };
 
@@ -138,15 +152,19 @@ void prof_drain() {
       g_prof_count[r.kind] += 1;
       g_prof_ms[r.kind] += ms;
     }
-    g_prof_pool.push_back(r.a);
+  }
+  for (auto& r : g_prof_live) {
+    if (r.own_a) g_prof_pool.push_back(r.a);
     g_prof_pool.push_back(r.b);
   }
   g_prof_live.clear();
+  g_prof_tail = nullptr;
 }
 }  // namespace
 
 extern "C" ift_status ift_profile_enable(int on) {
   g_prof_on = on != 0;
+  g_prof_tail = nullptr;
   return IFT_OK;
 }
 
@@ -845,7 +863,7 @@ struct EqLaunch {
         ProfScope ps(IFT_PROF_POINTS, st);
         hipLaunchKernelGGL((k_points_eq<D, R>), dim3(xcd_pad(a.n_s), n_pts), dim3(NTHR_PTS), 0, st, a);
       }
-      ProfScope ps(IFT_PROF_EQ_JAC, st);
+      ProfScope ps(IFT_PROF_EQ_JAC, st, true);
       if (!fa) hipLaunchKernelGGL((k_eq_asm<D, R>), dim3(a.n_s, n_pts), dim3(NTHR), 0, st, a, Bw, Bx);
       else if (nt == 1) fused<D, 1>();
       else if (nt == 2) fused<D, 2>();
@@ -883,7 +901,7 @@ static ift_status eq_jacobian_fused(ift_rom* r, const EqArgs& a, int n_pts, doub
   if (s != IFT_OK) return s;
   const int D1 = r->D + 1;
   const int nbe = (D1 * (D1 + 1) / 2 + GF_ENT - 1) / GF_ENT;
-  ProfScope ps(IFT_PROF_GRAM, stream);
+  ProfScope ps(IFT_PROF_GRAM, stream, true);
   hipLaunchKernelGGL(k_fused_final, dim3(nbe + 1, n_pts), dim3(256), 0, stream, (const double*)r->d_fpart,
                      (const int*)r->d_fbad, L.nblk, r->fused_nt, r->D, H, g, Jobj ? Jobj : r->d_J, n_bad,
                      r->d_flag_or);
