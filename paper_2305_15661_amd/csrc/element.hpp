@@ -446,6 +446,81 @@ IFT_DEV R jacobian_entry(const ElemLDS<D, R>& s, int r, int col) {
   return v;
 }
 
+// Blocked entries of the element Jacobian for four state components: the
+// four columns (node j, components 0..3) of row r share the basis and
+// geometry factors, and the four flux-Jacobian components are contiguous.
+// dR/dU_e[r][4 j + cc]: volume terms through df/du, faces through dH/du-.
+template <class D, class R>
+IFT_DEV void jac_u4(const RefTab& t, const Pts<D, R>& p, int r, int j, R* out) {
+  static_assert(D::NC == 4, "four state components");
+  const int i = r / 4, c = r % 4;
+  R v[4] = {R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int q = 0; q < D::NQV; ++q) {
+    const R w = R(t.wv[q] * t.phiv[q][j]);
+    const R g0 = p.gp[q][i][0] * w, g1 = p.gp[q][i][1] * w;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) v[cc] -= p.Af[q][c][0][cc] * g0 + p.Af[q][c][1][cc] * g1;
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int ki = t.nfk[i][f], kj = t.nfk[j][f];
+    if (ki < 0 || kj < 0) continue;
+#pragma unroll
+    for (int q = 0; q < D::NQF; ++q) {
+      const R w = R(t.wf[q] * t.L[q][ki] * t.L[q][kj]);
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) v[cc] += w * p.dHm[f][q][c][cc];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) out[cc] = v[cc];
+}
+
+// dR/dU_e'[r][4 (NE f + kn) + cc]: faces of node i through dH/du+.
+template <class D, class R>
+IFT_DEV void jac_un4(const RefTab& t, const Pts<D, R>& p, int r, int f, int kn, R* out) {
+  const int i = r / 4, c = r % 4;
+  R v[4] = {R(0), R(0), R(0), R(0)};
+  const int ki = t.nfk[i][f];
+  if (ki >= 0) {
+#pragma unroll
+    for (int q = 0; q < D::NQF; ++q) {
+      const R w = R(t.wf[q] * t.L[q][ki] * t.L[q][kn]);
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) v[cc] += w * p.dHp[f][q][c][cc];
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) out[cc] = v[cc];
+}
+
+// dR/dx_e[r][2 kn + a], a = 0, 1: cof(J) grad phi_i and n~ are linear in x_e.
+template <class D, class R>
+IFT_DEV void jac_x2(const RefTab& t, const Pts<D, R>& p, int r, int kn, R* out) {
+  const int i = r / D::NC, c = r % D::NC;
+  R v0 = R(0), v1 = R(0);
+#pragma unroll
+  for (int q = 0; q < D::NQV; ++q) {
+    const R K = R(t.wv[q] * (t.dphiv[q][kn][0] * t.dphiv[q][i][1] - t.dphiv[q][kn][1] * t.dphiv[q][i][0]));
+    v0 -= p.fv[q][c][1] * K;
+    v1 += p.fv[q][c][0] * K;
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const int ki = t.nfk[i][f], kk = t.nfk[kn][f];
+    if (ki < 0 || kk < 0) continue;
+#pragma unroll
+    for (int q = 0; q < D::NQF; ++q) {
+      const R w = R(t.wf[q] * t.L[q][ki] * t.dL[q][kk]);
+      v0 -= w * p.dHn[f][q][c][1];
+      v1 += w * p.dHn[f][q][c][0];
+    }
+  }
+  out[0] = v0;
+  out[1] = v1;
+}
+
 template <class D, class R, bool JAC>
 IFT_DEV void phase_assemble(ElemLDS<D, R>& s, int tid) {
   for (int r = tid; r < D::NUE; r += NTHR) s.Re[r] = residual_entry<D, R>(s, r);

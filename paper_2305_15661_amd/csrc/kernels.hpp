@@ -287,6 +287,45 @@ __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
   load_tab<D, R>(s, tid, NTHR);
   copy_words<D, R>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + e, tid, NTHR);
   __syncthreads();
+  if constexpr (D::NC == 4) {
+    // blocked entries straight to the outputs: (row, node) pairs of dR/dU_e
+    // and dR/dU_e' (four columns each), (row, node) pairs of dR/dx_e (two)
+    constexpr int NU = D::NUE * D::NN, NUN4 = D::NUE * 3 * D::NE, NX = D::NUE * D::NN;
+    if (a.R && tid < D::NUE) a.R[(long long)e * D::NUE + tid] = double(residual_entry<D, R>(s, tid));
+    for (int task = tid; task < NU + NUN4 + NX; task += NTHR) {
+      R v[4];
+      if (task < NU) {
+        if (!a.dRdU) continue;
+        const int r = task / D::NN, j = task % D::NN;
+        jac_u4<D, R>(s.tab, s.p, r, j, v);
+        double* o = a.dRdU + ((long long)e * D::NUE + r) * D::NUE + 4 * j;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) o[cc] = double(v[cc]);
+      } else if (task < NU + NUN4) {
+        if (!a.dRdUn) continue;
+        const int tk = task - NU;
+        const int r = tk / (3 * D::NE), fk = tk % (3 * D::NE);
+        jac_un4<D, R>(s.tab, s.p, r, fk / D::NE, fk % D::NE, v);
+        double* o = a.dRdUn + ((long long)e * D::NUE + r) * D::NUN + 4 * fk;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) o[cc] = double(v[cc]);
+      } else {
+        if (!a.dRdx) continue;
+        const int tk = task - NU - NUN4;
+        const int r = tk / D::NN, kn = tk % D::NN;
+        jac_x2<D, R>(s.tab, s.p, r, kn, v);
+        double* o = a.dRdx + ((long long)e * D::NUE + r) * D::NXE + 2 * kn;
+        o[0] = double(v[0]);
+        o[1] = double(v[1]);
+      }
+    }
+    if (tid == 0) {
+      if (a.N) a.N[e] = double(s.p.N);
+      a.flags[e] = s.p.bad;
+    }
+    if (a.dNdx && tid < D::NXE) a.dNdx[(long long)e * D::NXE + tid] = double(s.p.dN[tid]);
+    return;
+  }
   phase_assemble<D, R, true>(s, tid);
   __syncthreads();
   if (a.R && tid < D::NUE) a.R[(long long)e * D::NUE + tid] = double(s.Re[tid]);
