@@ -77,7 +77,6 @@ struct Pts {
   int pad_;
 };
 
-constexpr int ELEM_STAGE = 2048;   // doubles of lift staging per element block
 
 template <class D, class R>
 struct ElemLDS {
@@ -90,10 +89,7 @@ struct ElemLDS {
   Pts<D, R> p;
   R Re[D::NUE];
   R deta[D::NQV][5];   // per volume point: distortion integrand and its J-gradient
-  union {
-    R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
-    double stage[ELEM_STAGE];   // staging of the lift (Jacobian not yet formed)
-  };
+  R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
 };
 
 template <class D, class R>

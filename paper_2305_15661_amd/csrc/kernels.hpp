@@ -113,39 +113,11 @@ IFT_DEV void load_hdm(ElemLDS<D, R>& s, const HdmArgs& a, int e, int tid, int nt
   if (tid == 0) s.p.bad = 0;
 }
 
-// out[r] = base[r] + sum_j M[r][j] v[j] for a contiguous row-major block M
-// (rows x cols) in global memory: the products are staged through LDS with
-// coalesced loads that are all independent (one pass per chunk of rows),
-// then each row is summed in column order by one thread.
-template <class D, class R>
-IFT_DEV void lift_rows(ElemLDS<D, R>& s, const double* M, const double* v, int rows, int cols, const double* base,
-                       R* out, R* out2, int tid, int nthr) {
-  const int chunk = ELEM_STAGE / cols;   // cols <= 64 < ELEM_STAGE
-  for (int r0 = 0; r0 < rows; r0 += chunk) {
-    const int nr = min(chunk, rows - r0);
-    const int cnt = nr * cols;
-    const double* src = M + (long long)r0 * cols;
-    for (int i = tid; i < cnt; i += nthr) s.stage[i] = src[i] * v[i % cols];
-    __syncthreads();
-    for (int r = tid; r < nr; r += nthr) {
-      double acc = base ? base[r0 + r] : 0.0;
-      for (int j = 0; j < cols; ++j) acc += s.stage[r * cols + j];
-      out[r0 + r] = R(acc);
-      if (out2) out2[r0 + r] = R(base[r0 + r]);
-    }
-    __syncthreads();
-  }
-}
-
 // Lift U_e = Phi_e w, U_e' = Phi_e' w, x_e = X_e + Psi_e tau from the
-// gathered bases (rows are contiguous in global memory).  Ends with a
-// barrier: everything it wrote is visible to the block.
-// STAGED = false: one thread per row, a serial dot product from global
-// memory (best when the gathered bases are L2-resident, as when several
-// evaluation points share an element); STAGED = true: the products go
-// through LDS with independent coalesced loads (best when they come from
-// HBM, as in the batched solver).  Both end with a barrier.
-template <class D, class R, bool STAGED>
+// gathered bases (rows are contiguous in global memory): one thread per row,
+// a serial dot product.  Ends with a barrier: everything it wrote is
+// visible to the block.
+template <class D, class R>
 IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid, int nthr) {
   const int n = a.n, m = a.m;
   const double* w = a.w + (long long)pt * n;
@@ -156,66 +128,22 @@ IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid, 
   const double* Xs = a.X_s + (long long)k * D::NXE;
   if (tid < 3) s.face[tid] = a.face[a.eq_elem[k] * 3 + tid];
   if (tid == 0) s.p.bad = 0;
-  if constexpr (!STAGED) {
-    for (int t = tid; t < D::NUE + D::NUN + D::NXE; t += nthr) {
-      if (t < D::NUE + D::NUN) {
-        const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
-        double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += row[j] * w[j];
-        if (t < D::NUE) s.U[t] = R(acc);
-        else s.Un[t - D::NUE] = R(acc);
-      } else {
-        const int q = t - D::NUE - D::NUN;
-        double acc = Xs[q];
-        for (int j = 0; j < m; ++j) acc += Ps[(long long)q * m + j] * tau[j];
-        s.x[q] = R(acc);
-        s.X[q] = R(Xs[q]);
-      }
+  for (int t = tid; t < D::NUE + D::NUN + D::NXE; t += nthr) {
+    if (t < D::NUE + D::NUN) {
+      const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
+      double acc = 0.0;
+      for (int j = 0; j < n; ++j) acc += row[j] * w[j];
+      if (t < D::NUE) s.U[t] = R(acc);
+      else s.Un[t - D::NUE] = R(acc);
+    } else {
+      const int q = t - D::NUE - D::NUN;
+      double acc = Xs[q];
+      for (int j = 0; j < m; ++j) acc += Ps[(long long)q * m + j] * tau[j];
+      s.x[q] = R(acc);
+      s.X[q] = R(Xs[q]);
     }
-    __syncthreads();
-    return;
   }
-  const int c1 = D::NUE * n, c2 = c1 + D::NUN * n, c3 = c2 + D::NXE * m;
-  if (c3 <= ELEM_STAGE) {
-    // one pass: every product of the three blocks, then every row sum
-    for (int i = tid; i < c3; i += nthr) {
-      double v;
-      if (i < c1) v = Ph[i] * w[i % n];
-      else if (i < c2) v = Pn[i - c1] * w[(i - c1) % n];
-      else v = Ps[i - c2] * tau[(i - c2) % m];
-      s.stage[i] = v;
-    }
-    __syncthreads();
-    for (int r = tid; r < D::NUE + D::NUN + D::NXE; r += nthr) {
-      if (r < D::NUE + D::NUN) {
-        const double* row = s.stage + (long long)r * n;
-        double acc = 0.0;
-        for (int j = 0; j < n; ++j) acc += row[j];
-        if (r < D::NUE) s.U[r] = R(acc);
-        else s.Un[r - D::NUE] = R(acc);
-      } else {
-        const int q = r - D::NUE - D::NUN;
-        const double* row = s.stage + c2 + (long long)q * m;
-        double acc = Xs[q];
-        for (int j = 0; j < m; ++j) acc += row[j];
-        s.x[q] = R(acc);
-        s.X[q] = R(Xs[q]);
-      }
-    }
-    __syncthreads();
-    return;
-  }
-  lift_rows<D, R>(s, Ph, w, D::NUE, n, nullptr, s.U, nullptr, tid, nthr);
-  lift_rows<D, R>(s, Pn, w, D::NUN, n, nullptr, s.Un, nullptr, tid, nthr);
-  if (m > 0) {
-    lift_rows<D, R>(s, Ps, tau, D::NXE, m, Xs, s.x, s.X, tid, nthr);
-  } else {
-    for (int r = tid; r < D::NXE; r += nthr) {
-      s.x[r] = R(Xs[r]);
-      s.X[r] = s.x[r];
-    }
-    __syncthreads();
-  }
+  __syncthreads();
 }
 
 // ------------------------------------------------- full order, values only
@@ -256,10 +184,10 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
 }
 
 // Point data of sampled element k at evaluation point pt (one block).
-template <class D, class R, bool STAGED = false>
+template <class D, class R>
 IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R>(s, tid, NTHR_PTS);
-  load_eq<D, R, STAGED>(s, a, k, pt, tid, NTHR_PTS);
+  load_eq<D, R>(s, a, k, pt, tid, NTHR_PTS);
   __syncthreads();
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
