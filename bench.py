@@ -213,6 +213,37 @@ def batched_leg(n_inst: int, n_loop: int, dev):
         f"fp64 z median {af.get('z_median')}, w median {af.get('w_median')}")
     log(f"batched: {n_inst} instances, {conv} converged in {t_solve:.3f} s ({conv / t_solve:.1f} solves/s), "
         f"jacobian {t_jac * 1e3:.2f} ms ({ns / t_jac:.3e} evals/s), E={E}")
+    # greedy indicator, eq. (greedy0), at every FP64 solution: full-order
+    # residual norms over all elements, grouped by the pool basis
+    groups = []
+    for pidx in range(len(pool)):
+        ids = [i for i in range(n_inst) if bw.inst_pool[i] == pidx]
+        if not ids:
+            continue
+        n_p, m_p = bw.pool_nm[pidx]
+        wz = torch.tensor(np.stack([z64[i][:n_p] for i in ids]), device=dev)
+        tz = torch.tensor(np.stack([z64[i][n_p:] for i in ids]), device=dev)
+        mz = torch.tensor(bw.mus[ids], dtype=torch.float64, device=dev)
+        groups.append((ids, pidx, mz, wz, tz, torch.zeros(len(ids), dtype=torch.float64, device=dev)))
+    for _ in range(2):
+        for ids, pidx, mz, wz, tz, nz in groups:
+            prob.hdm_residual_norms(mz, pool[pidx][0], wz, pool[pidx][1], tz, nz)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for ids, pidx, mz, wz, tz, nz in groups:
+        prob.hdm_residual_norms(mz, pool[pidx][0], wz, pool[pidx][1], tz, nz)
+    torch.cuda.synchronize()
+    t_greedy = time.perf_counter() - t
+    norms = np.zeros(n_inst)
+    for ids, pidx, mz, wz, tz, nz in groups:
+        norms[ids] = nz.cpu().numpy()
+    best = ift.greedy_select(norms)
+    n_elem = bw.base.mesh.n_elem
+    greedy = {"candidates": n_inst, "elements": n_elem, "seconds": t_greedy,
+              "element_evals_per_s": n_inst * n_elem / t_greedy, "argmax": best,
+              "mu_argmax": [float(v) for v in bw.mus[best]], "norm_max": float(norms[best])}
+    log(f"greedy indicator: {n_inst} candidates x {n_elem} elements in {t_greedy * 1e3:.1f} ms "
+        f"({greedy['element_evals_per_s']:.3e} element-evals/s); next parameter {greedy['mu_argmax']}")
     # the same FP64 batch with the paper's initialisation (steps in w with
     # tau held until |S~| <= tol, then full steps)
     zp = z0.clone()
@@ -265,6 +296,7 @@ def batched_leg(n_inst: int, n_loop: int, dev):
                      "solves_per_s": loop_rate, "mean_gn_iterations": float(np.mean(lits))},
             "speedup_vs_loop": (conv / t_solve) / loop_rate if loop_rate > 0 else None,
             "with_w_only_initialisation": presolve,
+            "greedy_indicator": greedy,
             "mixed_precision": mixed}
 
 

@@ -128,6 +128,22 @@ ift_status hdm_assemble(ift_problem* prob, const double* mu, const double* U, co
                         double* R, double* N, double* dRdU, double* dRdUn, double* dRdx,
                         double* dNdx, int* n_bad, hipStream_t stream);
 
+/* The indicator of the greedy search, eq. (greedy0): for each of n_pts
+ * reduced solutions (w_p, tau_p) at mu_p, the 2-norm of the full-order DG
+ * residual |R(Phi w_p; X + Psi tau_p, mu_p)|_2 over all n_elem elements
+ * (eq. (hdm_elem); the distortion is not part of it), evaluated element by
+ * element without forming Phi w or X + Psi tau.  All arrays DEVICE: mu
+ * [n_pts][2], Phi [N_u][n] and Psi [N_x][m] row-major (the bases the ROM
+ * was built from), w [n_pts][n], tau [n_pts][m]; out: norms [n_pts] (+inf
+ * where an element has invalid geometry or state), n_bad [n_pts] (may be
+ * NULL) the number of such elements.  The argmax over the candidates picks
+ * the next training parameter.  The problem keeps a workspace of
+ * n_pts * ceil(n_elem / 16) doubles and ints, allocated or grown by the
+ * call that first needs it. */
+ift_status hdm_residual_norm_batched(ift_problem* prob, int n_pts, const double* mu, const double* Phi, int n,
+                                     const double* w, const double* Psi, int m, const double* tau, double* norms,
+                                     int* n_bad, hipStream_t stream);
+
 /* Reduced-order model with EQ set {(e_k, rho_k)}, k < n_s.  Phi [N_u][n]
  * and Psi [N_x][m] are DEVICE pointers, only read during creation;
  * eq_elem [n_s] and eq_rho [n_s] are HOST pointers (rho_k >= 0).  Creation

@@ -43,6 +43,9 @@ struct ift_problem {
   double* d_X = nullptr;
   int* d_flags = nullptr;
   void* d_pts = nullptr;   // point-data workspace of the Jacobian path [n_elem]
+  double* d_hn_part = nullptr;   // residual-norm block sums [points][blocks] (grown on demand)
+  int* d_hn_bad = nullptr;
+  long long hn_cap = 0;
 };
 
 struct ift_rom {
@@ -468,6 +471,8 @@ extern "C" void ift_problem_destroy(ift_problem* pr) {
   dfree(pr->d_Pn);
   dfree(pr->d_X);
   dfree(pr->d_flags);
+  dfree(pr->d_hn_part);
+  dfree(pr->d_hn_bad);
   if (pr->d_pts) (void)hipFree(pr->d_pts);
   delete pr;
 }
@@ -538,6 +543,59 @@ extern "C" ift_status hdm_assemble(ift_problem* pr, const double* mu, const doub
     if (hipGetLastError() != hipSuccess) return IFT_EDEVICE;
   }
   return IFT_OK;
+}
+
+// Full-order residual norms at reduced solutions (greedy indicator).
+struct HdmRomLaunch {
+  const HdmRomArgs& a;
+  int n_pts;
+  hipStream_t st;
+  template <class D>
+  void run() {
+    ProfScope ps(IFT_PROF_HDM, st);
+    hipLaunchKernelGGL((k_hdm_res_rom<D, double>), dim3(a.nblk, n_pts), dim3(RV_THR), 0, st, a);
+  }
+};
+
+extern "C" ift_status hdm_residual_norm_batched(ift_problem* pr, int n_pts, const double* mu, const double* Phi, int n,
+                                                const double* w, const double* Psi, int m, const double* tau,
+                                                double* norms, int* n_bad, hipStream_t stream) {
+  if (!pr || n_pts < 1 || !mu || !Phi || n < 1 || !w || m < 0 || (m > 0 && (!Psi || !tau)) || !norms)
+    return IFT_EINVAL;
+  const int nblk = (pr->n_elem + RV_SLOTS - 1) / RV_SLOTS;
+  const long long need = (long long)n_pts * nblk;
+  if (need > pr->hn_cap) {
+    dfree(pr->d_hn_part);
+    dfree(pr->d_hn_bad);
+    pr->hn_cap = 0;
+    ift_status e;
+    if ((e = dalloc(&pr->d_hn_part, need)) != IFT_OK || (e = dalloc(&pr->d_hn_bad, need)) != IFT_OK) return e;
+    pr->hn_cap = need;
+  }
+  const double mu0[2] = {1.0, 0.0};
+  HdmRomArgs a;
+  a.Phi = Phi;
+  a.Psi = Psi;
+  a.w = w;
+  a.tau = tau;
+  a.mu = mu;
+  a.gn = pr->d_gn;
+  a.face = pr->d_face;
+  a.Pn = pr->d_Pn;
+  a.X = pr->d_X;
+  a.pc = phys_const(pr, mu0);
+  a.eps = pr->eps_g;
+  a.bc_mu_scale = pr->bc_mu_scale;
+  a.n = n;
+  a.m = m;
+  a.n_elem = pr->n_elem;
+  a.nblk = nblk;
+  a.part = pr->d_hn_part;
+  a.nbad = pr->d_hn_bad;
+  with_disc(pr, HdmRomLaunch{a, n_pts, stream});
+  hipLaunchKernelGGL(k_hdm_norm_final, dim3(n_pts), dim3(256), 0, stream, (const double*)pr->d_hn_part,
+                     (const int*)pr->d_hn_bad, nblk, norms, n_bad);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }
 
 // -------------------------------------------------------------------- ROM

@@ -417,6 +417,135 @@ __global__ __launch_bounds__(RV_THR) void k_eq_res16(EqArgs a, int n_pts) {
 }
 
 // ------------------------------------------------------------------------
+// Full-order residual norms at reduced solutions, the indicator of the
+// greedy search, eq. (greedy0): for evaluation point pt, element e lifts
+// U_e = P_e^T Phi w, U_e' = P_e'^T Phi w (face-trace rows of the full basis)
+// and x_e = Q_e^T (X + Psi tau), evaluates R_e (values only, RV_LANES lanes
+// per element as k_eq_res16) and adds |R_e|^2.  Block b writes the sum of
+// its RV_SLOTS elements and the number of invalid ones; k_hdm_norm_final
+// adds the blocks of each point in block order.
+struct HdmRomArgs {
+  const double* Phi;   // [N_u][n]
+  const double* Psi;   // [N_x][m]
+  const double* w;     // [pt][n]
+  const double* tau;   // [pt][m]
+  const double* mu;    // [pt][2]
+  const int* gn;       // [Ne][nn]
+  const int* face;     // [Ne][3]
+  const int* Pn;       // [Ne][nun]
+  const double* X;     // [N_x]
+  PhysConst pc;
+  double eps, bc_mu_scale;
+  int n, m, n_elem, nblk;
+  double* part;        // [pt][nblk]
+  int* nbad;           // [pt][nblk]
+};
+
+template <class D, class R>
+__global__ __launch_bounds__(RV_THR) void k_hdm_res_rom(HdmRomArgs a) {
+  static_assert(n_point_tasks<D, false>() <= RV_LANES, "one point task per lane");
+  __shared__ ResShared<D, R> sh;
+  __shared__ double ssum[RV_SLOTS];
+  __shared__ int sbad[RV_SLOTS];
+  const int tid = threadIdx.x, g = tid / RV_LANES, j = tid % RV_LANES;
+  res_load_tab<D, R>(sh, tid);
+  const int pt = blockIdx.y;
+  const int e = blockIdx.x * RV_SLOTS + g;
+  const bool act = e < a.n_elem;
+  ElemVal<D, R>& el = sh.e[g];
+  const int n = a.n, m = a.m;
+  const double* w = a.w + (long long)pt * n;
+  const double* tau = a.tau + (long long)pt * m;
+  if (act) {
+    if (j < 3) el.face[j] = a.face[e * 3 + j];
+    if (j == 0) el.p.bad = 0;
+    for (int t = j; t < D::NUE + D::NUN + D::NXE; t += RV_LANES) {
+      if (t < D::NUE + D::NUN) {
+        const long long row = t < D::NUE ? (long long)e * D::NUE + t : (long long)a.Pn[(long long)e * D::NUN + t - D::NUE];
+        double acc = 0.0;
+        if (row >= 0) {
+          const double* ph = a.Phi + row * n;
+          for (int i = 0; i < n; ++i) acc += ph[i] * w[i];
+        }
+        if (t < D::NUE) el.U[t] = R(acc);
+        else el.Un[t - D::NUE] = R(acc);
+      } else {
+        const int r = t - D::NUE - D::NUN;
+        const long long c = 2LL * a.gn[(long long)e * D::NN + r / 2] + (r & 1);
+        double acc = a.X[c];
+        const double* ps = a.Psi + c * m;
+        for (int i = 0; i < m; ++i) acc += ps[i] * tau[i];
+        el.x[r] = R(acc);
+        el.X[r] = R(a.X[c]);
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+    const PhysConst pc = phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt);
+    if (j < D::NQV) {
+      vol_point<D, R, R>(sh.tab, el, j, -1, pc, R(a.eps));
+    } else if (j < D::NQV + 3 * D::NQF) {
+      const int r = j - D::NQV;
+      face_point<D, R, R>(sh.tab, el, r / D::NQF, r % D::NQF, -1, pc);
+    }
+  }
+  __syncthreads();
+  double ss = 0.0;
+  if (act)
+    for (int r = j; r < D::NUE; r += RV_LANES) {
+      const double v = double(residual_entry_p<D, R>(el.p, sh.tab, r));
+      ss += v * v;
+    }
+#pragma unroll
+  for (int o = RV_LANES / 2; o > 0; o >>= 1) ss += __shfl_xor(ss, o, RV_LANES);
+  if (j == 0) {
+    ssum[g] = ss;
+    sbad[g] = act && el.p.bad != 0 ? 1 : 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    int b = 0;
+    for (int q = 0; q < RV_SLOTS; ++q) {
+      t += ssum[q];
+      b += sbad[q];
+    }
+    a.part[(long long)pt * a.nblk + blockIdx.x] = t;
+    a.nbad[(long long)pt * a.nblk + blockIdx.x] = b;
+  }
+}
+
+// |R|_2 of each point from the block sums (fixed order), +inf if any
+// element is invalid; n_bad (may be null) receives the count.
+__global__ __launch_bounds__(256) void k_hdm_norm_final(const double* part, const int* nbad, int nblk, double* norms,
+                                                        int* n_bad) {
+  __shared__ double sp[256];
+  __shared__ int sb[256];
+  const int pt = blockIdx.x, t = threadIdx.x;
+  double v = 0.0;
+  int b = 0;
+  for (int i = t; i < nblk; i += 256) {
+    v += part[(long long)pt * nblk + i];
+    b += nbad[(long long)pt * nblk + i];
+  }
+  sp[t] = v;
+  sb[t] = b;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (t < d) {
+      sp[t] += sp[t + d];
+      sb[t] += sb[t + d];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    norms[pt] = sb[0] ? __builtin_inf() : sqrt(sp[0]);
+    if (n_bad) n_bad[pt] = sb[0];
+  }
+}
+
+// ------------------------------------------------------------------------
 // EQ assembly in factorized form.  With the point Jacobians of phase B,
 //   A_e = dR/dU_e Phi_e + dR/dU_e' Phi_e' = Aw * Bw,
 //   B_e = dR/dx_e Psi_e                  = Ax * Bx,

@@ -64,6 +64,8 @@ EXPORTS = {
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(ctypes.c_longlong)]),
     "hdm_assemble": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "hdm_residual_norm_batched": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P, _P, ctypes.c_int, _P,
+                                                 _P, _P, _P]),
     "ift_rom_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), _D, ctypes.c_int, ctypes.POINTER(_P)]),
     "ift_rom_destroy": (None, [_P]),
@@ -194,6 +196,27 @@ class Problem:
                                 _ptr(dRdUn, Ne * nue * nun, f64), _ptr(dRdx, Ne * nue * nxe, f64),
                                 _ptr(dNdx, Ne * nxe, f64), _ptr(n_bad, 1, torch.int32), _stream(stream))
         _check(st, "hdm_assemble")
+
+    def hdm_residual_norms(self, mu, Phi, w, Psi, tau, norms, n_bad=None, stream=None):
+        """hdm_residual_norm_batched: |R(Phi w_p; X + Psi tau_p, mu_p)|_2 for
+        each row p of mu [P,2], w [P,n], tau [P,m] (device tensors), with the
+        full bases Phi [N_u,n], Psi [N_x,m]; norms [P], n_bad [P] (int32)."""
+        import torch
+        f64 = torch.float64
+        P, n = w.shape
+        m = Psi.shape[1] if Psi is not None else 0
+        st = lib().hdm_residual_norm_batched(self.handle, int(P), _ptr(mu, 2 * P, f64), _ptr(Phi, self.N_u * n, f64),
+                                             int(n), _ptr(w, P * n, f64), _ptr(Psi, self.N_x * m, f64), int(m),
+                                             _ptr(tau, P * m, f64), _ptr(norms, P, f64),
+                                             _ptr(n_bad, P, torch.int32), _stream(stream))
+        _check(st, "hdm_residual_norm_batched")
+
+
+def greedy_select(norms) -> int:
+    """Index of the candidate with the largest full-order residual norm, the
+    next training parameter of eq. (greedy0) (host-side argmax)."""
+    v = np.asarray(norms.cpu().numpy() if hasattr(norms, "cpu") else norms, dtype=np.float64)
+    return int(np.argmax(v))
 
 
 class ROM:

@@ -106,3 +106,8 @@ def test_mlp_arguments_rejected():
     assert L.ift_mlp_train(None, None, None, 1, 1, 1e-3, None, None) == ift.IFT_EINVAL
     assert L.ift_mlp_predict(None, None, 1, None, 0, None) == ift.IFT_EINVAL
     L.ift_mlp_destroy(None)
+
+
+def test_residual_norm_arguments_rejected():
+    ift, L = _lib()
+    assert L.hdm_residual_norm_batched(None, 1, None, None, 1, None, None, 0, None, None, None, None) == ift.IFT_EINVAL

@@ -323,6 +323,43 @@ def test_gauss_newton_w_only_step_parity(tiny_case, qr):
         raise AssertionError("the w-only iteration did not converge in 12 steps")
 
 
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+def test_hdm_residual_norms_match_oracle(which, request):
+    """The greedy indicator, eq. (greedy0): |R(Phi w; X + Psi tau, mu)|_2 over
+    all elements for several reduced points in one call, against the norm of
+    the oracle's full-order residual; an invalid point reports +inf and its
+    invalid elements; the argmax is the same candidate."""
+    import torch
+    from oracle import residual as ors
+    from paper_2305_15661_amd import ift
+    case = request.getfixturevalue(which)
+    wl, d = case.wl, case.dev
+    ks = [0, 3, 6, 9]
+    mu2 = lambda v: np.r_[np.atleast_1d(v), 0.0][:2]          # [n_pts][2] layout (Burgers uses mu[0])
+    mus = np.stack([mu2(wl.mus[k]) for k in ks] + [mu2(wl.mus[0])])
+    ws = np.stack([wl.w_eval[k] for k in ks] + [wl.w_eval[0]])
+    taus = np.stack([wl.tau_eval[k] for k in ks] + [80.0 * wl.tau_eval[0]])
+    P = len(mus)
+    norms, nb = _z(P, d), _z(P, d, torch.int32)
+    _say(f"residual norms {wl.name}")
+    case.prob.hdm_residual_norms(_t(mus, d), _t(wl.Phi, d), _t(ws, d), _t(wl.Psi, d), _t(taus, d), norms, nb)
+    torch.cuda.synchronize()
+    g, gb = norms.cpu().numpy(), nb.cpu().numpy()
+    ref = []
+    for p in range(P):
+        mu_o = wl.mus[ks[p]] if p < len(ks) else wl.mus[0]
+        o = ors.hdm_assemble(case.oprob, mu_o, wl.Phi @ ws[p], wl.X + wl.Psi @ taus[p], jac=False)
+        if o["n_bad"]:
+            assert np.isinf(g[p]) and gb[p] == o["n_bad"] > 0
+            ref.append(np.inf)
+        else:
+            r = np.linalg.norm(o["R"])
+            assert abs(g[p] - r) <= 1e-12 * r and gb[p] == 0
+            ref.append(r)
+    assert np.isinf(ref[-1])
+    assert ift.greedy_select(g[:-1]) == int(np.argmax(ref[:-1]))
+
+
 def test_full_size_euler_samples(dev):
     """16384 P2 elements, 819 EQ elements, n = 20, m = 10 (the benchmark
     shape): full EQ assembly against the oracle, and the full-order residual
