@@ -378,6 +378,67 @@ def warm_start_leg(dev, n_train: int = 4096, n_test: int = 1024, train_steps: in
             "setup_seconds": time.perf_counter() - t0}
 
 
+def eqp_leg(dev, n_train: int = 8):
+    """EQ-weight training at the C1 shape: a ROM over all 16384 elements with
+    unit weights, its solutions at n_train training parameters (Gauss-Newton
+    steps on the device from the plain start), the elemental reduced
+    residuals at each solution on the device, and the linear program of the
+    paper's weight training solved on the host (HiGHS)."""
+    import torch
+    import synth
+    from scipy.stats import qmc
+    from paper_2305_15661_amd import eqp, ift
+    wl = synth.euler_p2()
+    prob = ift.Problem.from_workload(wl)
+    Ne = wl.mesh.n_elem
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), device=dev)
+    rom = ift.ROM(prob, t(wl.Phi), t(wl.Psi), np.arange(Ne, dtype=np.int32), np.ones(Ne))
+    sob = qmc.Sobol(d=2, scramble=True, seed=1010).random(n_train)
+    mus = np.stack([2.0 + sob[:, 0], -5.0 + 10.0 * sob[:, 1]], axis=1)
+    sols, t_solve, conv = [], 0.0, 0
+    for mu in mus:
+        w = torch.zeros(rom.n, dtype=torch.float64, device=dev)
+        tau = torch.zeros(rom.m, dtype=torch.float64, device=dev)
+        rom.plain_start(mu, w, tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(BATCH_MAX_IT):
+            st, info = rom.gauss_newton_step(mu, w, tau, lam=BATCH_LAMBDA)
+            if info["converged"] or st != 0:
+                break
+        torch.cuda.synchronize()
+        t_solve += time.perf_counter() - t0
+        conv += int(info["converged"])
+        sols.append((mu, w, tau))
+    C = torch.zeros(Ne * rom.D, dtype=torch.float64, device=dev)
+    contribs = []
+    rom.element_contributions(sols[0][0], sols[0][1], sols[0][2], C)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for mu, w, tau in sols:
+        rom.element_contributions(mu, w, tau, C)
+        contribs.append(C.cpu().numpy().reshape(Ne, rom.D).copy())
+    t_contrib = time.perf_counter() - t0
+    vol = eqp.element_volumes(wl.mesh.X, wl.mesh.elem_gnodes)
+    # accuracy tolerance relative to the elemental residuals (their sum, the
+    # reduced residual at a solution, is near zero); volume within 1 %
+    scale = max(float(np.abs(Cj).max()) for Cj in contribs)
+    delta = 1e-3 * scale
+    t0 = time.perf_counter()
+    rho, info = eqp.train_weights(contribs, vol, delta, delta_vol=1e-2)
+    t_lp = time.perf_counter() - t0
+    frac = info.get("nnz", Ne) / Ne
+    log(f"eq training: {conv}/{n_train} training solves in {t_solve:.2f} s; elemental residuals of {Ne} elements "
+        f"x {n_train} solutions in {t_contrib * 1e3:.1f} ms (incl. copies); program {2 + 2 * n_train * rom.D} x {Ne} "
+        f"solved in {t_lp:.2f} s: {info.get('nnz')} non-zero weights ({100 * frac:.2f} %)")
+    return {"workload": f"ROM over all {Ne} P2 Euler elements, n=20, m=10, unit weights; {n_train} training "
+                        f"parameters (Sobol on [2,3] x [-5,5] deg)",
+            "training_solves_converged": conv, "training_solve_seconds": t_solve,
+            "contribution_seconds": t_contrib, "program_rows": 2 + 2 * n_train * rom.D, "program_cols": Ne,
+            "delta": delta, "lp_seconds": t_lp, "lp_status": info.get("status"), "nonzero_weights": info.get("nnz"),
+            "nonzero_fraction": frac, "max_violation": info.get("max_violation")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,6 +452,7 @@ def main():
     ap.add_argument("--batch-inst", type=int, default=1024, help="instances of the batched-solve leg")
     ap.add_argument("--batch-loop", type=int, default=64, help="instances timed in the per-instance loop")
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start leg")
+    ap.add_argument("--no-eqp", action="store_true", help="skip the EQ-weight training leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (traffic-counter calibration)")
     args = ap.parse_args()
@@ -517,6 +579,8 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_leg(args.batch_inst, args.batch_loop, dev)
 
+    if not args.no_eqp:
+        out["eq_training"] = eqp_leg(dev)
     if not args.no_warm:
         out["warm_start"] = warm_start_leg(dev)
 

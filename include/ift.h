@@ -186,6 +186,17 @@ ift_status eq_assemble_jacobian(ift_rom* rom, const double* mu, const double* w,
                                 double* Jobj, double* g, double* H, double* Jt, int* n_bad,
                                 hipStream_t stream);
 
+/* The elemental reduced residuals of eq. (ift-eqp-res0), the data of the
+ * EQ-weight training program eq. (eqp-lp)-(eqp-con): for every sampled
+ * element k (element e_k = eq_elem[k]) at (mu, w, tau),
+ *   C[k] = [S^(e_k); T^(e_k)] = [A_k R_k; a_k N_k] contracted as in g,
+ * WITHOUT the weight rho_k (so that sum_k rho_k C[k] = [S~; T~]).  Build the
+ * ROM on all elements with rho = 1 to obtain the columns of the program at
+ * a training solution.  mu HOST [2]; w, tau, C DEVICE; C [n_s][n + m]
+ * row-major.  rho_k must be nonzero. */
+ift_status eq_element_contributions(ift_rom* rom, const double* mu, const double* w, const double* tau, double* C,
+                                    hipStream_t stream);
+
 /* Batched evaluation: n_pts evaluation points (mu_p, w_p, tau_p) of the same
  * ROM in one launch (e.g. many parameters, or several line-search trial
  * points).  ift_rom_reserve sizes the per-point workspaces for up to

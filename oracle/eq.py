@@ -78,8 +78,15 @@ class ROM:
         sq = np.sqrt(rho)
         Jt = np.vstack([(sq[:, None, None] * AB).reshape(-1, self.n + self.m), sq[:, None] * a0])
         Ft = np.r_[(sq[:, None] * R).ravel(), sq * N]
+        C = np.einsum("krz,kr->kz", AB, R) + a0 * N[:, None]
         return {"J": np.inf if invalid else J, "J_raw": J, "g": g, "H": H, "Jt": Jt, "Ft": Ft,
-                "invalid": invalid, "elem": r, "A": A, "B": B, "a": a}
+                "invalid": invalid, "elem": r, "A": A, "B": B, "a": a, "C": C}
+
+    def element_contributions(self, mu, w, tau):
+        """The elemental reduced residuals of eq. (ift-eqp-res0), one row per
+        sampled element and without the weight: C[k] = [S^(e_k); T^(e_k)],
+        so that g = sum_k rho_k C[k]."""
+        return self.jacobian(mu, w, tau)["C"]
 
 
 def plain_start(wl, mu):

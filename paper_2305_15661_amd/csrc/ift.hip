@@ -1027,6 +1027,25 @@ extern "C" ift_status eq_assemble_jacobian(ift_rom* r, const double* mu, const d
   return IFT_OK;
 }
 
+extern "C" ift_status eq_element_contributions(ift_rom* r, const double* mu, const double* w, const double* tau,
+                                               double* C, hipStream_t stream) {
+  if (!r || !w || (r->m > 0 && !tau) || !C || !finite_mu(r->prob, mu)) return IFT_EINVAL;
+  if (!lazy_points(r)) return IFT_ENOMEM;
+  EqArgs a = eq_args(r, mu, w, tau);
+  ift_status s;
+  if (r->fused_nt > 0) {
+    s = eq_jacobian_fused(r, a, 1, r->d_H, r->d_g, r->d_J, r->d_nbad, true, stream);
+  } else {
+    s = dispatch_eq(r, a, true, 1, stream);
+    if (s == IFT_OK) s = gram(r, 1, r->d_H, r->d_g, r->d_J, r->d_nbad, stream);
+  }
+  if (s != IFT_OK) return s;
+  const long long cnt = (long long)r->n_s * r->D;
+  hipLaunchKernelGGL(k_elem_contrib, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, (const double*)r->d_Jt,
+                     (const double*)r->d_Ft, (const double*)r->d_rho, r->n_s, r->prob->nue, r->D, C);
+  return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
 extern "C" ift_status eq_assemble_residual_batch(ift_rom* r, int n_pts, const double* mu, const double* w,
                                                  const double* tau, double* Jobj, int* n_bad, hipStream_t stream) {
   if (r && !lazy_points(r)) return IFT_ENOMEM;

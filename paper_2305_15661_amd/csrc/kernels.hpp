@@ -1703,6 +1703,25 @@ __global__ __launch_bounds__(QR_RB) void k_qr_rows(QrArgs q, int last) {
   }
 }
 
+// Elemental reduced residuals of eq. (ift-eqp-res0) from the stacked rows of
+// one evaluation point, Jt = sqrt(rho) [A; a] and Ft = sqrt(rho) [R; N]:
+// C[k][j] = (sum_r Jt[k nue + r][j] Ft[k nue + r] + Jt[n_s nue + k][j]
+// Ft[n_s nue + k]) / rho_k, i.e. [S^(e_k); T^(e_k)] without the weight.
+__global__ void k_elem_contrib(const double* Jt, const double* Ft, const double* rho, int n_s, int nue, int D,
+                               double* C) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n_s * D) return;
+  const int k = (int)(t / D), j = (int)(t % D);
+  double v = 0.0;
+  for (int r = 0; r < nue; ++r) {
+    const long long row = (long long)k * nue + r;
+    v += Jt[row * D + j] * Ft[row];
+  }
+  const long long rd = (long long)n_s * nue + k;
+  v += Jt[rd * D + j] * Ft[rd];
+  C[t] = v / rho[k];
+}
+
 __global__ void k_axpy2(const double* w, const double* tau, const double* dz, double alpha, int n, int m,
                         double* wo, double* to) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -64,6 +64,7 @@ EXPORTS = {
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(ctypes.c_longlong)]),
     "hdm_assemble": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "eq_element_contributions": (ctypes.c_int, [_P, _D, _P, _P, _P, _P]),
     "hdm_residual_norm_batched": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P, _P, ctypes.c_int, _P,
                                                  _P, _P, _P]),
     "ift_rom_create": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int,
@@ -270,6 +271,15 @@ class ROM:
                                         _ptr(Jt, self.nrows * self.D, f64), _ptr(n_bad, 1, torch.int32),
                                         _stream(stream))
         _check(st, "eq_assemble_jacobian")
+
+    def element_contributions(self, mu, w, tau, C, stream=None):
+        """eq_element_contributions: C [n_s, n+m] device tensor of the
+        unweighted elemental reduced residuals at (mu, w, tau)."""
+        import torch
+        f64 = torch.float64
+        st = lib().eq_element_contributions(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
+                                            _ptr(C, self.n_s * self.D, f64), _stream(stream))
+        _check(st, "eq_element_contributions")
 
     def reserve(self, max_pts: int):
         _check(lib().ift_rom_reserve(self.handle, int(max_pts)), "ift_rom_reserve")

@@ -360,6 +360,27 @@ def test_hdm_residual_norms_match_oracle(which, request):
     assert ift.greedy_select(g[:-1]) == int(np.argmax(ref[:-1]))
 
 
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+def test_element_contributions_match_oracle(which, request):
+    """The data of the EQ-weight training program: unweighted elemental
+    reduced residuals against the oracle's (1e-12), and sum_k rho_k C[k]
+    equal to the device gradient."""
+    import torch
+    case = request.getfixturevalue(which)
+    wl, d, r = case.wl, case.dev, case.rom
+    for k in (2, 11):
+        mu, w, tau = wl.mus[k], wl.w_eval[k], wl.tau_eval[k]
+        _say(f"element contributions {wl.name} point {k}")
+        C = _z(r.n_s * r.D, d)
+        r.element_contributions(mu, _t(w, d), _t(tau, d), C)
+        g = _eq_gpu(case, mu, w, tau)["g"]
+        torch.cuda.synchronize()
+        Cg = C.cpu().numpy().reshape(r.n_s, r.D)
+        Co = case.orom.element_contributions(mu, w, tau)
+        assert rel(Cg, Co) < 1e-12
+        assert rel(case.eq_rho @ Cg, g) < 1e-12
+
+
 def test_full_size_euler_samples(dev):
     """16384 P2 elements, 819 EQ elements, n = 20, m = 10 (the benchmark
     shape): full EQ assembly against the oracle, and the full-order residual
