@@ -4,8 +4,14 @@
 //
 // Every instance carries a small state machine (BatchState):
 //   BS_JAC     needs the Jacobian assembly at its iterate z,
-//   BS_SEARCH  has a step dz and tries z + alpha dz,
+//   BS_VERIFY  has taken the full step z <- z + dz (the previous iterate
+//              kept in zt) and needs the Jacobian assembly there, whose
+//              objective decides the Armijo test at alpha = 1,
+//   BS_SEARCH  backtracks: tries z + alpha dz, alpha = 1/2, 1/4, ...,
 //   BS_DONE    converged or stopped (status says why).
+// The full step is taken before its test because nearly every accepted
+// step has alpha = 1: the assembly at the new iterate then serves both the
+// test and the next step, and a rejected full step only restores z.
 // Each phase starts with k_batch_compact, which scans the instances in the
 // phase's state into work lists (exclusive sums of their element or block
 // counts); the work kernels are persistent grids that walk those lists, so
@@ -18,7 +24,7 @@
 
 namespace ift {
 
-enum { BS_JAC = 0, BS_SEARCH = 1, BS_DONE = 2 };
+enum { BS_JAC = 0, BS_SEARCH = 1, BS_DONE = 2, BS_VERIFY = 3 };
 
 // One instance: its ROM's element data and its slices of the batch
 // workspace.  a.w / a.tau point at the current iterate z, a.mu at its mu.
@@ -53,6 +59,7 @@ struct BatchState {
   int it_w;           // steps taken in w only
   double lam;         // LM weight of the next step
   double J, J0, Jtrial, alpha, slope, nS, nT, alpha_acc;
+  double Jprev;       // objective at the previous iterate (BS_VERIFY)
 };
 
 struct BatchParams {
@@ -97,8 +104,10 @@ constexpr int BC_THR = 1024;
 // Exclusive sums of the element and block counts of the instances in state
 // `want` (and, if want_prec >= 0, in that precision phase); one block,
 // fixed order.  with_blocks = 0 leaves the block lists empty.
+// (The Jacobian phase, want = BS_JAC, also takes the BS_VERIFY instances.)
 IFT_DEV bool batch_active(const BatchState& st, int want, int want_prec) {
-  return st.state == want && (want_prec < 0 || st.prec == want_prec);
+  const bool in = st.state == want || (want == BS_JAC && st.state == BS_VERIFY);
+  return in && (want_prec < 0 || st.prec == want_prec);
 }
 
 __global__ __launch_bounds__(BC_THR) void k_batch_compact(const BatchInst* I, const BatchState* S, BatchLists L,
@@ -182,7 +191,7 @@ __global__ __launch_bounds__(NTHR, NT == 1 ? 3 : (NT == 3 ? 2 : 1)) void k_fused
 __global__ __launch_bounds__(256) void k_final_batch(const BatchInst* I, BatchState* S) {
   __shared__ double red[GF_GRP][GF_ENT];
   const int inst = blockIdx.y;
-  if (S[inst].state != BS_JAC) return;
+  if (S[inst].state != BS_JAC && S[inst].state != BS_VERIFY) return;
   const BatchInst& bi = I[inst];
   const int D1 = bi.a.D + 1;
   const int nbe = (D1 * (D1 + 1) / 2 + GF_ENT - 1) / GF_ENT;
@@ -192,7 +201,8 @@ __global__ __launch_bounds__(256) void k_final_batch(const BatchInst* I, BatchSt
                    blockIdx.x, 0, red);
 }
 
-// Convergence test and LM step of each JAC instance (one wave each).
+// Armijo test of a full step (BS_VERIFY) and then, as for a BS_JAC
+// instance, the convergence test and the next LM step (one wave each).
 __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState* S, const BatchParams* P) {
   __shared__ double L[64 * 64];
   __shared__ double y[64];
@@ -200,11 +210,38 @@ __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState*
   __shared__ int fail;
   const int inst = blockIdx.x;
   BatchState& st = S[inst];
-  if (st.state != BS_JAC) return;
+  const int state = st.state;
+  if (state != BS_JAC && state != BS_VERIFY) return;
   const BatchInst& bi = I[inst];
   const int D = bi.a.D, n = bi.a.n;
   const BatchParams p = *P;
   const double J = st.J;
+  double lam = st.lam;
+  if (state == BS_VERIFY) {
+    // J (+inf if invalid) is the objective at z = z_prev + dz
+    const bool ok = J <= st.Jprev + p.c1 * st.slope;
+    if (!ok) {
+      // restore the previous iterate; the backtracking continues from the
+      // first halving when that is what the trial at alpha = 1 would have
+      // led to, else it re-tries alpha = 1 and the line search decides
+      for (int i = threadIdx.x; i < D; i += 64) bi.z[i] = bi.zt[i];
+      if (threadIdx.x == 0) {
+        const bool halve = p.max_backtrack > 0 && !(st.prec == 1 && p.max_bt_mixed <= 0);
+        st.Jtrial = J;
+        st.J = st.Jprev;
+        st.alpha = halve ? 0.5 : 1.0;
+        st.n_bt = halve ? 1 : 0;
+        st.state = BS_SEARCH;
+      }
+      return;
+    }
+    if (p.adapt) lam = lam * 0.1 < 1e-12 ? 0.0 : lam * 0.1;
+    if (threadIdx.x == 0) {
+      st.Jtrial = J;
+      st.alpha_acc = 1.0;
+      st.lam = lam;
+    }
+  }
   if (!(J < __builtin_inf())) {   // invalid geometry or state at the iterate
     if (threadIdx.x == 0) {
       st.status = (st.flag_or & BAD_GEOM) ? IFT_EBADMESH : IFT_ENONPHYS;
@@ -217,53 +254,64 @@ __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState*
   // the same iterate
   const int wonly = st.wonly;
   const int prec = st.prec;
-  lm_solve_body(bi.H, bi.g, D, n, wonly ? n : D, st.lam, bi.dz, out, L, y, fail);
+  lm_solve_body(bi.H, bi.g, D, n, wonly ? n : D, lam, bi.dz, out, L, y, fail);
   bool w_step = wonly != 0;
   if (wonly && out[1] <= (prec == 1 ? p.tol_mix : p.tol)) {
-    lm_solve_body(bi.H, bi.g, D, n, D, st.lam, bi.dz, out, L, y, fail);
+    lm_solve_body(bi.H, bi.g, D, n, D, lam, bi.dz, out, L, y, fail);
     w_step = false;
   }
+  // the decision below, taken by every lane (all read the same values)
+  bool step;
+  int next_prec = prec;
+  int stop = 0;      // an error status that ends the solve
+  bool conv = false;
+  if (w_step) {
+    if (st.it >= p.max_it) stop = IFT_ENOTCONV;
+    else if (out[0] != 0.0) stop = IFT_ESINGULAR;
+    step = stop == 0;
+  } else if (prec == 1 && out[1] <= p.tol_mix && out[2] <= p.tol_mix) {
+    next_prec = 0;   // refine in FP64 from here; the state stays JAC
+    step = false;
+  } else if (out[1] <= p.tol && out[2] <= p.tol && prec == 0) {
+    conv = true;
+    step = false;
+  } else {
+    if (st.it >= p.max_it) stop = IFT_ENOTCONV;
+    else if (out[0] != 0.0) stop = IFT_ESINGULAR;
+    step = stop == 0;
+  }
+  __syncthreads();   // every lane has read the state before lane 0 writes it
+  if (step)   // keep z in zt and take the full step (same arithmetic as a trial at alpha = 1)
+    for (int i = threadIdx.x; i < D; i += 64) {
+      const double zi = bi.z[i];
+      bi.zt[i] = zi;
+      bi.z[i] = zi + 1.0 * bi.dz[i];
+    }
   if (threadIdx.x == 0) {
-    if (st.it == 0 && st.prec == 1) st.J0 = J;
-    if (st.it == 0 && st.prec == 0 && st.J0 == 0.0) st.J0 = J;
+    if (st.it == 0 && prec == 1) st.J0 = J;
+    if (st.it == 0 && prec == 0 && st.J0 == 0.0) st.J0 = J;
     st.nS = out[1];
     st.nT = out[2];
     if (!w_step) st.wonly = 0;
-    if (w_step) {
-      if (st.it >= p.max_it) {
-        st.status = IFT_ENOTCONV;
-        st.state = BS_DONE;
-      } else if (out[0] != 0.0) {
-        st.status = IFT_ESINGULAR;
-        st.state = BS_DONE;
-      } else {
-        st.slope = out[3];
-        st.alpha = 1.0;
-        st.n_bt = 0;
-        st.it += 1;
-        st.it_w += 1;
-        st.it_mixed += st.prec;
-        st.state = BS_SEARCH;
-      }
-    } else if (st.prec == 1 && out[1] <= p.tol_mix && out[2] <= p.tol_mix) {
-      st.prec = 0;   // refine in FP64 from here; the state stays JAC
-    } else if (out[1] <= p.tol && out[2] <= p.tol && st.prec == 0) {
+    st.prec = next_prec;
+    if (conv) {
       st.converged = 1;
       st.status = IFT_OK;
       st.state = BS_DONE;
-    } else if (st.it >= p.max_it) {
-      st.status = IFT_ENOTCONV;
+    } else if (stop != 0) {
+      st.status = stop;
       st.state = BS_DONE;
-    } else if (out[0] != 0.0) {
-      st.status = IFT_ESINGULAR;
-      st.state = BS_DONE;
-    } else {
+    } else if (step) {
       st.slope = out[3];
+      st.Jprev = J;
       st.alpha = 1.0;
       st.n_bt = 0;
       st.it += 1;
-      st.it_mixed += st.prec;
-      st.state = BS_SEARCH;
+      st.it_w += w_step ? 1 : 0;
+      st.it_mixed += prec;
+      st.state = BS_VERIFY;
+    } else {
+      st.state = BS_JAC;
     }
   }
 }
