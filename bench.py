@@ -26,6 +26,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -241,7 +242,8 @@ def batched_leg(n_inst: int, n_loop: int, dev):
     n_elem = bw.base.mesh.n_elem
     greedy = {"candidates": n_inst, "elements": n_elem, "seconds": t_greedy,
               "element_evals_per_s": n_inst * n_elem / t_greedy, "argmax": best,
-              "mu_argmax": [float(v) for v in bw.mus[best]], "norm_max": float(norms[best])}
+              "mu_argmax": [float(v) for v in bw.mus[best]], "norm_max": float(norms[best]),
+              "invalid_candidates": int(np.count_nonzero(~np.isfinite(norms)))}
     log(f"greedy indicator: {n_inst} candidates x {n_elem} elements in {t_greedy * 1e3:.1f} ms "
         f"({greedy['element_evals_per_s']:.3e} element-evals/s); next parameter {greedy['mu_argmax']}")
     # the same FP64 batch with the paper's initialisation (steps in w with
@@ -439,6 +441,18 @@ def eqp_leg(dev, n_train: int = 8):
             "nonzero_fraction": frac, "max_violation": info.get("max_violation")}
 
 
+def _finite(o):
+    """The result with every non-finite float (an invalid candidate's norm)
+    replaced by None, so that the line is strict JSON."""
+    if isinstance(o, dict):
+        return {k: _finite(v) for k, v in o.items()}
+    if isinstance(o, (list, tuple)):
+        return [_finite(v) for v in o]
+    if isinstance(o, float) and not math.isfinite(o):
+        return None
+    return o
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -621,7 +635,7 @@ def main():
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.1f} evals/s")
-    print(json.dumps(out))
+    print(json.dumps(_finite(out), allow_nan=False))
 
 
 if __name__ == "__main__":

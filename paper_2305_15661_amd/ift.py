@@ -215,8 +215,11 @@ class Problem:
 
 def greedy_select(norms) -> int:
     """Index of the candidate with the largest full-order residual norm, the
-    next training parameter of eq. (greedy0) (host-side argmax)."""
+    next training parameter of eq. (greedy0) (host-side argmax).  A
+    non-finite norm (the lifted state of that reduced solution is invalid)
+    ranks above every finite one; ties go to the lowest index."""
     v = np.asarray(norms.cpu().numpy() if hasattr(norms, "cpu") else norms, dtype=np.float64)
+    v = np.where(np.isfinite(v), v, np.inf)
     return int(np.argmax(v))
 
 

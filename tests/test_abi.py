@@ -111,3 +111,12 @@ def test_mlp_arguments_rejected():
 def test_residual_norm_arguments_rejected():
     ift, L = _lib()
     assert L.hdm_residual_norm_batched(None, 1, None, None, 1, None, None, 0, None, None, None, None) == ift.IFT_EINVAL
+
+
+def test_greedy_select_ranks_invalid_candidates_first():
+    from paper_2305_15661_amd import ift
+    # host-side argmax of eq. (greedy0): an invalid lifted state (+inf or
+    # NaN norm) is the candidate most in need of a full-order solve
+    assert ift.greedy_select(np.array([0.1, 3.0, 2.0])) == 1
+    assert ift.greedy_select(np.array([0.1, 3.0, np.inf, np.nan])) == 2
+    assert ift.greedy_select(np.array([0.1, np.nan, 3.0])) == 1
