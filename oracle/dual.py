@@ -117,6 +117,12 @@ def sqrt(a: Dual) -> Dual:
     return Dual(r, a.d / (2.0 * r)[..., None])
 
 
+def exp(a: Dual) -> Dual:
+    a = _as_dual(a)
+    r = np.exp(a.v)
+    return Dual(r, a.d * r[..., None])
+
+
 def absd(a: Dual) -> Dual:
     a = _as_dual(a)
     s = np.where(a.v >= 0.0, 1.0, -1.0)

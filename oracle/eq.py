@@ -96,7 +96,8 @@ def plain_start(wl, mu):
     solver remark in Section 3.1.3.)"""
     from . import physics as ph
     if wl.pde == "burgers":
-        Ufs = np.full(wl.N_u, ph.burgers_inflow(mu, wl.bc_mu_scale))
+        Ufs = np.full(wl.N_u, ph.burgers_boundary_values(
+            mu, {"bc_mu_scale": wl.bc_mu_scale, "bc_spacetime": getattr(wl, "bc_spacetime", False)})[0])
     else:
         Ufs = np.tile(ph.euler_free_stream(mu, wl.gamma), wl.N_u // 4)
     return wl.Phi.T @ Ufs, np.zeros(wl.Psi.shape[1])

@@ -23,7 +23,9 @@ def physical_residual(wl, mu, U, x):
     nn = wl.n_nodes
     mesh = wl.mesh
     Ne = mesh.n_elem
-    prm = {"gamma": wl.gamma, "bc_mu_scale": wl.bc_mu_scale, "all_farfield": wl.all_farfield}
+    prm = {"gamma": wl.gamma, "bc_mu_scale": wl.bc_mu_scale, "all_farfield": wl.all_farfield,
+           "bc_spacetime": getattr(wl, "bc_spacetime", False)}
+    amp = getattr(wl, "src_amp", 0.0) if wl.pde == "burgers" else 0.0
     Ue = U.reshape(Ne, nn, nc)
     xe = x.reshape(-1, 2)[mesh.elem_gnodes]                      # [Ne, nn, 2]
     xq, wq = re.volume_rule(p)
@@ -36,6 +38,10 @@ def physical_residual(wl, mu, U, x):
             u = phi[q] @ Ue[e]
             f = ph.flux(wl.pde, u[None], prm).v[0]               # [nc, 2]
             R[e] -= wq[q] * np.linalg.det(J) * gradx @ f.T
+            if amp != 0.0:
+                # - int phi_i s dx over the physical element, s at the point's x
+                xpt = phi[q] @ xe[e]
+                R[e, :, 0] -= wq[q] * np.linalg.det(J) * phi[q] * (amp * np.exp(float(mu[1]) * xpt[0]))
         s, ws = re.face_rule(p)
         for fi in range(3):
             pts = re.face_points(fi, s)

@@ -1,7 +1,8 @@
 """Fluxes, numerical fluxes and boundary states (oracle; test infrastructure).
 
 Physical fluxes are the paper's: the space-time Burgers flux (u^2/2, u) of
-eq. (burgers) without source, and the Euler flux of eq. (euler) with the
+eq. (burgers) with its source s(x; (a, b)) = s_0 exp(b x) (s_0 = 0.02 in the
+paper; 0 switches it off), and the Euler flux of eq. (euler) with the
 ideal-gas pressure P = (gamma-1)(rho E - rho |v|^2 / 2).  The paper does not
 name its numerical fluxes; the readings here are a local Lax-Friedrichs flux
 for Burgers and Roe's approximate Riemann solver with Harten's entropy fix
@@ -14,7 +15,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .dual import Dual, absd, lift, maximum, sqrt, stack, where
+from .dual import Dual, absd, exp, lift, maximum, sqrt, stack, where
 
 
 def _nd(*xs):
@@ -143,12 +144,29 @@ def burgers_inflow(mu, bc_mu_scale):
     return 1.0 + bc_mu_scale * float(mu[0])
 
 
+def burgers_boundary_values(mu, params):
+    """(u+ on tag 1, u+ on tag 3).  The space-time problem of eq. (burgers)
+    (``bc_spacetime``) prescribes u(0, t) = a = mu[0] on the left edge and
+    the initial state u(x, 0) = 1 on the bottom edge; otherwise both edges
+    take the inflow value 1 + bc_mu_scale mu[0]."""
+    if params.get("bc_spacetime", False):
+        return float(mu[0]), 1.0
+    ub = burgers_inflow(mu, params["bc_mu_scale"])
+    return ub, ub
+
+
+def burgers_source(xphys, mu, amp):
+    """s(x; (a, b)) = amp exp(b x) of eq. (burgers) at the physical first
+    coordinate x (array or Dual), b = mu[1]."""
+    return amp * exp(float(mu[1]) * xphys)
+
+
 def boundary_state(pde, tag, uL, nt, mu, params):
     """Exterior state on a boundary face with tag 1 (left), 2 (right),
     3 (bottom) or 4 (top).
 
-    Burgers: tags 1 and 3 inflow u+ = 1 + bc_mu_scale mu; tags 2 and 4
-    outflow u+ = u-.  Euler: tag 1 supersonic inflow u+ = U_inf(mu); tag 2
+    Burgers: tags 1 and 3 inflow (``burgers_boundary_values``); tags 2
+    and 4 outflow u+ = u-.  Euler: tag 1 supersonic inflow u+ = U_inf(mu); tag 2
     supersonic outflow u+ = u-; tags 3 and 4 slip walls
     u+ = (rho, rho v - 2 (rho v . n) n, rho E) with n = nt / |nt|.
     With ``all_farfield`` every Euler tag takes u+ = U_inf(mu).
@@ -157,7 +175,7 @@ def boundary_state(pde, tag, uL, nt, mu, params):
     uL = lift(uL, nd)
     if pde == "burgers":
         if tag in (1, 3):
-            ub = burgers_inflow(mu, params["bc_mu_scale"])
+            ub = burgers_boundary_values(mu, params)[0 if tag == 1 else 1]
             return lift(np.full(uL.shape, ub), nd)
         return uL
     gamma = params["gamma"]

@@ -32,7 +32,8 @@ from .dual import Dual, ein, lift, maximum, stack, where
 
 def params_of(wl) -> dict:
     return {"pde": wl.pde, "p": wl.p, "n_c": wl.n_c, "gamma": wl.gamma, "kappa": wl.kappa,
-            "eps_g": wl.eps_g, "bc_mu_scale": wl.bc_mu_scale, "all_farfield": wl.all_farfield}
+            "eps_g": wl.eps_g, "bc_mu_scale": wl.bc_mu_scale, "all_farfield": wl.all_farfield,
+            "src_amp": getattr(wl, "src_amp", 0.0), "bc_spacetime": getattr(wl, "bc_spacetime", False)}
 
 
 # ------------------------------------------------------------ gather maps
@@ -111,6 +112,12 @@ def element_residual(prm, U_e, x_e, X_e, nbr_e, mu, trace_plus):
     grad0 = np.einsum("eqba,qnb->eqna", J0inv, dphi)             # J0^{-T} grad_xi phi
     vol = ein("eqcb,eqnb->eqnc", F, grad0)
     R = -1.0 * ein("eqnc,eq->enc", vol, wq[None, :] * detJ0)
+    if pde == "burgers" and prm.get("src_amp", 0.0) != 0.0:
+        # source of eq. (burgers) on the reference domain: S = g s(x(X)),
+        # at the mapped physical position x = sum_n x_n phi_n
+        xq_phys = ein("qn,ena->eqa", phi, x_e)
+        src = ph.burgers_source(xq_phys[..., 0], mu, prm["src_amp"]) * g
+        R = R - ein("qn,eq->en", phi, src * (wq[None, :] * detJ0))[..., None]
     bad = (g.v <= prm["eps_g"]).any(axis=1)
     nonphys = np.zeros(U_e.shape[0], dtype=bool)
     if pde == "euler":

@@ -12,6 +12,10 @@ Workloads
                    40 EQ elements.  Stands in for the shape of the paper's
                    Burgers benchmark (P1 simplices, scalar, space-time flux;
                    Section 4.1).
+``spacetime_burgers``  the paper's space-time Burgers problem (Section 4.1)
+                   on (0, 100) x (0, 50): source amplitude 0.02, inflow
+                   u = mu[0] at x = 0 and u = 1 at t = 0, mu = (a, b) in
+                   [3, 9] x [0.02, 0.075]; P1 or P2 on an nx x ny mesh.
 ``euler_p2``       P2 compressible Euler on a 128x64-cell mesh of [0,2]x[0,1]
                    (16384 elements), n = 20, m = 10, 819 EQ elements (5 %).
                    Stands in for the shape of the paper's NACA0012 benchmark
@@ -48,6 +52,8 @@ class Workload:
     gamma: float = GAMMA
     bc_mu_scale: float = 0.5  # Burgers inflow u_b = 1 + bc_mu_scale * mu[0]
     all_farfield: bool = False
+    src_amp: float = 0.0      # Burgers source amplitude s_0 (s = s_0 exp(mu[1] x)); 0: none
+    bc_spacetime: bool = False  # Burgers: u = mu[0] on the left edge, u = 1 on the bottom edge
     extra: dict = field(default_factory=dict)
 
     @property
@@ -192,6 +198,27 @@ def tiny_burgers(n_eval: int = 16, nx: int = 8, ny: int = 8, n: int = 4, n_s: in
     mus = np.full((n_eval, 1), 0.3)
     return Workload("tiny_burgers", "burgers", 1, mesh, 1, Phi, Psi, eq_elem, eq_rho,
                     mus, w, tau, kappa=kappa)
+
+
+def spacetime_burgers(n_eval: int = 16, nx: int = 8, ny: int = 8, p: int = 1, n: int = 4, m: int = 4,
+                      n_s: int = 40, kappa: float = 0.1) -> Workload:
+    """Space-time Burgers on (0, 100) x (0, 50) with the paper's source and
+    initial/boundary data; mapping modes as for the Euler workload, with
+    amplitude 5 % of the domain height."""
+    mesh = structured_mesh(nx, ny, 100.0, 50.0, p)
+    nn = (p + 1) * (p + 2) // 2
+    N_u = mesh.n_elem * nn
+    Phi = orthonormal_columns(np.random.default_rng(1001).standard_normal((N_u, n)))
+    Psi = psi_euler(mesh, m, A=2.5)
+    rng = np.random.default_rng(1003)
+    eq_elem = np.sort(rng.choice(mesh.n_elem, size=min(n_s, mesh.n_elem), replace=False)).astype(np.int32)
+    eq_rho = rng.uniform(0.5, 2.0, size=eq_elem.shape[0])
+    rng = np.random.default_rng(1004)
+    w = np.sqrt(N_u / n) * rng.standard_normal((n_eval, n))
+    tau = np.stack([_rescale_l1(rng.uniform(-1, 1, m)) for _ in range(n_eval)])
+    mus = np.stack([rng.uniform(3.0, 9.0, n_eval), rng.uniform(0.02, 0.075, n_eval)], axis=1)
+    return Workload(f"spacetime_burgers_p{p}", "burgers", p, mesh, 1, Phi, Psi, eq_elem, eq_rho,
+                    mus, w, tau, kappa=kappa, src_amp=0.02, bc_spacetime=True)
 
 
 def euler_p2(nx: int = 128, ny: int = 64, n: int = 20, m: int = 10, n_s: int | None = None,

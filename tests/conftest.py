@@ -28,6 +28,20 @@ def tiny():
 
 
 @pytest.fixture(scope="session")
+def st_burgers():
+    """The space-time Burgers problem with its source, 8x8 P1 cells."""
+    import synth
+    return synth.spacetime_burgers()
+
+
+@pytest.fixture(scope="session")
+def st_burgers_p2():
+    """The space-time Burgers problem with its source, 4x4 P2 cells."""
+    import synth
+    return synth.spacetime_burgers(nx=4, ny=4, p=2, n=6, n_s=12)
+
+
+@pytest.fixture(scope="session")
 def euler_small():
     """8x4-cell P2 Euler mesh (64 elements), n = 20, m = 10, 12 EQ elements."""
     import synth

@@ -14,7 +14,7 @@ def _rom(wl, el=None, rho=None):
     return eq.ROM(pb, wl.Phi, wl.Psi, wl.eq_elem if el is None else el, wl.eq_rho if rho is None else rho)
 
 
-@pytest.mark.parametrize("which", ["tiny", "euler_small"])
+@pytest.mark.parametrize("which", ["tiny", "euler_small", "st_burgers"])
 def test_elementwise_equals_global_masked(which, request):
     wl = request.getfixturevalue(which)
     rom = _rom(wl)

@@ -3,7 +3,7 @@
 Each case patches one plausible error into the oracle for the duration of
 the test and checks that an independent pin detects it: a transposed mapping
 Jacobian, a wrong neighbour orientation in the gather, a flipped upwinding
-sign, and a wrong distortion exponent."""
+sign, a wrong distortion exponent and a misplaced source point."""
 import numpy as np
 
 from conftest import rel
@@ -68,3 +68,21 @@ def test_wrong_distortion_exponent_is_caught(euler_small, monkeypatch):
     N = rs.hdm_assemble(pb, wl.mus[0], wl.Phi @ wl.w_eval[0], xs, jac=False)["N"]
     assert np.abs(N).max() > 1e-3
     assert good is not bad
+
+
+def test_source_at_reference_position_is_caught(st_burgers, monkeypatch):
+    # a wrong source (here exp(-b x)) breaks the identity with plain DG on
+    # the physical mesh, which evaluates s on its own
+    wl = st_burgers
+    good = ph.burgers_source
+    U = wl.Phi @ wl.w_eval[0]
+    x = wl.X + wl.Psi @ wl.tau_eval[0]
+    pb = rs.Problem(wl)
+    R_good = rs.hdm_assemble(pb, wl.mus[0], U, x, jac=False)["R"]
+    assert rel(R_good, physdg.physical_residual(wl, wl.mus[0], U, x)) < 1e-13
+
+    def bad(xphys, mu, amp):   # the exponent's sign flipped
+        return good(xphys, np.array([mu[0], -mu[1]]), amp)
+    monkeypatch.setattr(ph, "burgers_source", bad)
+    R = rs.hdm_assemble(rs.Problem(wl), wl.mus[0], U, x, jac=False)["R"]
+    assert rel(R, physdg.physical_residual(wl, wl.mus[0], U, x)) > 1e-6

@@ -66,7 +66,7 @@ def test_unmapped_reduction(euler_small):
     assert rel(out["R"], ref) < 1e-13
 
 
-@pytest.mark.parametrize("which", ["tiny", "euler_small"])
+@pytest.mark.parametrize("which", ["tiny", "euler_small", "st_burgers", "st_burgers_p2"])
 def test_transformed_equals_physical_dg(which, request):
     wl = request.getfixturevalue(which)
     pb = rs.Problem(wl)
@@ -187,7 +187,7 @@ def _fd_blocks(pb, el, Ue, Une, xe, mu):
     return r, res
 
 
-@pytest.mark.parametrize("which", ["tiny", "euler_small"])
+@pytest.mark.parametrize("which", ["tiny", "euler_small", "st_burgers", "st_burgers_p2"])
 def test_jacobians_match_central_fd(which, request):
     wl = request.getfixturevalue(which)
     pb = rs.Problem(wl)
@@ -205,7 +205,88 @@ def test_jacobians_match_central_fd(which, request):
             mask = np.ones_like(a, dtype=bool)
             for e in np.nonzero((wl.mesh.elem_nbr == -3).any(axis=1))[0]:
                 f = int(np.nonzero(wl.mesh.elem_nbr[e] == -3)[0][0])
-                for node in re.edge_nodes(1, f):
+                for node in re.edge_nodes(wl.p, f):
                     mask[e, :, 2 * node + 1] = False
             a, b = a[mask], b[mask]
         assert rel(a, b) < 1e-6, k
+
+
+def _physical_area(wl, x):
+    """Area of each physical element from its boundary, 1/2 sum over edges of
+    int (x dy - y dx), with the edge x(s) = sum_k L_k(s) x_k of degree p
+    (vertices v_f, v_f+1 and, for p = 2, the mid-edge node f) integrated by
+    3-point Gauss-Legendre (exact: the integrand has degree 2p - 1)."""
+    xe = x.reshape(-1, 2)[wl.mesh.elem_gnodes]
+    t, w = np.polynomial.legendre.leggauss(3)
+    s, w = 0.5 * (t + 1.0), 0.5 * w
+    area = np.zeros(wl.mesh.n_elem)
+    for f in range(3):
+        a, b = xe[:, f], xe[:, (f + 1) % 3]
+        if wl.p == 1:
+            pos = a[:, None] * (1 - s)[None, :, None] + b[:, None] * s[None, :, None]
+            der = (b - a)[:, None, :] * np.ones_like(s)[None, :, None]
+        else:
+            c = xe[:, 3 + f]
+            L = [(1 - s) * (1 - 2 * s), s * (2 * s - 1), 4 * s * (1 - s)]
+            dL = [4 * s - 3, 4 * s - 1, 4 - 8 * s]
+            pos = sum(v[:, None] * l[None, :, None] for v, l in zip((a, b, c), L))
+            der = sum(v[:, None] * l[None, :, None] for v, l in zip((a, b, c), dL))
+        area += 0.5 * ((pos[..., 0] * der[..., 1] - pos[..., 1] * der[..., 0]) * w[None, :]).sum(axis=1)
+    return area
+
+
+@pytest.mark.parametrize("which", ["st_burgers", "st_burgers_p2"])
+def test_constant_source_integrates_physical_area(which, request):
+    # b = 0: s = s_0 everywhere, and the nodal basis sums to one, so the source
+    # part of sum_i R_e[i] is -s_0 |Omega_e| on the mapped (curved) element;
+    # the volume rules integrate det J exactly (degree 2(p - 1) <= 2p)
+    import dataclasses
+    wl = request.getfixturevalue(which)
+    off = dataclasses.replace(wl, src_amp=0.0)
+    for k in (0, 3):
+        mu = np.array([wl.mus[k][0], 0.0])
+        U = wl.Phi @ wl.w_eval[k]
+        x = wl.X + wl.Psi @ wl.tau_eval[k]
+        Rs = rs.hdm_assemble(rs.Problem(wl), mu, U, x, jac=False)["R"]
+        R0 = rs.hdm_assemble(rs.Problem(off), mu, U, x, jac=False)["R"]
+        per_elem = (Rs - R0).reshape(wl.mesh.n_elem, -1).sum(axis=1)
+        assert rel(per_elem, -wl.src_amp * _physical_area(wl, x)) < 1e-13
+        assert abs(_physical_area(wl, x).sum() - 5000.0) < 1e-9   # tangential modes keep the domain
+
+
+def test_source_grows_with_physical_position(st_burgers):
+    # s(x) = s_0 exp(b x) at the mapped point: shifting every node right by
+    # d multiplies each element's source part by exp(b d) (a rigid translation
+    # leaves det J and the basis unchanged)
+    import dataclasses
+    wl = st_burgers
+    off = dataclasses.replace(wl, src_amp=0.0)
+    mu = wl.mus[2]
+    U = wl.Phi @ wl.w_eval[2]
+    x = wl.X.copy()
+    xs = x.reshape(-1, 2).copy()
+    xs[:, 0] += 3.0
+    xs = xs.reshape(-1)
+    parts = []
+    for xx in (x, xs):
+        Rs = rs.hdm_assemble(rs.Problem(wl), mu, U, xx, jac=False)["R"]
+        R0 = rs.hdm_assemble(rs.Problem(off), mu, U, xx, jac=False)["R"]
+        parts.append(Rs - R0)
+    assert rel(parts[1], parts[0] * np.exp(mu[1] * 3.0)) < 1e-13
+
+
+def test_spacetime_boundary_data(st_burgers):
+    # u = 1 everywhere, no source: with a = mu[0] = 1 every boundary value is
+    # 1 and the discrete residual vanishes (free stream); with a = 4 only the
+    # elements with a face on the left edge (tag 1, u = a) feel it, since the
+    # bottom edge (tag 3) keeps u = 1
+    import dataclasses
+    wl = dataclasses.replace(st_burgers, src_amp=0.0)
+    pb = rs.Problem(wl)
+    U = np.ones(wl.N_u)
+    R1 = rs.hdm_assemble(pb, np.array([1.0, 0.05]), U, wl.X.copy(), jac=False)["R"]
+    assert np.abs(R1).max() < 1e-12
+    R4 = rs.hdm_assemble(pb, np.array([4.0, 0.05]), U, wl.X.copy(), jac=False)["R"].reshape(wl.mesh.n_elem, -1)
+    left = (wl.mesh.elem_nbr == -1).any(axis=1)
+    assert np.abs(R4[~left]).max() < 1e-12
+    assert (np.abs(R4[left]).max(axis=1) > 1e-3).all()
