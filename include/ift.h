@@ -91,9 +91,15 @@ typedef struct ift_rom ift_rom;
  * creation.  elem_nbr[e*3+f] is the element across face f or -tag with tag
  * 1 (left), 2 (right), 3 (bottom), 4 (top); interior neighbours must be
  * mutual.  Boundary states (Section 4 reading): Burgers tags 1,3 inflow
- * u+ = 1 + bc_mu_scale*mu[0], tags 2,4 outflow u+ = u-; Euler tag 1
- * supersonic inflow u+ = U_inf(mu), tag 2 supersonic outflow, tags 3,4 slip
- * walls; all_farfield != 0 makes every Euler tag an inflow. */
+ * u+ = 1 + bc_mu_scale*mu[0], or with bc_spacetime = 1 the data of the
+ * space-time problem eq. (burgers), u+ = mu[0] on tag 1 (x = 0) and u+ = 1
+ * on tag 3 (t = 0); tags 2,4 outflow u+ = u-; Euler tag 1 supersonic inflow
+ * u+ = U_inf(mu), tag 2 supersonic outflow, tags 3,4 slip walls;
+ * all_farfield != 0 makes every Euler tag an inflow.
+ * src_amp != 0 (Burgers only) adds the source of eq. (burgers),
+ * s(x) = src_amp exp(mu[1] x) at the mapped physical position x (on the
+ * reference domain S = g s); every call then reads mu[0] and mu[1].  Euler
+ * problems must leave src_amp = 0 and bc_spacetime = 0 (else IFT_EINVAL). */
 typedef struct {
   ift_pde pde;
   int p;                   /* DG degree = mapping degree, 1 or 2          */
@@ -107,6 +113,8 @@ typedef struct {
   double eps_g;            /* eps of eq. (dist_elem1); also validity bound */
   double bc_mu_scale;      /* Burgers inflow scale                         */
   int all_farfield;
+  double src_amp;          /* Burgers source amplitude (0.02 in eq. (burgers); 0: none) */
+  int bc_spacetime;        /* Burgers: 1 = space-time boundary data        */
 } ift_problem_desc;
 
 ift_status ift_problem_create(const ift_problem_desc* desc, ift_problem** out);

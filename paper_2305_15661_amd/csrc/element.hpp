@@ -58,12 +58,31 @@ constexpr int NTHR = 256;
 
 enum { BAD_GEOM = 1, BAD_STATE = 2 };
 
+// Source of eq. (burgers) at the volume points, present for Burgers only
+// (an empty base otherwise): with s_q = s(x_q) at the mapped point x_q,
+//   src[q][0]      = det J s_q                 (the source integrand, S = g s
+//                                               per unit reference measure),
+//   src[q][1 + ab] = s_q d det J / dJ_ab       (ab = 2a + b, J_ab = dx_a/dxi_b),
+//   src[q][5]      = b det J s_q               (through the position, ds/dx = b s).
+template <class D, class R, bool = (D::PDE == PDE_BURGERS)>
+struct PtsSrc {
+  R src[D::NQV][6];
+};
+template <class D, class R>
+struct PtsSrc<D, R, false> {};
+
+template <class R>
+IFT_DEV R exp_r(R v) {
+  if constexpr (std::is_same<R, float>::value) return expf(v);
+  else return exp(v);
+}
+
 // Point data of one element: fluxes and exact point Jacobians at the
 // volume and face quadrature points, the distortion and its gradient, and
 // the validity flags.  This is what the point-physics kernel hands to the
 // assembly kernel (a plain copy through global memory).
 template <class D, class R>
-struct Pts {
+struct Pts : PtsSrc<D, R> {
   R fv[D::NQV][D::NC][2];          // f(u_q)
   R Af[D::NQV][D::NC][2][D::NC];   // df/du at volume points: [q][c][dim][c']
   R gp[D::NQV][D::NN][2];          // cof(J) grad_xi phi_i
@@ -234,6 +253,20 @@ IFT_DEV void vol_point(const RefTab& t, S& s, int q, int seed, const PhysConst& 
       s.p.gp[q][i][0] = J11 * a - J10 * b;
       s.p.gp[q][i][1] = J00 * b - J01 * a;
     }
+    if constexpr (D::PDE == PDE_BURGERS) {
+      // source at the mapped position x_q = sum_j x_j phi_j(xi_q)
+      R xq = R(0);
+#pragma unroll
+      for (int j = 0; j < D::NN; ++j) xq += R(t.phiv[q][j]) * s.x[2 * j];
+      const R sq = pc.src_amp != 0.0 ? R(pc.src_amp) * exp_r<R>(R(pc.src_b) * xq) : R(0);
+      const R dJ = J00 * J11 - J01 * J10;
+      s.p.src[q][0] = dJ * sq;
+      s.p.src[q][1] = sq * J11;
+      s.p.src[q][2] = -(sq * J10);
+      s.p.src[q][3] = -(sq * J01);
+      s.p.src[q][4] = sq * J00;
+      s.p.src[q][5] = R(pc.src_b) * s.p.src[q][0];
+    }
   }
   if constexpr (!std::is_same<T, R>::value) {
     if (seed >= 0) {
@@ -384,6 +417,26 @@ IFT_DEV R residual_entry_p(const P& p, const RefTab& t, int r) {
 #pragma unroll
     for (int q = 0; q < D::NQF; ++q) v += R(t.wf[q] * t.L[q][k]) * p.H[f][q][c];
   }
+  if constexpr (D::PDE == PDE_BURGERS) {
+#pragma unroll
+    for (int q = 0; q < D::NQV; ++q) v -= R(t.wv[q] * t.phiv[q][i]) * p.src[q][0];
+  }
+  return v;
+}
+
+// Source part of dR/dx_e[i][2 k + a] (Burgers): through det J and through
+// the position, -sum_q w_q phi_i (s dJ/dJ_a. . grad_xi phi_k + [a = 0] b det J s phi_k).
+template <class D, class R, class P>
+IFT_DEV R source_dx(const P& p, const RefTab& t, int i, int k, int a) {
+  R v = R(0);
+  if constexpr (D::PDE == PDE_BURGERS) {
+#pragma unroll
+    for (int q = 0; q < D::NQV; ++q) {
+      R d = p.src[q][1 + 2 * a] * R(t.dphiv[q][k][0]) + p.src[q][2 + 2 * a] * R(t.dphiv[q][k][1]);
+      if (a == 0) d += p.src[q][5] * R(t.phiv[q][k]);
+      v -= R(t.wv[q] * t.phiv[q][i]) * d;
+    }
+  }
   return v;
 }
 
@@ -438,6 +491,7 @@ IFT_DEV R jacobian_entry(const ElemLDS<D, R>& s, int r, int col) {
       for (int q = 0; q < D::NQF; ++q)
         v += R(t.wf[q] * t.L[q][ki] * t.dL[q][kk]) * (a == 0 ? -s.p.dHn[f][q][c][1] : s.p.dHn[f][q][c][0]);
     }
+    v += source_dx<D, R>(s.p, t, i, k, a);
   }
   return v;
 }
@@ -513,8 +567,8 @@ IFT_DEV void jac_x2(const RefTab& t, const Pts<D, R>& p, int r, int kn, R* out) 
       v1 += w * p.dHn[f][q][c][0];
     }
   }
-  out[0] = v0;
-  out[1] = v1;
+  out[0] = v0 + source_dx<D, R>(p, t, i, kn, 0);
+  out[1] = v1 + source_dx<D, R>(p, t, i, kn, 1);
 }
 
 template <class D, class R, bool JAC>

@@ -34,6 +34,8 @@ struct ift_problem {
   long long N_u = 0, N_x = 0;
   double gamma = 1.4, kappa = 0.0, eps_g = 1e-8, bc_mu_scale = 0.5;
   int all_farfield = 0;
+  double src_amp = 0.0;   // Burgers source amplitude (0: none)
+  int bc_spacetime = 0;
   std::vector<int> h_gn, h_face;
   std::vector<long long> h_Pn;
   std::vector<double> h_X;
@@ -319,7 +321,13 @@ static PhysConst phys_const(const ift_problem* pr, const double* mu) {
   pc.gamma = pr->gamma;
   pc.all_farfield = pr->all_farfield;
   if (pr->pde == IFT_BURGERS2D) {
-    pc.uinf[0] = 1.0 + pr->bc_mu_scale * mu[0];
+    pc.src_amp = pr->src_amp;
+    pc.bc_st = pr->bc_spacetime;
+    if (mu) {
+      pc.uinf[0] = pr->bc_spacetime ? mu[0] : 1.0 + pr->bc_mu_scale * mu[0];
+      pc.uinf[1] = pr->bc_spacetime ? 1.0 : pc.uinf[0];
+      pc.src_b = pr->src_amp != 0.0 ? mu[1] : 0.0;
+    }
   } else {
     const double M = mu[0];
     const double a = mu[1] * (M_PI / 180.0);
@@ -334,7 +342,7 @@ static PhysConst phys_const(const ift_problem* pr, const double* mu) {
 
 static bool finite_mu(const ift_problem* pr, const double* mu) {
   if (!mu) return false;
-  const int nmu = pr->pde == IFT_BURGERS2D ? 1 : 2;
+  const int nmu = pr->pde == IFT_BURGERS2D && pr->src_amp == 0.0 ? 1 : 2;
   for (int i = 0; i < nmu; ++i)
     if (!std::isfinite(mu[i])) return false;
   if (pr->pde == IFT_EULER2D && !(mu[0] > 0.0)) return false;
@@ -377,6 +385,8 @@ extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem*
   if (d->n_elem <= 0 || d->n_gnode <= 0 || !d->X || !d->elem_gnodes || !d->elem_nbr) return IFT_EINVAL;
   if (!(d->eps_g > 0.0) || !(d->kappa >= 0.0) || !std::isfinite(d->kappa)) return IFT_EINVAL;
   if (d->pde == IFT_EULER2D && !(d->gamma > 1.0)) return IFT_EINVAL;
+  if (!std::isfinite(d->src_amp) || (d->bc_spacetime != 0 && d->bc_spacetime != 1)) return IFT_EINVAL;
+  if (d->pde == IFT_EULER2D && (d->src_amp != 0.0 || d->bc_spacetime != 0)) return IFT_EINVAL;
   ift_status st;
   ift_problem* pr = new ift_problem();
   pr->pde = d->pde;
@@ -395,6 +405,8 @@ extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem*
   pr->eps_g = d->eps_g;
   pr->bc_mu_scale = d->bc_mu_scale;
   pr->all_farfield = d->all_farfield;
+  pr->src_amp = d->src_amp;
+  pr->bc_spacetime = d->bc_spacetime;
   const int Ne = d->n_elem, nn = pr->nn;
   pr->h_gn.assign(d->elem_gnodes, d->elem_gnodes + (size_t)Ne * nn);
   pr->h_face.assign(d->elem_nbr, d->elem_nbr + (size_t)Ne * 3);

@@ -67,7 +67,9 @@ struct EqArgs {
 IFT_DEV PhysConst phys_from_mu(const PhysConst& base, int pde, double bc_scale, const double* mu) {
   PhysConst pc = base;
   if (pde == PDE_BURGERS) {
-    pc.uinf[0] = 1.0 + bc_scale * mu[0];
+    pc.uinf[0] = base.bc_st ? mu[0] : 1.0 + bc_scale * mu[0];
+    pc.uinf[1] = base.bc_st ? 1.0 : pc.uinf[0];
+    pc.src_b = base.src_amp != 0.0 ? mu[1] : 0.0;
   } else {
     const double M = mu[0], a = mu[1] * (M_PI / 180.0), c = sqrt(base.gamma);
     pc.uinf[0] = 1.0;
@@ -287,7 +289,7 @@ constexpr int RV_THR = 256;
 constexpr int RV_SLOTS = RV_THR / RV_LANES;
 
 template <class D, class R>
-struct PtsVal {
+struct PtsVal : PtsSrc<D, R> {
   R fv[D::NQV][D::NC][2];
   R gp[D::NQV][D::NN][2];
   R H[3][D::NQF][D::NC];
@@ -569,7 +571,11 @@ struct EqOp {
   static constexpr int KW = KV + 2 * KF;
   static constexpr int KWP = (KW + 3) & ~3;          // padded to the MFMA k-step
   static constexpr int KXV = 4 * D::NQV;             // volume block of Ax
-  static constexpr int KX = KXV + 3 * D::NQF * 2;
+  static constexpr int KXF = 3 * D::NQF * 2;         // face block of Ax
+  // Burgers: one more row per volume point, the derivative of the source
+  // through the mapped position (x_q = sum_j x_j phi_j(xi_q))
+  static constexpr int KXQ = D::PDE == PDE_BURGERS ? D::NQV : 0;
+  static constexpr int KX = KXV + KXF + KXQ;
   static constexpr int KXP = (KX + 3) & ~3;
 };
 
@@ -611,7 +617,10 @@ IFT_DEV double ax_vol(const RefTab& t, const Pts<D, R>& p, int i, int c, int q, 
   const double px = t.dphiv[q][i][0], py = t.dphiv[q][i][1];
   const double f0 = double(p.fv[q][c][0]), f1 = double(p.fv[q][c][1]);
   const double sgn = (ab == 0 || ab == 3) ? -1.0 : 1.0;
-  return (sgn * t.wv[q]) * pick(f1, f0, ab < 2) * pick(px, py, (ab & 1) != 0);
+  double v = (sgn * t.wv[q]) * pick(f1, f0, ab < 2) * pick(px, py, (ab & 1) != 0);
+  if constexpr (D::PDE == PDE_BURGERS)   // source term -w_q phi_i s d det J / dJ_ab
+    v -= (t.wv[q] * t.phiv[q][i]) * double(p.src[q][1 + ab]);
+  return v;
 }
 
 template <class D, class R>
@@ -619,6 +628,23 @@ IFT_DEV double ax_face(const RefTab& t, const Pts<D, R>& p, int i, int c, int f,
   // d/dt_d of n~ = (t_y, -t_x)
   const double h0 = double(p.dHn[f][q][c][0]), h1 = double(p.dHn[f][q][c][1]);
   return t.wl[i][f][q] * pick(-h1, h0, d == 0);
+}
+
+// Column cf of the rows after the volume block of Ax: the face rows
+// (f, q, d) and, for Burgers, the source-position rows q.
+template <class D, class R>
+IFT_DEV double ax_tail(const RefTab& t, const Pts<D, R>& p, int i, int c, int cf) {
+  using O = EqOp<D>;
+  const int cff = cf < O::KXF ? cf : O::KXF - 1;
+  const double vf = ax_face<D, R>(t, p, i, c, cff / (2 * D::NQF), (cff >> 1) % D::NQF, cff & 1);
+  if constexpr (O::KXQ > 0) {
+    // -w_q phi_i b det J s_q against the row d x_q / d tau
+    const int q = cf >= O::KXF ? cf - O::KXF : 0;
+    const double vq = -(t.wv[q] * t.phiv[q][i]) * double(p.src[q][5]);
+    return pick(vf, vq, cf < O::KXF);
+  } else {
+    return vf;
+  }
 }
 
 template <class D, class R>
@@ -648,7 +674,7 @@ IFT_DEV double ax_entry(const RefTab& t, const Pts<D, R>& p, int r, int col) {
   const double vv = ax_vol<D, R>(t, p, i, c, cv >> 2, cv & 3);
   int cf = col - O::KXV;
   cf = cf < 0 ? 0 : (cf >= O::KX - O::KXV ? O::KX - O::KXV - 1 : cf);
-  const double vf = ax_face<D, R>(t, p, i, c, cf / (2 * D::NQF), (cf >> 1) % D::NQF, cf & 1);
+  const double vf = ax_tail<D, R>(t, p, i, c, cf);
   const double sv = col < O::KXV ? 1.0 : 0.0;
   return (vv * sv + vf * (1.0 - sv)) * ((r < D::NUE && col < O::KX) ? 1.0 : 0.0);
 }
@@ -692,10 +718,14 @@ __global__ __launch_bounds__(256) void k_point_bases(const double* Phi_s, const 
       if (row < O::KXV) {
         const int q = row >> 2, ab = row & 3, ca = ab >> 1, db = ab & 1;
         for (int kn = 0; kn < D::NN; ++kn) a += Ps[(2 * kn + ca) * m + j] * t.dphiv[q][kn][db];
-      } else if (row < O::KX) {
+      } else if (row < O::KXV + O::KXF) {
         const int cf = row - O::KXV;
         const int f = cf / (2 * D::NQF), q = (cf >> 1) % D::NQF, d = cf & 1;
         for (int kk = 0; kk < D::NE; ++kk) a += t.dL[q][kk] * Ps[(2 * t.en[f][kk] + d) * m + j];
+      } else if (row < O::KX) {
+        // first coordinate of the mapped volume point q
+        const int q = row - O::KXV - O::KXF;
+        for (int kn = 0; kn < D::NN; ++kn) a += t.phiv[q][kn] * Ps[(2 * kn) * m + j];
       }
     }
     Bx[((long long)k * O::KXP + row) * lx + j] = a;
@@ -1063,8 +1093,7 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
           double av[MT];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
-            av[mt] = ax_face<D, R>(tab, p, ri[mt], rc[mt], cf / (2 * D::NQF), (cf >> 1) % D::NQF, cf & 1) *
-                     (rm[mt] * cm);
+            av[mt] = ax_tail<D, R>(tab, p, ri[mt], rc[mt], cf) * (rm[mt] * cm);
           mfmas(av, xon);
           bload(KWS + D::NQV + ks + 1);
         }
@@ -1111,7 +1140,7 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
           double av[MT];
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt)
-            av[mt] = ax_face<D, R>(tab, p, ri[mt], rc[mt], cf / (2 * D::NQF), (cf >> 1) % D::NQF, cf & 1) * (rm[mt] * cm);
+            av[mt] = ax_tail<D, R>(tab, p, ri[mt], rc[mt], cf) * (rm[mt] * cm);
           xstep(D::NQV + ks, av);
         }
       }

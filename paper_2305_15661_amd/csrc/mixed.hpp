@@ -28,7 +28,7 @@ struct EqOp16 {
   static constexpr int KF16 = (KF + 15) / 16 * 16;
   static constexpr int KW16 = KV16 + 2 * KF16;
   static constexpr int KXV = 4 * D::NQV;
-  static constexpr int KXF = 3 * D::NQF * 2;
+  static constexpr int KXF = EqOp<D>::KXF + EqOp<D>::KXQ;   // face rows, then Burgers source-position rows
   static constexpr int KXV16 = (KXV + 15) / 16 * 16;
   static constexpr int KXF16 = (KXF + 15) / 16 * 16;
   static constexpr int KX16 = KXV16 + KXF16;
@@ -122,14 +122,26 @@ IFT_DEV void ax16(const RefTab& t, const Pts<D, float>& p, int i, int c, float r
       const float f0 = p.fv[q][c][0], f1 = p.fv[q][c][1];
       const float s1 = ab < 2 ? 1.f : 0.f, s2 = (ab & 1) ? 1.f : 0.f;
       const float sg = (ab == 0 || ab == 3) ? -1.f : 1.f;
-      v = sg * float(t.wv[q]) * (f1 * s1 + f0 * (1.f - s1)) * (px * s2 + py * (1.f - s2)) * ok;
+      v = sg * float(t.wv[q]) * (f1 * s1 + f0 * (1.f - s1)) * (px * s2 + py * (1.f - s2));
+      if constexpr (D::PDE == PDE_BURGERS) v -= float(t.wv[q] * t.phiv[q][i]) * p.src[q][1 + ab];
+      v *= ok;
     } else {
       const float ok = col < Q::KXF ? 1.f : 0.f;
-      const int cf = col < Q::KXF ? col : 0;
+      const int cf0 = col < Q::KXF ? col : 0;
+      constexpr int NF = EqOp<D>::KXF;
+      const int cf = cf0 < NF ? cf0 : 0;
       const int f = cf / (2 * D::NQF), q = (cf >> 1) % D::NQF, d = cf & 1;
       const float h0 = p.dHn[f][q][c][0], h1 = p.dHn[f][q][c][1];
       const float sd = d == 0 ? 1.f : 0.f;
-      v = float(t.wl[i][f][q]) * (-h1 * sd + h0 * (1.f - sd)) * ok;
+      v = float(t.wl[i][f][q]) * (-h1 * sd + h0 * (1.f - sd));
+      if constexpr (EqOp<D>::KXQ > 0) {
+        // source-position row qq: -w_q phi_i b det J s_q
+        const int qq = cf0 >= NF ? cf0 - NF : 0;
+        const float vq = -float(t.wv[qq] * t.phiv[qq][i]) * p.src[qq][5];
+        const float sf = cf0 < NF ? 1.f : 0.f;
+        v = v * sf + vq * (1.f - sf);
+      }
+      v *= ok;
     }
     out[u] = v * rm;
   }

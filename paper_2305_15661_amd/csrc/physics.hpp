@@ -22,8 +22,11 @@ template <> struct NComp<PDE_EULER> { static constexpr int value = 4; };
 // Problem constants seen by the device code.
 struct PhysConst {
   double gamma;
-  double uinf[4];   // Euler: free stream U_inf(mu); Burgers: uinf[0] = inflow value
+  double uinf[4];   // Euler: free stream U_inf(mu); Burgers: uinf[0] on tag 1, uinf[1] on tag 3
+  double src_amp;   // Burgers source s(x) = src_amp exp(src_b x) of eq. (burgers); 0: none
+  double src_b;
   int all_farfield;
+  int bc_st;        // Burgers: 1 = space-time data (tag 1: u = mu[0], tag 3: u = 1)
 };
 
 // f(u) as [nc][2].
@@ -134,7 +137,7 @@ IFT_DEV void boundary_state(int tag, const T* um, T ntx, T nty, const PhysConst&
   constexpr int NC = NComp<PDE>::value;
   if constexpr (PDE == PDE_BURGERS) {
     if (tag == 1 || tag == 3)
-      up[0] = mk<T, R>(R(pc.uinf[0]));
+      up[0] = mk<T, R>(R(pc.uinf[tag == 1 ? 0 : 1]));
     else
       up[0] = um[0];
   } else {

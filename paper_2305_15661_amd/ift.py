@@ -35,7 +35,8 @@ class ProblemDesc(ctypes.Structure):
     _fields_ = [("pde", ctypes.c_int), ("p", ctypes.c_int), ("n_elem", ctypes.c_int), ("n_gnode", ctypes.c_int),
                 ("X", ctypes.POINTER(ctypes.c_double)), ("elem_gnodes", ctypes.POINTER(ctypes.c_int)),
                 ("elem_nbr", ctypes.POINTER(ctypes.c_int)), ("gamma", ctypes.c_double), ("kappa", ctypes.c_double),
-                ("eps_g", ctypes.c_double), ("bc_mu_scale", ctypes.c_double), ("all_farfield", ctypes.c_int)]
+                ("eps_g", ctypes.c_double), ("bc_mu_scale", ctypes.c_double), ("all_farfield", ctypes.c_int),
+                ("src_amp", ctypes.c_double), ("bc_spacetime", ctypes.c_int)]
 
 
 class GNParams(ctypes.Structure):
@@ -156,7 +157,7 @@ def _mu(mu):
 
 class Problem:
     def __init__(self, pde: str, p: int, X, elem_gnodes, elem_nbr, gamma=1.4, kappa=0.1, eps_g=1e-8,
-                 bc_mu_scale=0.5, all_farfield=False):
+                 bc_mu_scale=0.5, all_farfield=False, src_amp=0.0, bc_spacetime=False):
         L = lib()
         self._X = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(-1))
         self._gn = np.ascontiguousarray(elem_gnodes, dtype=np.int32)
@@ -164,7 +165,8 @@ class Problem:
         d = ProblemDesc(PDE[pde], int(p), int(self._gn.shape[0]), int(self._X.size // 2),
                         self._X.ctypes.data_as(_D), self._gn.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                         self._nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(gamma), float(kappa),
-                        float(eps_g), float(bc_mu_scale), int(bool(all_farfield)))
+                        float(eps_g), float(bc_mu_scale), int(bool(all_farfield)), float(src_amp),
+                        int(bool(bc_spacetime)))
         h = _P()
         _check(L.ift_problem_create(ctypes.byref(d), ctypes.byref(h)), "ift_problem_create")
         self.handle = h
@@ -179,7 +181,8 @@ class Problem:
     @classmethod
     def from_workload(cls, wl):
         return cls(wl.pde, wl.p, wl.mesh.X, wl.mesh.elem_gnodes, wl.mesh.elem_nbr, gamma=wl.gamma,
-                   kappa=wl.kappa, eps_g=wl.eps_g, bc_mu_scale=wl.bc_mu_scale, all_farfield=wl.all_farfield)
+                   kappa=wl.kappa, eps_g=wl.eps_g, bc_mu_scale=wl.bc_mu_scale, all_farfield=wl.all_farfield,
+                   src_amp=getattr(wl, "src_amp", 0.0), bc_spacetime=getattr(wl, "bc_spacetime", False))
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -33,16 +33,18 @@ def _desc(ift, wl, **over):
     gn = np.ascontiguousarray(wl.mesh.elem_gnodes, dtype=np.int32)
     nb = np.ascontiguousarray(wl.mesh.elem_nbr, dtype=np.int32)
     kw = dict(pde=ift.PDE[wl.pde], p=wl.p, n_elem=gn.shape[0], n_gnode=X.size // 2, gamma=1.4, kappa=0.1,
-              eps_g=1e-8, bc_mu_scale=0.5, all_farfield=0)
+              eps_g=1e-8, bc_mu_scale=0.5, all_farfield=0, src_amp=0.0, bc_spacetime=0)
     kw.update(over)
     d = ift.ProblemDesc(kw["pde"], kw["p"], kw["n_elem"], kw["n_gnode"], X.ctypes.data_as(ift._D),
                         gn.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), nb.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                        kw["gamma"], kw["kappa"], kw["eps_g"], kw["bc_mu_scale"], kw["all_farfield"])
+                        kw["gamma"], kw["kappa"], kw["eps_g"], kw["bc_mu_scale"], kw["all_farfield"],
+                        kw["src_amp"], kw["bc_spacetime"])
     return d, (X, gn, nb)
 
 
 @pytest.mark.parametrize("over", [dict(p=3), dict(pde=7), dict(n_elem=0), dict(eps_g=0.0), dict(kappa=-1.0),
-                                  dict(gamma=1.0, pde=1)])
+                                  dict(gamma=1.0, pde=1), dict(src_amp=float("nan")), dict(bc_spacetime=2),
+                                  dict(pde=1, src_amp=0.02), dict(pde=1, bc_spacetime=1)])
 def test_bad_descriptor_rejected(over):
     ift, L = _lib()
     wl = synth.tiny_burgers()

@@ -346,3 +346,51 @@ def test_plain_start_matches_oracle(setup):
         c["rom"].plain_start(c["mu"], w, tau)
         torch.cuda.synchronize()
         assert rel(w.cpu().numpy(), c["w0"]) < 1e-13 and np.all(tau.cpu().numpy() == 0.0)
+
+
+def test_batched_solve_with_source_matches_oracle():
+    """The space-time Burgers problem with its source (P1, 8x8 cells of
+    (0, 100) x (0, 50), n = m = 4, 40 EQ elements): eight instances at their
+    own mu = (a, b) solved together from the plain start, against the
+    oracle's Levenberg-Marquardt iteration from the same start.  The
+    synthetic bases leave objectives of 1e3..1e5 (no basis state solves the
+    problem), and there a decrease of the objective below its rounding
+    (about 1e-16 J) decides the line search: the gradient norms at which
+    that happens reach a few 1e-4 (the device compares objectives summed in
+    two different orders, the oracle one), so both run to 1e-3.  Both stop
+    near the same minimiser: same step count up to one (the oracle solves
+    each step by lstsq, the device by Cholesky), the objective within 1e-9
+    and the iterate within 1e-4."""
+    import torch
+    from oracle import eq as oeq
+    from oracle import gn as ogn
+    from oracle import residual as ors
+    from paper_2305_15661_amd import ift
+    dev = torch.device("cuda:0")
+    wl = synth.spacetime_burgers()
+    prob = ift.Problem.from_workload(wl)
+    rom = ift.ROM(prob, torch.tensor(wl.Phi, device=dev), torch.tensor(wl.Psi, device=dev), wl.eq_elem, wl.eq_rho)
+    P = 8
+    b = ift.Batch([rom] * P)
+    mu = torch.tensor(wl.mus[:P], dtype=torch.float64, device=dev)
+    z = torch.zeros(b.nz, dtype=torch.float64, device=dev)
+    b.plain_start(mu, z)
+    info = b.info_buffer(dev)
+    _say("batched solve, space-time Burgers with source")
+    b.solve(mu, z, info, lam=LAM, max_it=60, tol=1e-3)
+    torch.cuda.synchronize()
+    out = b.info_array(info)
+    zb = b.unpack(z)
+    for i in range(P):
+        _say(f"  info {i}: " + " ".join(f"{k}={out[k][i]}" for k in out.dtype.names))
+    orom = oeq.ROM(ors.Problem(wl), wl.Phi, wl.Psi, wl.eq_elem, wl.eq_rho)
+    for i in range(P):
+        w0, t0 = oeq.plain_start(wl, wl.mus[i])
+        w, tau, oinfo = ogn.lm_solve(orom, wl.mus[i], w0, t0, LAM, 1e-3, 60)
+        Jo = orom.jacobian(wl.mus[i], w, tau)["J"]
+        _say(f"  instance {i}: batched status {out['status'][i]} steps {out['iterations'][i]} J {out['J_new'][i]:.12e}; "
+             f"oracle {oinfo['status']} steps {oinfo['iterations']} J {Jo:.12e}")
+        assert oinfo["status"] == "converged" and out["converged"][i] == 1
+        assert abs(int(out["iterations"][i]) - oinfo["iterations"]) <= 1
+        assert abs(out["J_new"][i] - Jo) <= 1e-9 * Jo
+        assert rel(zb[i], np.r_[w, tau]) < 1e-4

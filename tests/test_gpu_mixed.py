@@ -54,6 +54,31 @@ def _jac(rom, dev, mu, w, tau):
     return J.item(), g.cpu().numpy(), H.cpu().numpy().reshape(rom.D, rom.D)
 
 
+@pytest.mark.parametrize("p", [1, 2])
+def test_mixed_jacobian_with_source_error_bounds(p):
+    """The space-time Burgers problem with its source (the extra
+    source-position rows of the mapping factor in BF16) within the same
+    bounds of the FP64 oracle."""
+    import torch
+    from oracle import eq as oeq
+    from oracle import residual as ors
+    from paper_2305_15661_amd import ift
+    dev = torch.device("cuda:0")
+    wl = synth.spacetime_burgers(p=p) if p == 1 else synth.spacetime_burgers(nx=6, ny=6, p=2, n=6, n_s=30)
+    prob = ift.Problem.from_workload(wl)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), device=dev)
+    rom = ift.ROM(prob, t(wl.Phi), t(wl.Psi), wl.eq_elem, wl.eq_rho, "mixed")
+    orom = oeq.ROM(ors.Problem(wl), wl.Phi, wl.Psi, wl.eq_elem, wl.eq_rho)
+    for k in (0, 5, 10):
+        mu, w, tau = wl.mus[k], wl.w_eval[k], wl.tau_eval[k]
+        _say(f"mixed jacobian with source p{p} point {k}")
+        oj = orom.jacobian(mu, w, tau)
+        Jm, gm, Hm = _jac(rom, dev, mu, w, tau)
+        _say(f"  rel J {abs(Jm - oj['J']) / oj['J']:.2e} g {rel(gm, oj['g']):.2e} H {rel(Hm, oj['H']):.2e}")
+        assert abs(Jm - oj["J"]) <= 1e-5 * oj["J"]
+        assert rel(gm, oj["g"]) < 2e-2 and rel(Hm, oj["H"]) < 2e-2
+
+
 def test_mixed_jacobian_error_bounds(euler_mixed):
     from oracle import eq as oeq
     from oracle import residual as ors

@@ -63,6 +63,18 @@ def tiny_case(dev):
 
 
 @pytest.fixture(scope="module")
+def st_case(dev):
+    # the space-time Burgers problem with its source, 8x8 P1 cells
+    return Case(synth.spacetime_burgers(), dev)
+
+
+@pytest.fixture(scope="module")
+def st_p2_case(dev):
+    # the same on 6x6 P2 cells (curved elements), 30 EQ elements
+    return Case(synth.spacetime_burgers(nx=6, ny=6, p=2, n=6, n_s=30), dev)
+
+
+@pytest.fixture(scope="module")
 def euler_case(dev):
     # 16x8 cells (256 P2 elements), 64 EQ elements: several tiles and a ragged tail
     return Case(synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=64), dev)
@@ -81,7 +93,7 @@ def _hdm_gpu(case, mu, U, x, jac=True):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
 def test_hdm_assemble_parity(which, request):
     from oracle import residual as ors
     case = request.getfixturevalue(which)
@@ -115,7 +127,7 @@ def test_hdm_residual_only_matches_jacobian_path(euler_case):
     assert np.abs(a["N"] - b["N"]).max() < 1e-14 * eta_scale
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
 def test_gathers_bit_exact(which, request):
     case = request.getfixturevalue(which)
     _say(f"gathers {case.wl.name}")
@@ -141,7 +153,7 @@ def _eq_gpu(case, mu, w, tau):
                 Ft=f(Ft), PhiT_r=f(ptr), n_bad=int(f(nb)[0]))
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
 def test_eq_assembly_parity(which, request):
     case = request.getfixturevalue(which)
     wl = case.wl
@@ -190,7 +202,7 @@ def test_single_element_and_boundary_only_eq_sets(dev):
         assert rel(g["g"], oj["g"]) < 1e-12 and rel(g["H"], oj["H"]) < 1e-12
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
 def test_batched_points_match_single_calls_and_oracle(which, request):
     """All 16 seeded evaluation points in one batched launch (device mu)."""
     import torch
@@ -220,13 +232,14 @@ def test_batched_points_match_single_calls_and_oracle(which, request):
     assert all(np.isinf(J[k]) == (nb_o[k] > 0) for k in range(P))
 
 
-def test_gauss_newton_steps_parity(tiny_case):
+@pytest.mark.parametrize("which", ["tiny_case", "st_case"])
+def test_gauss_newton_steps_parity(which, request):
     """Twenty steps from the plain start; each GPU step is compared with the
     oracle's step from the same z_n (normal equations, Armijo backtracking)."""
     import torch
     from oracle import eq as oeq
     from oracle import gn as ogn
-    case = tiny_case
+    case = request.getfixturevalue(which)
     wl, d = case.wl, case.dev
     mu = wl.mus[0]
     w0, t0 = oeq.plain_start(wl, mu)
@@ -323,7 +336,7 @@ def test_gauss_newton_w_only_step_parity(tiny_case, qr):
         raise AssertionError("the w-only iteration did not converge in 12 steps")
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
 def test_hdm_residual_norms_match_oracle(which, request):
     """The greedy indicator, eq. (greedy0): |R(Phi w; X + Psi tau, mu)|_2 over
     all elements for several reduced points in one call, against the norm of
@@ -360,7 +373,7 @@ def test_hdm_residual_norms_match_oracle(which, request):
     assert ift.greedy_select(g[:-1]) == int(np.argmax(ref[:-1]))
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
 def test_element_contributions_match_oracle(which, request):
     """The data of the EQ-weight training program: unweighted elemental
     reduced residuals against the oracle's (1e-12), and sum_k rho_k C[k]
