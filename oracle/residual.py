@@ -13,7 +13,10 @@ Follows Section 2 of the paper:
 
 The DG weak form (a reading; the paper only says "standard nodal DG"):
     R_e[i] = sum_faces int phi_i H(U-, U+, n~) dS - int grad_0 phi_i : F dX
-where the surface term is written with Nanson's relation,
+             - int phi_i S dX,
+with the transformed source S = g s of eq. (p2r-flux) (the source of the
+space-time Burgers problem, eq. (burgers), at the mapped point; else 0).
+The surface term is written with Nanson's relation,
 n~ = g G^{-T} N dS_0 per unit edge parameter, evaluated here literally.
 Jacobians come from forward-mode dual numbers (``oracle.dual``).
 

@@ -1,8 +1,10 @@
 // One DG element per 256-thread workgroup (four 64-lane waves).
 //
 // Discretisation (Section 2.3 of the paper, readings where it is silent):
-//   R_e[i,c] = sum_faces int phi_i H_c(u-, u+, n~) ds - int grad_0 phi_i . F_c dX,
-//   F = g f(U) G^{-T} (eq. (p2r-flux)).
+//   R_e[i,c] = sum_faces int phi_i H_c(u-, u+, n~) ds - int grad_0 phi_i . F_c dX
+//              - int phi_i S_c dX,
+//   F = g f(U) G^{-T}, S = g s (eq. (p2r-flux)); s is the source of the
+//   space-time Burgers problem, eq. (burgers), or zero.
 // With J = dx/dxi and J0 = dX/dxi the volume integrand reduces to
 // f(u) . (cof(J) grad_xi phi_i) per unit reference-triangle measure, where
 // cof(J) = det(J) J^{-T} is linear in x_e in 2-D; the face term uses

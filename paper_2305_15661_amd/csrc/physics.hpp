@@ -1,8 +1,9 @@
 // Physical fluxes, numerical fluxes and boundary states, templated on the
 // scalar type (double / float values, or Tan<> for one Jacobian column).
 //
-// Burgers: space-time flux f(u) = (u^2/2, u) (the paper's Burgers problem
-// without source); local Lax-Friedrichs numerical flux.
+// Burgers: space-time flux f(u) = (u^2/2, u) of eq. (burgers) (its source
+// enters at the volume points, element.hpp); local Lax-Friedrichs
+// numerical flux.
 // Euler: flux of the paper's eq. (euler), ideal-gas pressure; Roe's
 // approximate Riemann solver with Harten's entropy fix on all four waves,
 // delta = 0.1 * Roe-averaged sound speed.
