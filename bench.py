@@ -363,6 +363,31 @@ def warm_start_leg(dev, n_train: int = 4096, n_test: int = 1024, train_steps: in
     zp_, ip, tp = solve(bte, mu_te)
     zw_, iw, tw = solve(bte, mu_te, warm_z=zw)
     cp, cw = int(ip["converged"].sum()), int(iw["converged"].sum())
+    # the plain FP64 single-instance GPU path on the first n_loop held-out mu:
+    # rom_gauss_newton_step from the plain start until convergence
+    n_loop = 64
+    t = time.perf_counter()
+    lconv, lits = 0, []
+    for mu in mu_te[:n_loop]:
+        w = torch.zeros(rom64.n, dtype=torch.float64, device=dev)
+        tau = torch.zeros(rom64.m, dtype=torch.float64, device=dev)
+        rom64.plain_start(mu, w, tau)
+        steps = 0
+        while True:
+            last = steps == BATCH_MAX_IT
+            wc, tc = (w.clone(), tau.clone()) if last else (w, tau)
+            st_, inf_ = rom64.gauss_newton_step(mu, wc, tc, lam=BATCH_LAMBDA)
+            if inf_["converged"] or st_ != 0 or last:
+                break
+            steps += 1
+        lconv += int(inf_["converged"])
+        lits.append(steps)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t
+    loop_rate = lconv / t_loop
+    cw_rate = cw / tw
+    log(f"warm start: FP64 single-instance loop over {n_loop} held-out mu: {lconv} converged, "
+        f"{np.mean(lits):.1f} its, {loop_rate:.1f} solves/s; batched mixed + warm is {cw_rate / loop_rate:.1f}x that")
     log(f"warm start: plain {cp} converged, {ip['iterations'].mean():.1f} its, {tp:.3f} s; warm {cw} converged, "
         f"{iw['iterations'].mean():.1f} its, {tw:.3f} s, {int(np.sum(iw['fallback'] == 1))} fallbacks, "
         f"{int(np.sum(iw['fallback'] == 2))} restarts; statuses {dict(zip(*np.unique(iw['status'], return_counts=True)))}")
@@ -377,6 +402,9 @@ def warm_start_leg(dev, n_train: int = 4096, n_test: int = 1024, train_steps: in
                      "solves_per_s": cw / tw, "fallbacks": int(np.sum(iw["fallback"] == 1)),
                      "restarts_after_failed_line_search": int(np.sum(iw["fallback"] == 2))},
             "speedup_warm_vs_plain": (cw / tw) / (cp / tp) if cp and tp > 0 else None,
+            "fp64_single_instance_loop": {"instances": n_loop, "converged": lconv, "seconds": t_loop,
+                                          "solves_per_s": loop_rate, "mean_gn_iterations": float(np.mean(lits))},
+            "speedup_vs_fp64_single_instance_loop": cw_rate / loop_rate if loop_rate > 0 else None,
             "setup_seconds": time.perf_counter() - t0}
 
 
