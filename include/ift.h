@@ -329,6 +329,11 @@ ift_status eq_assemble_jacobian_batched(ift_batch* batch, const double* mu, cons
  * params->lambda: lambda / 10 after a step accepted at alpha = 1 (0 below
  * 1e-12), max(10 lambda, 1e-8) after a step accepted at alpha < 1.
  * params->use_qr and params->w_only must be 0.
+ * The full step z + dz is taken first and tested by the next Jacobian
+ * assembly, whose objective decides the sufficient-decrease test at
+ * alpha = 1 (the objective equals the trial residual's to rounding); a
+ * rejected step restores z and backtracks from alpha = 1/2 with trial
+ * residual evaluations.
  * The rounds (Jacobian assembly, LM step, two line-search trials) run in
  * replays of four captured rounds; after each replay the stream is
  * synchronised to read how many instances are still running.  Returns
