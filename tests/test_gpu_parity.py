@@ -261,7 +261,7 @@ def test_gauss_newton_steps_parity(which, request):
         z = np.r_[wo, to]
 
 
-@pytest.mark.parametrize("which,lam", [("tiny_case", 0.0), ("euler_case", 1e-3)])
+@pytest.mark.parametrize("which,lam", [("tiny_case", 0.0), ("euler_case", 1e-3), ("st_p2_case", 1e-3)])
 def test_gauss_newton_qr_step_parity(which, lam, request):
     """The least-squares form of the step (Householder QR of the stacked rows
     [J~_z | -F~] and, for lambda > 0, the sqrt(lambda) rows of the mapping
