@@ -122,6 +122,14 @@ void ift_problem_destroy(ift_problem* prob);
 /* Sizes of the problem: nue, nun, nxe, N_u, N_x (any may be NULL). */
 ift_status ift_problem_sizes(const ift_problem* prob, int* nue, int* nun, int* nxe,
                              long long* N_u, long long* N_x);
+/* The neighbour DoF map built at creation (the assembly operator of the
+ * neighbour traces U_e' in eq. (hdm_elem)): Pn HOST, caller-allocated
+ * [n_elem][nun]; entry (e, f, k, c) is the index into U of component c of
+ * the neighbour across face f at e's edge node k (edge order of e), or -1
+ * on a boundary face.  With it the element blocks of hdm_assemble assemble
+ * into the global sparse Jacobian dR/dU (the snapshot alignment of
+ * eq. (align0)).  IFT_EINVAL for null arguments. */
+ift_status ift_problem_neighbour_map(const ift_problem* prob, long long* Pn);
 
 /* Full-order element loop over all n_elem elements (eq. (hdm_elem) and
  * eq. (hdm_elem_jac1), distortion eq. (dist_elem0)-(dist_elem1)).

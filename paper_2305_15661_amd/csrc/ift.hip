@@ -500,6 +500,12 @@ extern "C" ift_status ift_problem_sizes(const ift_problem* pr, int* nue, int* nu
   return IFT_OK;
 }
 
+extern "C" ift_status ift_problem_neighbour_map(const ift_problem* pr, long long* Pn) {
+  if (!pr || !Pn) return IFT_EINVAL;
+  std::copy(pr->h_Pn.begin(), pr->h_Pn.end(), Pn);
+  return IFT_OK;
+}
+
 // --------------------------------------------------------------- dispatch
 struct HdmLaunch {
   const HdmArgs& a;

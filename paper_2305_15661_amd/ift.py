@@ -64,6 +64,7 @@ EXPORTS = {
     "ift_problem_sizes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(ctypes.c_longlong)]),
+    "ift_problem_neighbour_map": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_longlong)]),
     "hdm_assemble": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "eq_element_contributions": (ctypes.c_int, [_P, _D, _P, _P, _P, _P]),
     "hdm_residual_norm_batched": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_int, _P, _P, ctypes.c_int, _P,
@@ -189,6 +190,13 @@ class Problem:
         if h and _lib is not None:
             _lib.ift_problem_destroy(h)
             self.handle = None
+
+    def neighbour_map(self) -> np.ndarray:
+        """ift_problem_neighbour_map: [n_elem][nun] indices into U, -1 on boundary faces."""
+        out = np.zeros(self.n_elem * self.nun, dtype=np.int64)
+        _check(lib().ift_problem_neighbour_map(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong))),
+               "ift_problem_neighbour_map")
+        return out.reshape(self.n_elem, self.nun)
 
     def hdm_assemble(self, mu, U, x, R=None, N=None, dRdU=None, dRdUn=None, dRdx=None, dNdx=None, n_bad=None,
                      stream=None):
