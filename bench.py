@@ -542,6 +542,43 @@ def burgers_leg(dev, reps: int = 50):
             "status_counts": {str(int(k)): int(v) for k, v in zip(*np.unique(o["status"], return_counts=True))}}
 
 
+def align_leg(dev, nx: int = 32, ny: int = 16, j: int = 4, steps: int = 3):
+    """Snapshot alignment of the greedy loop, eq. (align0), on an nx x ny P2
+    Euler mesh: Gauss-Newton on (w, x) with the first j state modes and the
+    whole node vector, full-order residual and Jacobian blocks on the device
+    (hdm_assemble), sparse normal equations on the host, device line search;
+    then the Gram-Schmidt append of x* - X to the mapping basis."""
+    import synth
+    from paper_2305_15661_amd import align, ift
+    wl = synth.euler_p2(nx=nx, ny=ny, n=20, m=10, n_s=12, n_eval=2)
+    prob = ift.Problem.from_workload(wl)
+    Phi_j = np.linalg.qr(wl.Phi[:, :j])[0]
+    al = align.Alignment(prob, Phi_j)
+    mu = wl.mus[1]
+    w = Phi_j.T @ (wl.Phi @ wl.w_eval[1])
+    x = wl.X + wl.Psi @ wl.tau_eval[1]
+    al.jacobian(mu, w, x)                       # warm-up
+    t0 = time.perf_counter()
+    for _ in range(3):
+        al.jacobian(mu, w, x)
+    t_jac = (time.perf_counter() - t0) / 3
+    hist = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        w, x, info = al.step(mu, w, x, 1e-2)
+        hist.append(info)
+    t_steps = (time.perf_counter() - t0) / steps
+    Psi1 = align.gram_schmidt_append(np.linalg.qr(wl.Psi)[0], x - wl.X)
+    log(f"alignment: {wl.mesh.n_elem} P2 elements, {x.size} node coordinates + {j} state modes: "
+        f"device blocks + host assembly {t_jac * 1e3:.1f} ms, {t_steps * 1e3:.1f} ms per step; "
+        f"objective {hist[0]['J_old']:.3e} -> {hist[-1]['J_new']:.3e}")
+    return {"workload": f"Euler P2 {nx}x{ny} cells ({wl.mesh.n_elem} elements), {x.size} node coordinates, "
+                        f"{j} state modes, lambda 1e-2",
+            "jacobian_assembly_ms": t_jac * 1e3, "step_ms": t_steps * 1e3, "steps": steps,
+            "objective_first": hist[0]["J_old"], "objective_last": hist[-1]["J_new"],
+            "statuses": [h["status"] for h in hist], "mapping_basis_columns": int(Psi1.shape[1])}
+
+
 def _finite(o):
     """The result with every non-finite float (an invalid candidate's norm)
     replaced by None, so that the line is strict JSON."""
@@ -569,6 +606,7 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="skip the learned warm-start leg")
     ap.add_argument("--no-eqp", action="store_true", help="skip the EQ-weight training leg")
     ap.add_argument("--no-burgers", action="store_true", help="skip the space-time Burgers leg")
+    ap.add_argument("--no-align", action="store_true", help="skip the snapshot-alignment leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (traffic-counter calibration)")
     args = ap.parse_args()
@@ -699,6 +737,8 @@ def main():
         out["eq_training"] = eqp_leg(dev)
     if not args.no_burgers:
         out["spacetime_burgers"] = burgers_leg(dev)
+    if not args.no_align:
+        out["snapshot_alignment"] = align_leg(dev)
     if not args.no_warm:
         out["warm_start"] = warm_start_leg(dev)
 
