@@ -31,7 +31,9 @@
  *     (nun = 3*(p+1)*nc: for face f and edge node k ordered from vertex f to
  *     vertex f+1, the neighbour's DoFs at that node; zero on boundary faces),
  *     element mapping DoFs x_e (nxe = 2*nn).
- *   - mu: host pointer; Burgers: mu[0] (inflow u_b = 1 + bc_mu_scale*mu[0]),
+ *   - mu: host pointer; Burgers: mu[0] (inflow u_b = 1 + bc_mu_scale*mu[0],
+ *     or u_b = mu[0] on the left edge with bc_spacetime) and, when the
+ *     problem has the source of eq. (burgers), mu[1] = its rate b;
  *     Euler: mu[0] = free-stream Mach number, mu[1] = inflow angle (deg).
  *   - unless stated otherwise, every array argument is a DEVICE pointer
  *     owned by the caller; the library never frees caller memory.
