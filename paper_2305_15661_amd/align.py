@@ -90,17 +90,20 @@ class Alignment:
         return F, Jw, Jx, int(o["n_bad"][0])
 
     def direction(self, mu, w, x, lam: float):
-        """The damped least-squares step (dw, dx) and {F, J, g} at (w, x),
-        from the sparse normal equations
+        """The damped least-squares step (dw, dx) and {F, J, g} at (w, x)
+        (a zero step and J = +inf at an invalid point), from the sparse
+        normal equations
             [Jw^T Jw  Jw^T Jx; Jx^T Jw  Jx^T Jx + lambda I] d = -[Jw^T F; Jx^T F]."""
         import scipy.sparse as sp
         import scipy.sparse.linalg as spl
         if not lam > 0.0:
             raise ValueError("lambda must be positive (rigid translations of the nodes are null directions)")
         F, Jw, Jx, n_bad = self.jacobian(mu, w, x)
-        g = np.r_[Jw.T @ F, Jx.T @ F]
-        J = np.inf if n_bad else 0.5 * float(F @ F)
         Nx = Jx.shape[1]
+        if n_bad:   # invalid point: no step
+            return np.zeros(self.j), np.zeros(Nx), {"F": F, "J": np.inf, "g": np.full(self.j + Nx, np.nan)}
+        g = np.r_[Jw.T @ F, Jx.T @ F]
+        J = 0.5 * float(F @ F)
         A = sp.bmat([[sp.csr_matrix(Jw.T @ Jw), sp.csr_matrix(Jx.T @ Jw).T],
                      [sp.csr_matrix(Jx.T @ Jw), (Jx.T @ Jx + lam * sp.identity(Nx)).tocsr()]]).tocsc()
         d = spl.spsolve(A, -g)
@@ -117,6 +120,7 @@ class Alignment:
                 "norm_g": float(np.linalg.norm(d["g"])), "status": "ok"}
         if not np.isfinite(d["J"]):
             info["status"] = "invalid"
+            info["norm_g"] = np.inf
             return w, x, info
         slope = float(d["g"] @ np.r_[dw, dx])
         alpha = 1.0

@@ -74,3 +74,27 @@ def test_alignment_step_matches_oracle(case):
     P1 = align.gram_schmidt_append(Psi_j, x - wl.X)
     P2 = oal.gram_schmidt_append(Psi_j, x - wl.X)
     assert np.abs(P1 - P2).max() < 1e-13 and np.abs(P1.T @ P1 - np.eye(4)).max() < 1e-13
+
+
+def test_alignment_invalid_point_and_arguments():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from oracle import align as oal
+    from oracle import residual as ors
+    from paper_2305_15661_amd import align, ift
+    wl = synth.tiny_burgers()
+    prob = ift.Problem.from_workload(wl)
+    Phi_j = np.linalg.qr(wl.Phi[:, :3])[0]
+    al = align.Alignment(prob, Phi_j)
+    w = Phi_j.T @ (wl.Phi @ wl.w_eval[0])
+    x_bad = wl.X + 80.0 * (wl.Psi @ wl.tau_eval[0])      # inverted elements
+    _say("alignment at an invalid point")
+    assert np.isinf(al.objective(wl.mus[0], w, x_bad))
+    assert np.isinf(oal.objective(ors.Problem(wl), Phi_j, wl.mus[0], w, x_bad))
+    w1, x1, info = al.step(wl.mus[0], w, x_bad, LAM)
+    assert info["status"] == "invalid" and np.array_equal(x1, x_bad)
+    with pytest.raises(ValueError):
+        al.direction(wl.mus[0], w, wl.X.copy(), 0.0)
+    with pytest.raises(ValueError):
+        align.Alignment(prob, Phi_j[:-1])
