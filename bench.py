@@ -770,7 +770,8 @@ def main():
         gbs = HDM_BYTES_PER_ELEM * Ne / t_avg / 1e9
         out["hdm_assemble"] = {"evals_per_s": Ne / t_avg, "launch_avg_us": t_avg * 1e6, "bound": "hbm",
                                "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS,
-                               "points_us": ms2 / c2 * 1e3, "assembly_us": ms / c * 1e3}
+                               "points_us": ms2 / c2 * 1e3 if c2 else None, "assembly_us": ms / c * 1e3,
+                               "kernels": "one pass (point physics and blocks)" if not c2 else "points + assembly"}
         log(f"hdm_assemble: {t_avg * 1e6:.1f} us, {Ne / t_avg:.3e} evals/s, {gbs:.0f} GB/s")
         del dRdU, dRdUn, dRdx
 

@@ -513,7 +513,11 @@ struct HdmLaunch {
   hipStream_t st;
   template <class D>
   void run() {
-    if (jac) {
+    if (jac && D::NC == 4) {
+      // one pass: point physics and the blocks written from the same LDS
+      ProfScope ps(IFT_PROF_HDM, st);
+      hipLaunchKernelGGL((k_hdm_fused<D, double>), dim3(a.n_elem), dim3(NTHR_PTS), 0, st, a);
+    } else if (jac) {
       {
         ProfScope ps(IFT_PROF_POINTS, st);
         hipLaunchKernelGGL((k_points_hdm<D, double>), dim3(a.n_elem), dim3(NTHR_PTS), 0, st, a);

@@ -169,6 +169,68 @@ __global__ __launch_bounds__(NTHR) void k_hdm_val(HdmArgs a) {
 }
 
 // ------------------------------------------------ point physics (tangent)
+// Outputs of one full-order element with four state components, from its
+// point data in LDS: R_e, N_e, the flags, dN_e/dx_e and the blocked entries
+// of the element Jacobian, written straight to the outputs ((row, node)
+// pairs of dR/dU_e and dR/dU_e', four columns each; (row, node) pairs of
+// dR/dx_e, two columns).
+template <class D, class R>
+IFT_DEV void hdm_write_blocks(const ElemLDS<D, R>& s, const HdmArgs& a, int e, int tid, int nthr) {
+  static_assert(D::NC == 4, "four state components");
+  constexpr int NU = D::NUE * D::NN, NUN4 = D::NUE * 3 * D::NE, NX = D::NUE * D::NN;
+  if (a.R && tid < D::NUE) a.R[(long long)e * D::NUE + tid] = double(residual_entry<D, R>(s, tid));
+  for (int task = tid; task < NU + NUN4 + NX; task += nthr) {
+    R v[4];
+    if (task < NU) {
+      if (!a.dRdU) continue;
+      const int r = task / D::NN, j = task % D::NN;
+      jac_u4<D, R>(s.tab, s.p, r, j, v);
+      double* o = a.dRdU + ((long long)e * D::NUE + r) * D::NUE + 4 * j;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) o[cc] = double(v[cc]);
+    } else if (task < NU + NUN4) {
+      if (!a.dRdUn) continue;
+      const int tk = task - NU;
+      const int r = tk / (3 * D::NE), fk = tk % (3 * D::NE);
+      jac_un4<D, R>(s.tab, s.p, r, fk / D::NE, fk % D::NE, v);
+      double* o = a.dRdUn + ((long long)e * D::NUE + r) * D::NUN + 4 * fk;
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) o[cc] = double(v[cc]);
+    } else {
+      if (!a.dRdx) continue;
+      const int tk = task - NU - NUN4;
+      const int r = tk / D::NN, kn = tk % D::NN;
+      jac_x2<D, R>(s.tab, s.p, r, kn, v);
+      double* o = a.dRdx + ((long long)e * D::NUE + r) * D::NXE + 2 * kn;
+      o[0] = double(v[0]);
+      o[1] = double(v[1]);
+    }
+  }
+  if (tid == 0) {
+    if (a.N) a.N[e] = double(s.p.N);
+    a.flags[e] = s.p.bad;
+  }
+  if (a.dNdx && tid < D::NXE) a.dNdx[(long long)e * D::NXE + tid] = double(s.p.dN[tid]);
+}
+
+// Full-order element with all Jacobian blocks in one block (four state
+// components): the point physics of k_points_hdm, then the outputs written
+// from the same LDS, with no point-data round trip through memory.
+template <class D, class R>
+__global__ __launch_bounds__(NTHR_PTS) void k_hdm_fused(HdmArgs a) {
+  __shared__ ElemLDS<D, R> s;
+  const int e = blockIdx.x;
+  const int tid = threadIdx.x;
+  load_tab<D, R>(s, tid, NTHR_PTS);
+  load_hdm<D, R>(s, a, e, tid, NTHR_PTS);
+  __syncthreads();
+  phase_points<D, R, true>(s, tid, a.pc, R(a.kappa), R(a.eps));
+  __syncthreads();
+  phase_distortion<D, R>(s, tid, R(a.kappa));
+  __syncthreads();
+  if constexpr (D::NC == 4) hdm_write_blocks<D, R>(s, a, e, tid, NTHR_PTS);
+}
+
 template <class D, class R>
 __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
   __shared__ ElemLDS<D, R> s;
@@ -218,42 +280,7 @@ __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
   copy_words<D, R>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + e, tid, NTHR);
   __syncthreads();
   if constexpr (D::NC == 4) {
-    // blocked entries straight to the outputs: (row, node) pairs of dR/dU_e
-    // and dR/dU_e' (four columns each), (row, node) pairs of dR/dx_e (two)
-    constexpr int NU = D::NUE * D::NN, NUN4 = D::NUE * 3 * D::NE, NX = D::NUE * D::NN;
-    if (a.R && tid < D::NUE) a.R[(long long)e * D::NUE + tid] = double(residual_entry<D, R>(s, tid));
-    for (int task = tid; task < NU + NUN4 + NX; task += NTHR) {
-      R v[4];
-      if (task < NU) {
-        if (!a.dRdU) continue;
-        const int r = task / D::NN, j = task % D::NN;
-        jac_u4<D, R>(s.tab, s.p, r, j, v);
-        double* o = a.dRdU + ((long long)e * D::NUE + r) * D::NUE + 4 * j;
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) o[cc] = double(v[cc]);
-      } else if (task < NU + NUN4) {
-        if (!a.dRdUn) continue;
-        const int tk = task - NU;
-        const int r = tk / (3 * D::NE), fk = tk % (3 * D::NE);
-        jac_un4<D, R>(s.tab, s.p, r, fk / D::NE, fk % D::NE, v);
-        double* o = a.dRdUn + ((long long)e * D::NUE + r) * D::NUN + 4 * fk;
-#pragma unroll
-        for (int cc = 0; cc < 4; ++cc) o[cc] = double(v[cc]);
-      } else {
-        if (!a.dRdx) continue;
-        const int tk = task - NU - NUN4;
-        const int r = tk / D::NN, kn = tk % D::NN;
-        jac_x2<D, R>(s.tab, s.p, r, kn, v);
-        double* o = a.dRdx + ((long long)e * D::NUE + r) * D::NXE + 2 * kn;
-        o[0] = double(v[0]);
-        o[1] = double(v[1]);
-      }
-    }
-    if (tid == 0) {
-      if (a.N) a.N[e] = double(s.p.N);
-      a.flags[e] = s.p.bad;
-    }
-    if (a.dNdx && tid < D::NXE) a.dNdx[(long long)e * D::NXE + tid] = double(s.p.dN[tid]);
+    hdm_write_blocks<D, R>(s, a, e, tid, NTHR);
     return;
   }
   phase_assemble<D, R, true>(s, tid);
