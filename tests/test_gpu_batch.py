@@ -394,3 +394,61 @@ def test_batched_solve_with_source_matches_oracle():
         assert abs(int(out["iterations"][i]) - oinfo["iterations"]) <= 1
         assert abs(out["J_new"][i] - Jo) <= 1e-9 * Jo
         assert rel(zb[i], np.r_[w, tau]) < 1e-4
+
+
+def test_full_size_batch_samples():
+    """The benchmark's batch (1024 instances on the 16384-element mesh, pool
+    n in {10, 20, 30} x m in {5, 10}, EQ sets of 200..2000 elements plus the
+    inflow elements), autotuned as the benchmark runs it: the batched plain
+    start against the oracle's, and the batched Jacobian at seeded perturbed
+    points against the oracle on sampled instances (the smallest and the
+    largest EQ sets and the largest D)."""
+    import dataclasses
+
+    import torch
+    from oracle import eq as oeq
+    from oracle import residual as ors
+    from paper_2305_15661_amd import ift
+    dev = torch.device("cuda:0")
+    bw = synth.euler_batch(n_inst=1024)
+    prob = ift.Problem.from_workload(bw.base)
+    pool = [(torch.tensor(np.ascontiguousarray(P), device=dev), torch.tensor(np.ascontiguousarray(S), device=dev))
+            for P, S in bw.pool]
+    roms = [ift.ROM(prob, *pool[bw.inst_pool[i]], bw.inst_elem[i], bw.inst_rho[i]) for i in range(1024)]
+    b = ift.Batch(roms)
+    mu = torch.tensor(bw.mus, dtype=torch.float64, device=dev)
+    z0 = torch.zeros(b.nz, dtype=torch.float64, device=dev)
+    b.plain_start(mu, z0)
+    E = b.autotune(mu, z0)
+    _say(f"full-size batch: autotuned E = {E}")
+    # the Jacobian at perturbed points (at the plain start most element
+    # residuals vanish up to rounding, which leaves nothing to compare)
+    zp = b.unpack(z0)
+    rng = np.random.default_rng(1011)
+    zt = []
+    for i in range(1024):
+        n, m = bw.pool_nm[bw.inst_pool[i]]
+        w = zp[i][:n] + 0.02 * np.linalg.norm(zp[i][:n]) / np.sqrt(n) * rng.standard_normal(n)
+        tau = rng.uniform(-1.0, 1.0, m)
+        zt.append(np.r_[w, tau / max(1.0, np.abs(tau).sum())])
+    J = torch.zeros(1024, dtype=torch.float64, device=dev)
+    g = torch.zeros(b.nz, dtype=torch.float64, device=dev)
+    H = torch.zeros(b.nh, dtype=torch.float64, device=dev)
+    b.eq_assemble_jacobian(mu, b.pack(zt, dev), J, g, H)
+    torch.cuda.synchronize()
+    J, g, H = J.cpu().numpy(), g.cpu().numpy(), H.cpu().numpy()
+    sizes = np.array([e.size for e in bw.inst_elem])
+    D = np.array([sum(bw.pool_nm[p]) for p in bw.inst_pool])
+    for i in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.argmax(D * 10000 + sizes))}):
+        P, S = bw.pool[bw.inst_pool[i]]
+        n = P.shape[1]
+        _say(f"  instance {i}: n_s {sizes[i]}, D {D[i]}")
+        wl = synth.with_eq(bw.base, bw.inst_elem[i], bw.inst_rho[i])
+        orom = oeq.ROM(ors.Problem(wl), P, S, bw.inst_elem[i], bw.inst_rho[i])
+        wl_mu = bw.mus[i]
+        wp = oeq.plain_start(dataclasses.replace(wl, Phi=P, Psi=S), wl_mu)
+        assert rel(zp[i], np.r_[wp[0], wp[1]]) < 1e-13
+        oj = orom.jacobian(wl_mu, zt[i][:n], zt[i][n:])
+        assert abs(J[i] - oj["J"]) <= 1e-12 * oj["J"]
+        assert rel(g[b.zoff[i]:b.zoff[i + 1]], oj["g"]) < 1e-12
+        assert rel(H[b.hoff[i]:b.hoff[i + 1]].reshape(D[i], D[i]), oj["H"]) < 1e-12
