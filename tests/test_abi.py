@@ -79,6 +79,7 @@ def test_null_handles_rejected():
     assert L.eq_assemble_jacobian(None, mu, None, None, None, None, None, None, None, None) == ift.IFT_EINVAL
     assert L.rom_gauss_newton_step(None, mu, None, None, None, None, None) == ift.IFT_EINVAL
     assert L.ift_rom_get_gathers(None, None, None, None, None, None) == ift.IFT_EINVAL
+    assert L.ift_problem_neighbour_map(None, None) == ift.IFT_EINVAL
     L.ift_problem_destroy(None)
     L.ift_rom_destroy(None)
 
