@@ -369,7 +369,16 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
     constexpr int nface = 3 * D::NQF * (2 * D::NC + 2);
     constexpr int ntask = n_point_tasks<D, true>();
     if (tid < ntask) {
-      const int k = tid;
+      int k = tid;
+      if constexpr (nface >= 64) {
+        // wave 0: faces, then the distortion tasks; wave 1: the other
+        // faces, then the volume tasks (each wave's lanes run their kinds of
+        // task one after the other, so the two waves' chains are balanced)
+        constexpr int f0 = 64 - D::NQV;
+        if (tid >= f0 && tid < 64) k = nface + nvol + (tid - f0);
+        else if (tid >= 64 && tid < 64 + nface - f0) k = tid - 64 + f0;
+        else if (tid >= 64 + nface - f0) k = nface + (tid - 64 - (nface - f0));
+      }
       // face tasks first so that whole waves run the (heavier) face path
       if (k < nface) {
         int dir = k % (2 * D::NC + 2);
