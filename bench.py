@@ -66,7 +66,7 @@ KNAMES = {"points": "k_points_eq<Euler P2, fp64>", "eq_jac": "k_eq_fused<Euler P
 # counters have been taken on the kernel as it now stands.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 # Measured on this workload (profiles/eq_jacobian_euler_p2_819x16.md).
-TRAFFIC_KIB = {"points": (4594.0, 74120.0), "eq_jac": (45546.0, 3088.0), "gram": (2458.0, 291.0)}
+TRAFFIC_KIB = {"points": (4600.0, 74120.0), "eq_jac": (45547.0, 3088.0), "gram": (2458.0, 291.0)}
 # Full-order loop with Jacobians: reads U_e, the neighbour traces, x_e, X_e
 # and connectivity; writes R_e, N_e, dR/dU_e, dR/dU_e', dR/dx_e, dN/dx_e.
 HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)
@@ -680,8 +680,7 @@ def main():
     avg = {k: (ms / c * 1e-3 if c else 0.0) for k, (c, ms) in kt.items()}
     log("step %.1f us: " % (ms_per_step * 1e3) + ", ".join(
         f"{k} {v * 1e6:.1f} us x {kt[k][0] / args.steps:.0f}" for k, v in avg.items()))
-    # a kernel may run as several launches per step (the Jacobian call runs
-    # its point physics and projection as a pipeline over chunks of points)
+    # per launch: a kernel may run as several launches per step
     launches = {k: c / args.steps for k, (c, ms) in kt.items()}
     dom = max(avg, key=lambda k: avg[k] * launches[k])
     t_dom = avg[dom]
