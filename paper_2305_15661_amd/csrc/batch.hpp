@@ -520,6 +520,13 @@ __global__ __launch_bounds__(64) void k_start_select(const BatchInst* I, BatchSt
   }
 }
 
+// Keeps every stride-th instance in its state and marks the others DONE
+// (the autotuner's stand-in for the late rounds of a solve).
+__global__ void k_batch_keep_every(BatchState* S, int n_inst, int stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_inst && i % stride != 0) S[i].state = BS_DONE;
+}
+
 // Fresh state for every instance.
 __global__ void k_batch_init(BatchState* S, int n_inst, int mixed, int presolve, double lambda) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -1257,6 +1257,7 @@ struct ift_batch {
 
 static constexpr int BATCH_E_CAND[] = {4, 8, 16, 32};
 static constexpr int BATCH_T = 2;           // line-search trials per round
+static constexpr float BATCH_TUNE_TAIL = 4.f;   // weight of the one-in-eight timing in the autotuner
 static constexpr int BATCH_ROUNDS = 4;      // rounds per graph replay (one completion check each)
 static constexpr double BATCH_TOL_MIX = 1e-5;   // gradient norms that end the mixed-precision rounds
 static constexpr int BATCH_BT_MIX = 3;          // mixed-precision halvings before the switch to FP64
@@ -1542,17 +1543,25 @@ extern "C" ift_status ift_batch_autotune(ift_batch* b, const double* mu, const d
   for (int E : BATCH_E_CAND) {
     b->E = E;
     if ((s = batch_upload(b)) != IFT_OK) break;
+    // the Jacobian phase with every instance active and with one in eight
+    // (the late rounds of a solve, where few instances remain), weighted
+    // by the share of a solve's rounds each stands for
     float tot = 0.f;
-    for (int rep = 0; rep < 3; ++rep) {
-      hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
-                         b->precision == IFT_MIXED_BF16 ? 1 : 0, 0, 0.0);
-      HIP_TRY(hipEventRecord(e0, stream));
-      batch_phase(b, 0, stream);
-      HIP_TRY(hipEventRecord(e1, stream));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (rep > 0) tot += ms;   // the first run warms up
+    for (int sub = 0; sub < 2; ++sub) {
+      for (int rep = 0; rep < 3; ++rep) {
+        hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
+                           b->precision == IFT_MIXED_BF16 ? 1 : 0, 0, 0.0);
+        if (sub)
+          hipLaunchKernelGGL(k_batch_keep_every, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state,
+                             b->n_inst, 8);
+        HIP_TRY(hipEventRecord(e0, stream));
+        batch_phase(b, 0, stream);
+        HIP_TRY(hipEventRecord(e1, stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tot += (sub ? BATCH_TUNE_TAIL : 1.f) * ms;   // the first run warms up
+      }
     }
     if (bestE == -1 || best == 0.f || tot < best) {
       best = tot;
