@@ -305,7 +305,8 @@ ift_status ift_batch_layout(const ift_batch* batch, int* zoff, int* hoff);
  * batch by timing the candidates {4, 8, 16, 32} on the Jacobian assembly at
  * (mu, z) (device arrays as below), with every instance active and with one
  * instance in eight (weighted 4:1 for the late rounds of a solve, where few
- * instances remain); the choice is kept by the handle.
+ * instances remain; the fastest of four runs each), a larger split being
+ * taken only when 3 % faster; the choice is kept by the handle.
  * Synchronises the stream.  *chosen (host, may be null) receives it. */
 ift_status ift_batch_autotune(ift_batch* batch, const double* mu, const double* z, int* chosen, hipStream_t stream);
 

@@ -1257,7 +1257,8 @@ struct ift_batch {
 
 static constexpr int BATCH_E_CAND[] = {4, 8, 16, 32};
 static constexpr int BATCH_T = 2;           // line-search trials per round
-static constexpr float BATCH_TUNE_TAIL = 4.f;   // weight of the one-in-eight timing in the autotuner
+static constexpr float BATCH_TUNE_TAIL = 4.f;    // weight of the one-in-eight timing in the autotuner
+static constexpr float BATCH_TUNE_MARGIN = 0.97f; // a larger work split must be 3 % faster
 static constexpr int BATCH_ROUNDS = 4;      // rounds per graph replay (one completion check each)
 static constexpr double BATCH_TOL_MIX = 1e-5;   // gradient norms that end the mixed-precision rounds
 static constexpr int BATCH_BT_MIX = 3;          // mixed-precision halvings before the switch to FP64
@@ -1545,10 +1546,12 @@ extern "C" ift_status ift_batch_autotune(ift_batch* b, const double* mu, const d
     if ((s = batch_upload(b)) != IFT_OK) break;
     // the Jacobian phase with every instance active and with one in eight
     // (the late rounds of a solve, where few instances remain), weighted
-    // by the share of a solve's rounds each stands for
+    // by the share of a solve's rounds each stands for; the fastest of four
+    // timed runs of each
     float tot = 0.f;
     for (int sub = 0; sub < 2; ++sub) {
-      for (int rep = 0; rep < 3; ++rep) {
+      float fastest = 0.f;
+      for (int rep = 0; rep < 5; ++rep) {
         hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
                            b->precision == IFT_MIXED_BF16 ? 1 : 0, 0, 0.0);
         if (sub)
@@ -1560,10 +1563,13 @@ extern "C" ift_status ift_batch_autotune(ift_batch* b, const double* mu, const d
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (rep > 0) tot += (sub ? BATCH_TUNE_TAIL : 1.f) * ms;   // the first run warms up
+        if (rep > 0 && (fastest == 0.f || ms < fastest)) fastest = ms;   // the first run warms up
       }
+      tot += (sub ? BATCH_TUNE_TAIL : 1.f) * fastest;
     }
-    if (bestE == -1 || best == 0.f || tot < best) {
+    // candidates ascend in E: a larger split must be clearly faster (the
+    // late rounds with very few instances, not timed here, favour small E)
+    if (best == 0.f || tot < BATCH_TUNE_MARGIN * best) {
       best = tot;
       bestE = E;
     }
