@@ -727,6 +727,26 @@ def main():
         out["solves"] = {"converged": conv, "attempted": n_eval, "mean_gn_iterations": float(np.mean(iters)),
                          "tol": 1e-8, "seconds": dt}
         log(f"solves: {conv}/{n_eval} converged, {conv / dt:.1f} solves/s, mean iterations {np.mean(iters):.1f}")
+        # the same solves as one batch (one ROM, the points as instances)
+        bs = ift.Batch([rom] * n_eval)
+        mub = np.zeros((n_eval, 2))
+        mub[:, :wl.mus.shape[1]] = wl.mus[:n_eval]
+        mub = torch.tensor(mub, device=dev)
+        zb0 = bs.pack([np.r_[W[k].cpu().numpy(), T[k].cpu().numpy()] for k in range(n_eval)], dev)
+        infob = bs.info_buffer(dev)
+        for rep in range(2):   # the first call captures the graph
+            zb = zb0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bs.solve(mub, zb, infob, lam=0.0, max_it=60)
+            torch.cuda.synchronize()
+            dtb = time.perf_counter() - t0
+        ob = ift.Batch.info_array(infob)
+        convb = int(ob["converged"].sum())
+        out["solves"]["batched"] = {"converged": convb, "seconds": dtb, "solves_per_s": convb / dtb,
+                                    "mean_gn_iterations": float(ob["iterations"].mean())}
+        log(f"solves as one batch: {convb}/{n_eval} converged, {convb / dtb:.1f} solves/s")
+        del bs
 
     # ------------------------------------------------------- batched solves
     if not args.no_batch:
