@@ -611,7 +611,7 @@ def main():
                     help="only run a device copy of this size (traffic-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this build has no multi-GPU path)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs one GPU per process; instances shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _lib():
     from paper_2305_15661_amd import ift
     if not os.path.exists(ift.LIB_PATH):
-        pytest.fail("libift.so not built: run __graft_entry__.build()")
+        pytest.fail("libift.so not built: run paper_2305_15661_amd/build.py")
     return ift, ift.lib()
 
 
