@@ -3,7 +3,8 @@
 Each case patches one plausible error into the oracle for the duration of
 the test and checks that an independent pin detects it: a transposed mapping
 Jacobian, a wrong neighbour orientation in the gather, a flipped upwinding
-sign, a wrong distortion exponent and a misplaced source point."""
+sign, a wrong distortion exponent, a wrong source and a missing block of the
+alignment Jacobian."""
 import numpy as np
 
 from conftest import rel
@@ -86,3 +87,32 @@ def test_source_at_reference_position_is_caught(st_burgers, monkeypatch):
     monkeypatch.setattr(ph, "burgers_source", bad)
     R = rs.hdm_assemble(rs.Problem(wl), wl.mus[0], U, x, jac=False)["R"]
     assert rel(R, physdg.physical_residual(wl, wl.mus[0], U, x)) > 1e-6
+
+
+def test_alignment_without_distortion_rows_is_caught(monkeypatch):
+    # dropping the N_x rows of the alignment Jacobian (or misplacing the
+    # R_U Phi_j block) breaks the central-difference pin of dF/d(w, x)
+    import synth
+    from oracle import align
+    wl = synth.tiny_burgers()
+    pb = rs.Problem(wl)
+    Phi_j = wl.Phi[:, :3]
+    good = align.jacobian
+
+    def bad(prob, Phi, A):
+        J = good(prob, Phi, A)
+        J[-A["Nx"].shape[0]:, :] = 0.0
+        return J
+    monkeypatch.setattr(align, "jacobian", bad)
+    mu = wl.mus[0]
+    w = Phi_j.T @ (wl.Phi @ wl.w_eval[0])
+    x = wl.X + wl.Psi @ wl.tau_eval[0]
+    F, _, A = align.residual(pb, Phi_j, mu, w, x)
+    J = align.jacobian(pb, Phi_j, A)
+    c = 3 + 2 * 40            # x-coordinate of an interior node
+    h = 1e-6
+    xp, xm = x.copy(), x.copy()
+    xp[c - 3] += h
+    xm[c - 3] -= h
+    fd = (align.residual(pb, Phi_j, mu, w, xp)[0] - align.residual(pb, Phi_j, mu, w, xm)[0]) / (2 * h)
+    assert rel(J[:, c], fd) > 1e-3
