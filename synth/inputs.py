@@ -224,8 +224,9 @@ def spacetime_burgers(n_eval: int = 16, nx: int = 8, ny: int = 8, p: int = 1, n:
 def euler_p2(nx: int = 128, ny: int = 64, n: int = 20, m: int = 10, n_s: int | None = None,
              n_eval: int = 16, seed_phi: int = 1001, kappa: float = 0.1,
              alpha_deg: float = 0.0, all_farfield: bool = False,
-             rho_dist: str = "lognormal") -> Workload:
-    mesh = structured_mesh(nx, ny, 2.0, 1.0, 2)
+             rho_dist: str = "lognormal", p: int = 2) -> Workload:
+    """The Euler workload; P2 (the benchmark) unless p = 1."""
+    mesh = structured_mesh(nx, ny, 2.0, 1.0, p)
     if n_s is None:
         n_s = max(1, int(round(0.05 * mesh.n_elem)))
     U_ref = euler_reference_state(mesh)
@@ -254,7 +255,7 @@ def euler_p2(nx: int = 128, ny: int = 64, n: int = 20, m: int = 10, n_s: int | N
     scale = 0.02 * np.linalg.norm(U_ref) / np.sqrt(n)
     w = w0[None, :] + scale * rng.standard_normal((n_eval, n))
     tau = np.stack([_rescale_l1(rng.uniform(-1, 1, m)) for _ in range(n_eval)])
-    return Workload("euler_p2", "euler", 2, mesh, 4, Phi, Psi, eq_elem, eq_rho, mus, w, tau,
+    return Workload(f"euler_p{p}", "euler", p, mesh, 4, Phi, Psi, eq_elem, eq_rho, mus, w, tau,
                     kappa=kappa, all_farfield=all_farfield, extra={"U_ref": U_ref})
 
 

@@ -75,6 +75,12 @@ def st_p2_case(dev):
 
 
 @pytest.fixture(scope="module")
+def euler_p1_case(dev):
+    # P1 Euler, 16x8 cells, 64 EQ elements (the other four-component discretisation)
+    return Case(synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=64, p=1), dev)
+
+
+@pytest.fixture(scope="module")
 def euler_case(dev):
     # 16x8 cells (256 P2 elements), 64 EQ elements: several tiles and a ragged tail
     return Case(synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=64), dev)
@@ -93,7 +99,7 @@ def _hdm_gpu(case, mu, U, x, jac=True):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case"])
 def test_hdm_assemble_parity(which, request):
     from oracle import residual as ors
     case = request.getfixturevalue(which)
@@ -153,7 +159,7 @@ def _eq_gpu(case, mu, w, tau):
                 Ft=f(Ft), PhiT_r=f(ptr), n_bad=int(f(nb)[0]))
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case"])
 def test_eq_assembly_parity(which, request):
     case = request.getfixturevalue(which)
     wl = case.wl
@@ -202,7 +208,7 @@ def test_single_element_and_boundary_only_eq_sets(dev):
         assert rel(g["g"], oj["g"]) < 1e-12 and rel(g["H"], oj["H"]) < 1e-12
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case"])
 def test_batched_points_match_single_calls_and_oracle(which, request):
     """All 16 seeded evaluation points in one batched launch (device mu)."""
     import torch
