@@ -123,3 +123,12 @@ def test_greedy_select_ranks_invalid_candidates_first():
     assert ift.greedy_select(np.array([0.1, 3.0, 2.0])) == 1
     assert ift.greedy_select(np.array([0.1, 3.0, np.inf, np.nan])) == 2
     assert ift.greedy_select(np.array([0.1, np.nan, 3.0])) == 1
+
+
+def test_bench_refuses_several_gpus():
+    # one GPU per process: the benchmark says so instead of running
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
