@@ -57,7 +57,7 @@ KBYTES = {"points": 8 * (24 * 20 + 36 * 20 + 12 * 10 + 12) + 24,
 KFLOPS = {"points": None,
           "eq_jac": 57600 + 5760 + 43200 + 1440,
           "gram": None}
-KNAMES = {"points": "k_points_eq<Euler P2, fp64>", "eq_jac": "k_eq_fused<Euler P2, fp64, 2>",
+KNAMES = {"points": "k_points_eq2<Euler P2, fp64>", "eq_jac": "k_eq_fused<Euler P2, fp64, 2>",
           "gram": "k_fused_final"}
 # HBM traffic per launch of each kernel from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) on this workload, scaled by what the same
@@ -66,7 +66,7 @@ KNAMES = {"points": "k_points_eq<Euler P2, fp64>", "eq_jac": "k_eq_fused<Euler P
 # counters have been taken on the kernel as it now stands.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 # Measured on this workload (profiles/eq_jacobian_euler_p2_819x16.md).
-TRAFFIC_KIB = {"points": (4600.0, 74120.0), "eq_jac": (45547.0, 3088.0), "gram": (2458.0, 291.0)}
+TRAFFIC_KIB = {"points": (4512.0, 74017.0), "eq_jac": (45552.0, 3088.0), "gram": (2458.0, 291.0)}
 # Full-order loop with Jacobians: reads U_e, the neighbour traces, x_e, X_e
 # and connectivity; writes R_e, N_e, dR/dU_e, dR/dU_e', dR/dx_e, dN/dx_e.
 HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)

@@ -395,6 +395,40 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
   }
 }
 
+// Phase B with Jacobians for two elements in a 256-thread block, used when
+// one element has at least 64 face tasks (four-component P2).  The 2 x nface
+// face tasks fill waves 0-2 evenly; wave 3 runs the 2 x NQV*NC volume tasks
+// and then the 2 x NQV distortion tasks.  No wave runs both the face and the
+// volume path, which the one-element layout cannot avoid.
+template <class D>
+constexpr bool pair_layout() {
+  constexpr int nface = 3 * D::NQF * (2 * D::NC + 2), nvol = D::NQV * D::NC;
+  return nface >= 64 && (2 * nface) % 3 == 0 && 2 * nface / 3 <= 64 && 2 * (nvol + D::NQV) <= 64;
+}
+
+template <class D, class R>
+IFT_DEV void phase_points_pair(ElemLDS<D, R>* s, int tid, const PhysConst& pc, R kappa, R eps) {
+  static_assert(pair_layout<D>(), "two-element layout");
+  using TT = Tan<R>;
+  constexpr int nvol = D::NQV * D::NC;
+  constexpr int nface = 3 * D::NQF * (2 * D::NC + 2);
+  constexpr int fw = 2 * nface / 3;   // face lanes per wave
+  const int w = tid >> 6, l = tid & 63;
+  if (w < 3) {
+    if (l < fw) {
+      const int g = w * fw + l, h = g / nface, k = g % nface;
+      const int dir = k % (2 * D::NC + 2), pt = k / (2 * D::NC + 2);
+      face_point<D, TT, R>(s[h].tab, s[h], pt / D::NQF, pt % D::NQF, dir, pc);
+    }
+  } else if (l < 2 * nvol) {
+    const int h = l / nvol, r = l % nvol;
+    vol_point<D, TT, R>(s[h].tab, s[h], r / D::NC, r % D::NC, pc, eps);
+  } else if (l < 2 * nvol + 2 * D::NQV) {
+    const int h = (l - 2 * nvol) / D::NQV, q = (l - 2 * nvol) % D::NQV;
+    eta_point_grad<D, R>(s[h].tab, q, s[h].x, s[h].X, eps, s[h].deta[q]);
+  }
+}
+
 // After phase B with Jacobians (and a barrier): N_e and dN_e/dx_e from the
 // per-point distortion terms, J = sum_k x_k grad_xi phi_k.
 template <class D, class R>

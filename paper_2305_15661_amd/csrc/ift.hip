@@ -516,7 +516,10 @@ struct HdmLaunch {
     if (jac && D::NC == 4) {
       // one pass: point physics and the blocks written from the same LDS
       ProfScope ps(IFT_PROF_HDM, st);
-      hipLaunchKernelGGL((k_hdm_fused<D, double>), dim3(a.n_elem), dim3(NTHR_PTS), 0, st, a);
+      if constexpr (pair_layout<D>())
+        hipLaunchKernelGGL((k_hdm_fused2<D, double>), dim3((a.n_elem + 1) / 2), dim3(2 * NTHR_PTS), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_hdm_fused<D, double>), dim3(a.n_elem), dim3(NTHR_PTS), 0, st, a);
     } else if (jac) {
       {
         ProfScope ps(IFT_PROF_POINTS, st);
@@ -941,7 +944,10 @@ struct EqLaunch {
     if (jac) {
       {
         ProfScope ps(IFT_PROF_POINTS, st);
-        hipLaunchKernelGGL((k_points_eq<D, R>), dim3(xcd_pad(a.n_s), n_pts), dim3(NTHR_PTS), 0, st, a);
+        if constexpr (pair_layout<D>())
+          hipLaunchKernelGGL((k_points_eq2<D, R>), dim3(xcd_pad((a.n_s + 1) / 2), n_pts), dim3(2 * NTHR_PTS), 0, st, a);
+        else
+          hipLaunchKernelGGL((k_points_eq<D, R>), dim3(xcd_pad(a.n_s), n_pts), dim3(NTHR_PTS), 0, st, a);
       }
       ProfScope ps(IFT_PROF_EQ_JAC, st, true);
       if (!fa) hipLaunchKernelGGL((k_eq_asm<D, R>), dim3(a.n_s, n_pts), dim3(NTHR), 0, st, a, Bw, Bx);

@@ -231,6 +231,25 @@ __global__ __launch_bounds__(NTHR_PTS) void k_hdm_fused(HdmArgs a) {
   if constexpr (D::NC == 4) hdm_write_blocks<D, R>(s, a, e, tid, NTHR_PTS);
 }
 
+// The same for elements 2b and 2b+1 in one 256-thread block (four-component
+// P2, phase_points_pair).  With an odd element count the last block computes
+// its one element twice and writes it once.
+template <class D, class R>
+__global__ __launch_bounds__(2 * NTHR_PTS) void k_hdm_fused2(HdmArgs a) {
+  __shared__ ElemLDS<D, R> s[2];
+  const int e0 = 2 * blockIdx.x;
+  const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
+  const int e = e0 + min(h, a.n_elem - 1 - e0);
+  load_tab<D, R>(s[h], t, NTHR_PTS);
+  load_hdm<D, R>(s[h], a, e, t, NTHR_PTS);
+  __syncthreads();
+  phase_points_pair<D, R>(s, tid, a.pc, R(a.kappa), R(a.eps));
+  __syncthreads();
+  phase_distortion<D, R>(s[h], t, R(a.kappa));
+  __syncthreads();
+  if (e == e0 + h) hdm_write_blocks<D, R>(s[h], a, e, t, NTHR_PTS);
+}
+
 template <class D, class R>
 __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
   __shared__ ElemLDS<D, R> s;
@@ -268,6 +287,27 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_eq(EqArgs a) {
   const int k = blockIdx.x, pt = blockIdx.y;
   if (k >= a.n_s) return;   // the element axis is padded to a multiple of 8 (one XCD per element)
   points_eq_body<D, R>(s, a, k, pt, threadIdx.x);
+}
+
+// Point data of sampled elements 2b and 2b+1 at evaluation point pt (one
+// 256-thread block, phase_points_pair).  With an odd n_s the last block
+// computes its one element twice and writes it once.
+template <class D, class R>
+__global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
+  __shared__ ElemLDS<D, R> s[2];
+  const int k0 = 2 * blockIdx.x, pt = blockIdx.y;
+  if (k0 >= a.n_s) return;   // padding blocks (whole block)
+  const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
+  const int k = k0 + min(h, a.n_s - 1 - k0);
+  load_tab<D, R>(s[h], t, NTHR_PTS);
+  load_eq<D, R>(s[h], a, k, pt, t, NTHR_PTS);   // ends with a barrier
+  const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
+  phase_points_pair<D, R>(s, tid, pc, R(a.kappa), R(a.eps));
+  __syncthreads();
+  phase_distortion<D, R>(s[h], t, R(a.kappa));
+  __syncthreads();
+  if (k == k0 + h)
+    copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s[h].p, t, NTHR_PTS);
 }
 
 // ------------------------------------------------ full-order assembly

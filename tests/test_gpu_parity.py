@@ -86,6 +86,28 @@ def euler_case(dev):
     return Case(synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=64), dev)
 
 
+@pytest.fixture(scope="module")
+def euler_odd_case(dev):
+    # an odd element count and an odd EQ set: the 16x8 P2 mesh without its
+    # last element (the face it shared becomes a top-boundary face), so the
+    # kernels that take two elements per block run their one-element tail
+    import dataclasses
+    wl = synth.euler_p2(nx=16, ny=8, n=20, m=10, n_s=64)
+    m = wl.mesh
+    Ne = m.n_elem
+    nbr = m.elem_nbr[:-1].copy()
+    nbr[nbr == Ne - 1] = -4
+    mesh = dataclasses.replace(m, elem_gnodes=m.elem_gnodes[:-1].copy(), elem_nbr=nbr)
+    nue = wl.Phi.shape[0] // Ne
+    keep = np.nonzero(wl.eq_elem < Ne - 1)[0]
+    if keep.size % 2 == 0:
+        keep = keep[1:]
+    wl = dataclasses.replace(wl, name=wl.name + "-odd", mesh=mesh, Phi=wl.Phi[:-nue].copy(),
+                             eq_elem=wl.eq_elem[keep].copy(), eq_rho=wl.eq_rho[keep].copy())
+    assert mesh.n_elem % 2 == 1 and wl.eq_elem.size % 2 == 1
+    return Case(wl, dev)
+
+
 def _hdm_gpu(case, mu, U, x, jac=True):
     import torch
     p, d = case.prob, case.dev
@@ -99,7 +121,8 @@ def _hdm_gpu(case, mu, U, x, jac=True):
     return {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case",
+                                   "euler_odd_case"])
 def test_hdm_assemble_parity(which, request):
     from oracle import residual as ors
     case = request.getfixturevalue(which)
@@ -159,7 +182,8 @@ def _eq_gpu(case, mu, w, tau):
                 Ft=f(Ft), PhiT_r=f(ptr), n_bad=int(f(nb)[0]))
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case",
+                                   "euler_odd_case"])
 def test_eq_assembly_parity(which, request):
     case = request.getfixturevalue(which)
     wl = case.wl
@@ -208,7 +232,8 @@ def test_single_element_and_boundary_only_eq_sets(dev):
         assert rel(g["g"], oj["g"]) < 1e-12 and rel(g["H"], oj["H"]) < 1e-12
 
 
-@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case"])
+@pytest.mark.parametrize("which", ["tiny_case", "euler_case", "st_case", "st_p2_case", "euler_p1_case",
+                                   "euler_odd_case"])
 def test_batched_points_match_single_calls_and_oracle(which, request):
     """All 16 seeded evaluation points in one batched launch (device mu)."""
     import torch
