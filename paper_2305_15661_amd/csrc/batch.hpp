@@ -165,6 +165,34 @@ __global__ __launch_bounds__(NTHR_PTS, 2) void k_points_batch(const BatchInst* I
   }
 }
 
+// The same with two listed items per 256-thread block (four-component P2,
+// phase_points_pair); the two may belong to different instances, so each
+// half keeps its physical constants in LDS.  An odd item count leaves the
+// last block one item, computed twice and written once.
+template <class D, class R>
+__global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchInst* I, BatchLists L, int n_inst) {
+  __shared__ ElemLDS<D, R> s[2];
+  __shared__ PhysConst spc[2];
+  const int total = L.cnt[0];
+  const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
+  int inst = 0;
+  for (int i0 = 2 * blockIdx.x; i0 < total; i0 += 2 * gridDim.x) {
+    const int item = i0 + min(h, total - 1 - i0);
+    inst = __builtin_amdgcn_readfirstlane(batch_owner_from(L.off, n_inst, item, inst));
+    const int k = item - L.off[inst];
+    const EqArgs& a = I[inst].a;
+    load_tab<D, R>(s[h], t, NTHR_PTS);
+    if (t == 0) spc[h] = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu) : a.pc;
+    load_eq<D, R>(s[h], a, k, 0, t, NTHR_PTS);   // ends with a barrier
+    phase_points_pair<D, R>(s, tid, [&](int e) -> const PhysConst& { return spc[e]; }, R(a.eps));
+    __syncthreads();
+    phase_distortion<D, R>(s[h], t, R(a.kappa));
+    __syncthreads();
+    if (item == i0 + h) copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + k, &s[h].p, t, NTHR_PTS);
+    __syncthreads();
+  }
+}
+
 // Fused assembly + Gram of the JAC instances with NT column tiles.
 template <class D, class R, int NT>
 __global__ __launch_bounds__(NTHR, NT == 1 ? 3 : (NT == 3 ? 2 : 1)) void k_fused_batch(const BatchInst* I, BatchLists L, int n_inst, int E) {

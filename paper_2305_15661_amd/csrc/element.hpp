@@ -399,15 +399,17 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
 // one element has at least 64 face tasks (four-component P2).  The 2 x nface
 // face tasks fill waves 0-2 evenly; wave 3 runs the 2 x NQV*NC volume tasks
 // and then the 2 x NQV distortion tasks.  No wave runs both the face and the
-// volume path, which the one-element layout cannot avoid.
+// volume path, which the one-element layout cannot avoid.  pc_of(h) gives
+// the physical constants of element h (the two may belong to different
+// instances of a batch).
 template <class D>
 constexpr bool pair_layout() {
   constexpr int nface = 3 * D::NQF * (2 * D::NC + 2), nvol = D::NQV * D::NC;
   return nface >= 64 && (2 * nface) % 3 == 0 && 2 * nface / 3 <= 64 && 2 * (nvol + D::NQV) <= 64;
 }
 
-template <class D, class R>
-IFT_DEV void phase_points_pair(ElemLDS<D, R>* s, int tid, const PhysConst& pc, R kappa, R eps) {
+template <class D, class R, class PC>
+IFT_DEV void phase_points_pair(ElemLDS<D, R>* s, int tid, const PC& pc_of, R eps) {
   static_assert(pair_layout<D>(), "two-element layout");
   using TT = Tan<R>;
   constexpr int nvol = D::NQV * D::NC;
@@ -418,11 +420,11 @@ IFT_DEV void phase_points_pair(ElemLDS<D, R>* s, int tid, const PhysConst& pc, R
     if (l < fw) {
       const int g = w * fw + l, h = g / nface, k = g % nface;
       const int dir = k % (2 * D::NC + 2), pt = k / (2 * D::NC + 2);
-      face_point<D, TT, R>(s[h].tab, s[h], pt / D::NQF, pt % D::NQF, dir, pc);
+      face_point<D, TT, R>(s[h].tab, s[h], pt / D::NQF, pt % D::NQF, dir, pc_of(h));
     }
   } else if (l < 2 * nvol) {
     const int h = l / nvol, r = l % nvol;
-    vol_point<D, TT, R>(s[h].tab, s[h], r / D::NC, r % D::NC, pc, eps);
+    vol_point<D, TT, R>(s[h].tab, s[h], r / D::NC, r % D::NC, pc_of(h), eps);
   } else if (l < 2 * nvol + 2 * D::NQV) {
     const int h = (l - 2 * nvol) / D::NQV, q = (l - 2 * nvol) % D::NQV;
     eta_point_grad<D, R>(s[h].tab, q, s[h].x, s[h].X, eps, s[h].deta[q]);

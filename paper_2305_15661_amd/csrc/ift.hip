@@ -1439,8 +1439,12 @@ struct BatchLaunch {
     if (phase == 0) {
       hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
                          (const BatchState*)b->d_state, L, ni, (int)BS_JAC, want_prec, 1);
-      hipLaunchKernelGGL((k_points_batch<D, R>), dim3(BATCH_GRID_PTS), dim3(NTHR_PTS), 0, st,
-                         (const BatchInst*)b->d_inst, L, ni);
+      if constexpr (pair_layout<D>())
+        hipLaunchKernelGGL((k_points_batch2<D, R>), dim3(BATCH_GRID_PTS / 2), dim3(2 * NTHR_PTS), 0, st,
+                           (const BatchInst*)b->d_inst, L, ni);
+      else
+        hipLaunchKernelGGL((k_points_batch<D, R>), dim3(BATCH_GRID_PTS), dim3(NTHR_PTS), 0, st,
+                           (const BatchInst*)b->d_inst, L, ni);
       fused<D, R, 1>(L, mixed);
       fused<D, R, 2>(L, mixed);
       fused<D, R, 3>(L, mixed);

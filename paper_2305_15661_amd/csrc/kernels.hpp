@@ -243,7 +243,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_hdm_fused2(HdmArgs a) {
   load_tab<D, R>(s[h], t, NTHR_PTS);
   load_hdm<D, R>(s[h], a, e, t, NTHR_PTS);
   __syncthreads();
-  phase_points_pair<D, R>(s, tid, a.pc, R(a.kappa), R(a.eps));
+  phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return a.pc; }, R(a.eps));
   __syncthreads();
   phase_distortion<D, R>(s[h], t, R(a.kappa));
   __syncthreads();
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   load_tab<D, R>(s[h], t, NTHR_PTS);
   load_eq<D, R>(s[h], a, k, pt, t, NTHR_PTS);   // ends with a barrier
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
-  phase_points_pair<D, R>(s, tid, pc, R(a.kappa), R(a.eps));
+  phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return pc; }, R(a.eps));
   __syncthreads();
   phase_distortion<D, R>(s[h], t, R(a.kappa));
   __syncthreads();
