@@ -1269,6 +1269,9 @@ static constexpr int BATCH_ROUNDS = 4;      // rounds per graph replay (one comp
 static constexpr double BATCH_TOL_MIX = 1e-5;   // gradient norms that end the mixed-precision rounds
 static constexpr int BATCH_BT_MIX = 3;          // mixed-precision halvings before the switch to FP64
 static constexpr int BATCH_GRID_PTS = 2048, BATCH_GRID_RES = 1024, BATCH_GRID_FUSED = 1024;
+// the two-item points kernel: one 4-wave block per resident slot (two per CU
+// at two waves per SIMD; 512 blocks ran 1 % faster than 1024 or 2048)
+static constexpr int BATCH_GRID_PTS2 = 512;
 
 static int batch_nblk(int n_s, int E) { return (n_s + 4 * E - 1) / (4 * E); }
 
@@ -1440,7 +1443,7 @@ struct BatchLaunch {
       hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
                          (const BatchState*)b->d_state, L, ni, (int)BS_JAC, want_prec, 1);
       if constexpr (pair_layout<D>())
-        hipLaunchKernelGGL((k_points_batch2<D, R>), dim3(BATCH_GRID_PTS / 2), dim3(2 * NTHR_PTS), 0, st,
+        hipLaunchKernelGGL((k_points_batch2<D, R>), dim3(BATCH_GRID_PTS2), dim3(2 * NTHR_PTS), 0, st,
                            (const BatchInst*)b->d_inst, L, ni);
       else
         hipLaunchKernelGGL((k_points_batch<D, R>), dim3(BATCH_GRID_PTS), dim3(NTHR_PTS), 0, st,
