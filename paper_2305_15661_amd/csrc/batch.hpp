@@ -176,12 +176,12 @@ __global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchIn
   const int total = L.cnt[0];
   const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
   int inst = 0;
+  load_tab<D, R>(s[h], t, NTHR_PTS);   // constant: visible after the first barrier
   for (int i0 = 2 * blockIdx.x; i0 < total; i0 += 2 * gridDim.x) {
     const int item = i0 + min(h, total - 1 - i0);
     inst = __builtin_amdgcn_readfirstlane(batch_owner_from(L.off, n_inst, item, inst));
     const int k = item - L.off[inst];
     const EqArgs& a = I[inst].a;
-    load_tab<D, R>(s[h], t, NTHR_PTS);
     if (t == 0) spc[h] = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu) : a.pc;
     load_eq<D, R>(s[h], a, k, 0, t, NTHR_PTS);   // ends with a barrier
     phase_points_pair<D, R>(s, tid, [&](int e) -> const PhysConst& { return spc[e]; }, R(a.eps));
