@@ -116,3 +116,23 @@ def test_alignment_without_distortion_rows_is_caught(monkeypatch):
     xm[c - 3] -= h
     fd = (align.residual(pb, Phi_j, mu, w, xp)[0] - align.residual(pb, Phi_j, mu, w, xm)[0]) / (2 * h)
     assert rel(J[:, c], fd) > 1e-3
+
+
+def test_harten_fix_without_factor_two_is_caught(monkeypatch):
+    # (lam^2 + delta^2) / delta instead of / (2 delta): the fix then jumps
+    # to 2 delta at |lam| = delta, and doubles the entropy-wave dissipation
+    # of a slow contact; both pins must fail
+    import test_oracle_physics as top
+    good = ph.harten_abs
+
+    def bad(lam, delta):
+        a = ph.absd(lam)
+        fixed = (lam * lam + delta * delta) / (1.0 * delta)
+        return ph.where(a.v < delta.v, fixed, a)
+    monkeypatch.setattr(ph, "harten_abs", bad)
+    import pytest
+    with pytest.raises(AssertionError):
+        top.test_harten_fix_is_c1_at_the_threshold()
+    with pytest.raises(AssertionError):
+        top.test_roe_flux_at_a_slow_contact_matches_hand_computation()
+    assert good is not bad

@@ -127,3 +127,64 @@ def test_lf_is_monotone():
     d = Dual.seed(x, 0, 4)
     H = ph.burgers_lf(d[:, 0:1], d[:, 1:2], d[:, 2:4])
     assert (H.d[:, 0, 0] >= -1e-15).all() and (H.d[:, 0, 1] <= 1e-15).all()
+
+
+def test_harten_fix_is_c1_at_the_threshold():
+    """Harten's fix replaces |lam| below delta by the parabola
+    (lam^2 + delta^2) / (2 delta): it equals |lam| = delta with slope +-1 at
+    |lam| = delta (C^1 joint), takes its minimum delta / 2 at lam = 0, and
+    leaves |lam| >= delta untouched (Sec. 4.2 reading of the Roe flux)."""
+    for delta in (0.07, 0.3, 1.9):
+        d = Dual.seed(np.array([0.0]), 0, 1)
+        dl = 0.0 * d + delta            # a constant Dual
+        eps = 1e-9 * delta
+        for sgn in (1.0, -1.0):
+            lo = ph.harten_abs(d + sgn * (delta - eps), dl)
+            hi = ph.harten_abs(d + sgn * (delta + eps), dl)
+            # value continuity at the joint (a jump of O(delta) fails)
+            assert abs(lo.v[0] - delta) < 1e-8 * delta
+            assert abs(hi.v[0] - delta) < 1e-8 * delta
+            # slope continuity: d/dlam = sign(lam) on both sides
+            assert abs(lo.d[0, 0] - sgn) < 1e-8 and abs(hi.d[0, 0] - sgn) == 0.0
+        mid = ph.harten_abs(d + 0.0, dl)
+        assert abs(mid.v[0] - 0.5 * delta) < 1e-15 * delta and abs(mid.d[0, 0]) < 1e-15
+        q = ph.harten_abs(d + 0.25 * delta, dl)
+        # (1/16 + 1) delta^2 / (2 delta) = 17/32 delta, slope 1/4
+        assert abs(q.v[0] - 17.0 / 32.0 * delta) < 1e-15 and abs(q.d[0, 0] - 0.25) < 1e-14
+
+
+def _slow_contact_flux(rhoL, rhoR, v, p, nt):
+    """Roe flux across a pure contact (equal velocity and pressure) written out
+    by hand: only the entropy wave carries strength, alpha_2 = rho_R - rho_L
+    along r_2 = (1, u, v, |v|^2 / 2), at speed v.n.  Its Roe-averaged sound
+    speed has the closed form c~^2 = gamma p / sqrt(rho_L rho_R), and with
+    |v.n| < delta = c~ / 10 the fixed speed is (vn^2 + delta^2) / (2 delta)."""
+    nmag = np.hypot(*nt)
+    n = nt / nmag
+    vn = v @ n
+    ct = np.sqrt(G * p / np.sqrt(rhoL * rhoR))
+    delta = 0.1 * ct
+    assert abs(vn) < delta
+    lam_fix = (vn * vn + delta * delta) / (2.0 * delta)
+    def fn(rho):
+        E = p / (G - 1) + 0.5 * rho * (v @ v)
+        m = rho * v
+        return np.array([m @ nt, m[0] * (v @ nt) + p * nt[0], m[1] * (v @ nt) + p * nt[1], (E + p) * (v @ nt)])
+    r2 = np.array([1.0, v[0], v[1], 0.5 * (v @ v)])
+    return 0.5 * (fn(rhoL) + fn(rhoR)) - 0.5 * nmag * lam_fix * (rhoR - rhoL) * r2
+
+
+def _contact_states(rhoL, rhoR, v, p):
+    st = lambda rho: np.array([rho, rho * v[0], rho * v[1], p / (G - 1) + 0.5 * rho * (v @ v)])
+    return st(rhoL)[None], st(rhoR)[None]
+
+
+def test_roe_flux_at_a_slow_contact_matches_hand_computation():
+    for v, nt in ((np.array([0.03, 0.2]), np.array([1.0, 0.0])),
+                  (np.array([-0.02, 0.05]), np.array([0.6, -1.7])),
+                  (np.array([0.0, 0.0]), np.array([0.0, 2.0]))):
+        rhoL, rhoR, p = 1.0, 2.25, 1.3
+        uL, uR = _contact_states(rhoL, rhoR, v, p)
+        H = ph.euler_roe(uL, uR, nt[None], G).v[0]
+        ref = _slow_contact_flux(rhoL, rhoR, v, p, nt)
+        assert np.abs(H - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
