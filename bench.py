@@ -412,8 +412,10 @@ def eqp_leg(dev, n_train: int = 8):
     """EQ-weight training at the C1 shape: a ROM over all 16384 elements with
     unit weights, its solutions at n_train training parameters (Gauss-Newton
     steps on the device from the plain start), the elemental reduced
-    residuals at each solution on the device, and the linear program of the
-    paper's weight training solved on the host (HiGHS)."""
+    residuals at each converged solution on the device, and the linear
+    program of the paper's weight training solved on the host (HiGHS).  The
+    constraints of eq. (eqp-con) are stated at ROM-IFT solutions, so a
+    training solve that does not converge is counted and left out."""
     import torch
     import synth
     from scipy.stats import qmc
@@ -439,7 +441,11 @@ def eqp_leg(dev, n_train: int = 8):
         torch.cuda.synchronize()
         t_solve += time.perf_counter() - t0
         conv += int(info["converged"])
-        sols.append((mu, w, tau))
+        if info["converged"]:
+            sols.append((mu, w, tau))
+    if not sols:
+        log(f"eq training: none of {n_train} training solves converged; program skipped")
+        return {"training_solves_converged": 0, "training_solves": n_train}
     C = torch.zeros(Ne * rom.D, dtype=torch.float64, device=dev)
     contribs = []
     rom.element_contributions(sols[0][0], sols[0][1], sols[0][2], C)
@@ -459,12 +465,13 @@ def eqp_leg(dev, n_train: int = 8):
     t_lp = time.perf_counter() - t0
     frac = info.get("nnz", Ne) / Ne
     log(f"eq training: {conv}/{n_train} training solves in {t_solve:.2f} s; elemental residuals of {Ne} elements "
-        f"x {n_train} solutions in {t_contrib * 1e3:.1f} ms (incl. copies); program {2 + 2 * n_train * rom.D} x {Ne} "
+        f"x {len(sols)} converged solutions in {t_contrib * 1e3:.1f} ms (incl. copies); program "
+        f"{2 + 2 * len(sols) * rom.D} x {Ne} "
         f"solved in {t_lp:.2f} s: {info.get('nnz')} non-zero weights ({100 * frac:.2f} %)")
     return {"workload": f"ROM over all {Ne} P2 Euler elements, n=20, m=10, unit weights; {n_train} training "
                         f"parameters (Sobol on [2,3] x [-5,5] deg)",
-            "training_solves_converged": conv, "training_solve_seconds": t_solve,
-            "contribution_seconds": t_contrib, "program_rows": 2 + 2 * n_train * rom.D, "program_cols": Ne,
+            "training_solves": n_train, "training_solves_converged": conv, "training_solve_seconds": t_solve,
+            "contribution_seconds": t_contrib, "program_rows": 2 + 2 * len(sols) * rom.D, "program_cols": Ne,
             "delta": delta, "lp_seconds": t_lp, "lp_status": info.get("status"), "nonzero_weights": info.get("nnz"),
             "nonzero_fraction": frac, "max_violation": info.get("max_violation")}
 

@@ -60,3 +60,24 @@ def test_training_program_feasible_sparse_and_accurate(tiny):
         g = erom.jacobian(mu, w, tau)["g"]
         assert np.max(np.abs(g - full)) <= delta / len(train) * (1 + 1e-8) + 1e-12
     assert abs(vol @ rho - vol.sum()) <= delta * vol.sum() * (1 + 1e-8)
+
+
+def test_program_targets_the_unweighted_sums_for_any_guess(tiny):
+    """With a guess rho_check != 1 the training solutions move, but the
+    accuracy constraints still compare with the unweighted all-element sums
+    (the hatted S, T of eq. (eqp-con)): rho = 1 stays feasible, while the
+    guess itself is not (its weighted sums miss the unweighted ones by far
+    more than delta)."""
+    wl = tiny
+    Ne = wl.mesh.n_elem
+    rng = np.random.default_rng(17)
+    rho_check = np.where(rng.random(Ne) < 0.3, rng.uniform(0.5, 3.0, Ne), 0.0)
+    rom = _all_elements_rom(wl)
+    train = [(wl.mus[k], wl.w_eval[k], wl.tau_eval[k]) for k in (2, 6)]
+    contribs = [rom.element_contributions(*t) for t in train]
+    vol = eqp.element_volumes(wl.mesh.X, wl.mesh.elem_gnodes)
+    scale = max(np.abs(C.sum(axis=0)).max() for C in contribs)
+    delta = 1e-3 * scale
+    c, A, b = eqp.program(contribs, vol, delta, delta_vol=10.0)
+    assert np.all(A @ np.ones(Ne) <= b + 1e-12)
+    assert np.max(A @ rho_check - b) > 1.0
