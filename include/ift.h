@@ -274,7 +274,9 @@ typedef struct {
  * params->use_qr the equivalent least-squares problem by Householder QR of
  * the stacked rows, whose workspace the first such call allocates) and
  * backtrack alpha = 1, 1/2, ... until J~(z + alpha dz) <= J~(z) +
- * c1 alpha g.dz, then overwrite (w, tau).  info is a HOST pointer.
+ * c1 alpha g.dz, then overwrite (w, tau).  Both objectives of that test
+ * come from the residual kernels of eq_assemble_residual, summed in one
+ * order (J~(z) is evaluated once more for it).  info is a HOST pointer.
  * Synchronises the stream. */
 ift_status rom_gauss_newton_step(ift_rom* rom, const double* mu, double* w, double* tau,
                                  const ift_gn_params* params, ift_gn_info* info, hipStream_t stream);
@@ -343,10 +345,11 @@ ift_status eq_assemble_jacobian_batched(ift_batch* batch, const double* mu, cons
  * 1e-12), max(10 lambda, 1e-8) after a step accepted at alpha < 1.
  * params->use_qr and params->w_only must be 0.
  * The full step z + dz is taken first and tested by the next Jacobian
- * assembly, whose objective decides the sufficient-decrease test at
- * alpha = 1 (the objective equals the trial residual's to rounding); a
- * rejected step restores z and backtracks from alpha = 1/2 with trial
- * residual evaluations.
+ * assembly: the sufficient-decrease test at alpha = 1 compares the
+ * objectives of two Jacobian assemblies.  A rejected step restores z,
+ * re-evaluates J~(z) with the trial residual kernels and backtracks from
+ * alpha = 1/2 with trial residual evaluations, so that every test compares
+ * objectives summed by the same kernels in the same order.
  * The rounds (Jacobian assembly, LM step, two line-search trials) run in
  * replays of four captured rounds; after each replay the stream is
  * synchronised to read how many instances are still running.  Returns

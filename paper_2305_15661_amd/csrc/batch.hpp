@@ -12,6 +12,12 @@
 // The full step is taken before its test because nearly every accepted
 // step has alpha = 1: the assembly at the new iterate then serves both the
 // test and the next step, and a rejected full step only restores z.
+// Every Armijo test compares two objectives summed by the same kernels in
+// the same order: the full step's test compares the Gram corners of two
+// Jacobian assemblies, and backtracking first re-evaluates J~(z) with the
+// residual kernels that evaluate its trials (their per-element sums differ
+// from the Gram corner's by rounding, which near a minimum is as large as
+// the decrease the test asks for).
 // Each phase starts with k_batch_compact, which scans the instances in the
 // phase's state into work lists (exclusive sums of their element or block
 // counts); the work kernels are persistent grids that walk those lists, so
@@ -57,6 +63,7 @@ struct BatchState {
   int prec0;          // precision phase of a fresh start
   int wonly;          // 1: initialisation steps in w with tau held
   int it_w;           // steps taken in w only
+  int reval;          // 1: the next trial re-evaluates J~ at z itself (alpha = 0)
   double lam;         // LM weight of the next step
   double J, J0, Jtrial, alpha, slope, nS, nT, alpha_acc;
   double Jprev;       // objective at the previous iterate (BS_VERIFY)
@@ -229,6 +236,45 @@ __global__ __launch_bounds__(256) void k_final_batch(const BatchInst* I, BatchSt
                    blockIdx.x, 0, red);
 }
 
+// Line-search failure rules, shared by the test of the full step and the
+// trials.  After n_bt halvings a further halving is allowed unless that
+// makes more than max_backtrack, or the instance is in mixed-precision
+// rounds and has reached their halving limit.
+IFT_DEV bool ls_may_halve(const BatchState& st, const BatchParams& p, int n_bt) {
+  return n_bt < p.max_backtrack && !(st.prec == 1 && n_bt >= p.max_bt_mixed);
+}
+
+// A failed line search that restarts from the plain start (warm starts).
+IFT_DEV bool ls_restarts(const BatchState& st, const BatchParams& p) {
+  return !st.wonly && !(st.prec == 1 && st.n_bt >= p.max_bt_mixed) && st.restart;
+}
+
+// State after a line search that found no decrease within its halvings
+// (st.n_bt of them): the w-only initialisation ends, a mixed-precision
+// instance continues in FP64 rounds, a warm-started instance restarts from
+// the plain start (the caller has copied zp into z), else the solve stops.
+IFT_DEV void ls_failed(BatchState& st, const BatchParams& p) {
+  const int nb = st.n_bt;
+  st.n_bt = nb + 1;
+  st.n_bt_total += st.n_bt;
+  st.reval = 0;
+  if (st.wonly && nb >= p.max_backtrack) {
+    st.wonly = 0;       // the initialisation ends here; full steps from this iterate
+    st.state = BS_JAC;
+  } else if (st.prec == 1 && nb >= p.max_bt_mixed) {
+    st.prec = 0;        // no decrease at mixed precision: continue in FP64
+    st.state = BS_JAC;
+  } else if (st.restart) {
+    st.restart = 0;
+    st.fallback = 2;
+    st.prec = st.prec0;
+    st.state = BS_JAC;
+  } else {
+    st.status = IFT_ELINESEARCH;
+    st.state = BS_DONE;
+  }
+}
+
 // Armijo test of a full step (BS_VERIFY) and then, as for a BS_JAC
 // instance, the convergence test and the next LM step (one wave each).
 __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState* S, const BatchParams* P) {
@@ -250,16 +296,26 @@ __global__ __launch_bounds__(64) void k_lm_batch(const BatchInst* I, BatchState*
     const bool ok = J <= st.Jprev + p.c1 * st.slope;
     if (!ok) {
       // restore the previous iterate; the backtracking continues from the
-      // first halving when that is what the trial at alpha = 1 would have
-      // led to, else it re-tries alpha = 1 and the line search decides
-      for (int i = threadIdx.x; i < D; i += 64) bi.z[i] = bi.zt[i];
+      // first halving, after J~(z) has been re-evaluated by the residual
+      // kernels of the trials; with no halving allowed the trial at
+      // alpha = 1 has failed for good
+      const bool halve = ls_may_halve(st, p, 0);
+      const bool restart = !halve && ls_restarts(st, p);
+      const double* src = restart ? bi.zp : bi.zt;
+      for (int i = threadIdx.x; i < D; i += 64) bi.z[i] = src[i];
+      __syncthreads();
       if (threadIdx.x == 0) {
-        const bool halve = p.max_backtrack > 0 && !(st.prec == 1 && p.max_bt_mixed <= 0);
         st.Jtrial = J;
         st.J = st.Jprev;
-        st.alpha = halve ? 0.5 : 1.0;
-        st.n_bt = halve ? 1 : 0;
-        st.state = BS_SEARCH;
+        if (halve) {
+          st.alpha = 0.5;
+          st.n_bt = 1;
+          st.reval = 1;
+          st.state = BS_SEARCH;
+        } else {
+          st.n_bt = 0;
+          ls_failed(st, p);
+        }
       }
       return;
     }
@@ -349,6 +405,10 @@ __global__ __launch_bounds__(64) void k_trial_batch(const BatchInst* I, const Ba
   const int inst = blockIdx.x;
   if (S[inst].state != BS_SEARCH) return;
   const BatchInst& bi = I[inst];
+  if (S[inst].reval) {   // J~ at z itself, by the kernels that evaluate the trials
+    for (int i = threadIdx.x; i < bi.a.D; i += 64) bi.zt[i] = bi.z[i];
+    return;
+  }
   const double al = S[inst].alpha;
   for (int i = threadIdx.x; i < bi.a.D; i += 64) bi.zt[i] = bi.z[i] + al * bi.dz[i];
 }
@@ -403,14 +463,22 @@ __global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState
     }
     __syncthreads();
   }
-  // accept: copy the trial iterate (all lanes), then update the state
   const BatchParams p = *P;
   const double Jt = so[0] ? __builtin_inf() : sj[0];
+  if (st.reval) {
+    // J~(z) by the same kernels and order as the trials; the backtracking
+    // continues with the halving already recorded
+    __syncthreads();
+    if (t == 0) {
+      st.J = Jt;
+      st.reval = 0;
+    }
+    return;
+  }
+  // accept: copy the trial iterate (all lanes), then update the state
   const bool ok = Jt <= st.J + p.c1 * st.alpha * st.slope;
-  // the line search has failed for good: a warm-started instance restarts
-  // from the plain start instead of stopping
-  const bool fail = !ok && !st.wonly && !(st.prec == 1 && st.n_bt >= p.max_bt_mixed) && st.n_bt >= p.max_backtrack;
-  const bool restart = fail && st.restart;
+  const bool halve = !ok && ls_may_halve(st, p, st.n_bt);
+  const bool restart = !ok && !halve && ls_restarts(st, p);
   if (ok)
     for (int i = t; i < bi.a.D; i += 256) bi.z[i] = bi.zt[i];
   if (restart)
@@ -426,31 +494,11 @@ __global__ __launch_bounds__(256) void k_ls_batch(const BatchInst* I, BatchState
         if (st.alpha == 1.0) st.lam = st.lam * 0.1 < 1e-12 ? 0.0 : st.lam * 0.1;
         else st.lam = fmax(10.0 * st.lam, 1e-8);
       }
-    } else if (st.wonly && st.n_bt >= p.max_backtrack) {
-      st.n_bt += 1;
-      st.n_bt_total += st.n_bt;
-      st.wonly = 0;       // the initialisation ends here; full steps from this iterate
-      st.state = BS_JAC;
-    } else if (st.prec == 1 && st.n_bt >= p.max_bt_mixed) {
-      st.n_bt += 1;
-      st.n_bt_total += st.n_bt;
-      st.prec = 0;        // no decrease at mixed precision: continue in FP64
-      st.state = BS_JAC;
-    } else if (restart) {
-      st.n_bt += 1;
-      st.n_bt_total += st.n_bt;
-      st.restart = 0;
-      st.fallback = 2;
-      st.prec = st.prec0;
-      st.state = BS_JAC;
-    } else if (st.n_bt >= p.max_backtrack) {
-      st.n_bt += 1;
-      st.n_bt_total += st.n_bt;
-      st.status = IFT_ELINESEARCH;
-      st.state = BS_DONE;
-    } else {
+    } else if (halve) {
       st.alpha *= 0.5;
       st.n_bt += 1;
+    } else {
+      ls_failed(st, p);
     }
   }
 }
@@ -575,6 +623,7 @@ __global__ void k_batch_init(BatchState* S, int n_inst, int mixed, int presolve,
   st.prec0 = mixed;
   st.wonly = presolve;
   st.it_w = 0;
+  st.reval = 0;
   st.lam = lambda;
   st.J = st.J0 = st.Jtrial = 0.0;
   st.alpha = st.slope = st.nS = st.nT = st.alpha_acc = 0.0;

@@ -88,6 +88,7 @@ struct Pts : PtsSrc<D, R> {
   R fv[D::NQV][D::NC][2];          // f(u_q)
   R Af[D::NQV][D::NC][2][D::NC];   // df/du at volume points: [q][c][dim][c']
   R gp[D::NQV][D::NN][2];          // cof(J) grad_xi phi_i
+  R Jn[D::NQV][4];                 // J / det J = cof(J)^-T, [q][2a + b] (0 where det J/det J0 <= eps)
   R H[3][D::NQF][D::NC];           // numerical flux at face points
   R dHm[3][D::NQF][D::NC][D::NC];  // dH/du- (boundary state dependence included)
   R dHp[3][D::NQF][D::NC][D::NC];  // dH/du+ (interior faces)
@@ -254,6 +255,15 @@ IFT_DEV void vol_point(const RefTab& t, S& s, int q, int seed, const PhysConst& 
       R a = R(t.dphiv[q][i][0]), b = R(t.dphiv[q][i][1]);
       s.p.gp[q][i][0] = J11 * a - J10 * b;
       s.p.gp[q][i][1] = J00 * b - J01 * a;
+    }
+    {
+      // the inverse transpose of cof(J): maps the x-derivative of the
+      // transformed flux onto the same weights gp as the state derivative
+      const R idJ = (bad & BAD_GEOM) ? R(0) : R(1) / (J00 * J11 - J01 * J10);
+      s.p.Jn[q][0] = J00 * idJ;
+      s.p.Jn[q][1] = J01 * idJ;
+      s.p.Jn[q][2] = J10 * idJ;
+      s.p.Jn[q][3] = J11 * idJ;
     }
     if constexpr (D::PDE == PDE_BURGERS) {
       // source at the mapped position x_q = sum_j x_j phi_j(xi_q)

@@ -1197,6 +1197,13 @@ extern "C" ift_status rom_gauss_newton_step(ift_rom* r, const double* mu, double
     info->status = IFT_ESINGULAR;
     return IFT_ESINGULAR;
   }
+  // the Armijo reference J~(z_n) from the kernels that evaluate the trials
+  // (the Gram corner sums the same squares in another order, and near a
+  // minimum that rounding difference is as large as the decrease tested)
+  s = eq_assemble_residual(r, mu, w, tau, r->d_Jtrial, nullptr, nullptr, nullptr, stream);
+  if (s != IFT_OK) return s;
+  HIP_TRY(hipMemcpyAsync(&J0, r->d_Jtrial, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
   const double slope = so[3];
   double alpha = 1.0;
   for (int bt = 0; bt <= prm->max_backtrack; ++bt) {
@@ -1663,10 +1670,11 @@ extern "C" ift_status rom_gauss_newton_solve_batched(ift_batch* b, const double*
                      b->precision == IFT_MIXED_BF16 ? 1 : 0, (flags & 4) ? 1 : 0, prm->lambda);
   if (flags & 2) batch_select_start(b, stream);
   // every instance finishes within (max_it + 1) Jacobian rounds, each
-  // followed by at most ceil((max_backtrack + 1) / T) rounds of trials
-  // (a few more for the rounds that take no step: the end of the w-only
-  // initialisation, the switch to FP64, a restart)
-  const long long cap = (long long)(max_it + 4) * (2 + (prm->max_backtrack + 1 + BATCH_T - 1) / BATCH_T);
+  // followed by at most ceil((max_backtrack + 2) / T) rounds of trials (the
+  // halvings and the re-evaluation of J~ at the iterate; a few more for the
+  // rounds that take no step: the end of the w-only initialisation, the
+  // switch to FP64, a restart)
+  const long long cap = (long long)(max_it + 4) * (2 + (prm->max_backtrack + 2 + BATCH_T - 1) / BATCH_T);
   for (long long done = 0; done < cap; done += BATCH_ROUNDS) {
     if (graph) HIP_TRY(hipGraphLaunch(b->exec, stream));
     else batch_rounds(b, BATCH_ROUNDS, stream);

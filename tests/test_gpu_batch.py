@@ -348,19 +348,27 @@ def test_plain_start_matches_oracle(setup):
         assert rel(w.cpu().numpy(), c["w0"]) < 1e-13 and np.all(tau.cpu().numpy() == 0.0)
 
 
+# space-time Burgers instances whose last steps ask for decreases below one
+# ulp of the objective (see the test below)
+SOURCE_BELOW_FLOOR = (3, 6)
+
+
 def test_batched_solve_with_source_matches_oracle():
     """The space-time Burgers problem with its source (P1, 8x8 cells of
     (0, 100) x (0, 50), n = m = 4, 40 EQ elements): eight instances at their
     own mu = (a, b) solved together from the plain start, against the
-    oracle's Levenberg-Marquardt iteration from the same start.  The
-    synthetic bases leave objectives of 1e3..1e5 (no basis state solves the
-    problem), and there a decrease of the objective below its rounding
-    (about 1e-16 J) decides the line search: the gradient norms at which
-    that happens reach a few 1e-4 (the device compares objectives summed in
-    two different orders, the oracle one), so both run to 1e-3.  Both stop
-    near the same minimiser: same step count up to one (the oracle solves
-    each step by lstsq, the device by Cholesky), the objective within 1e-9
-    and the iterate within 1e-4."""
+    oracle's Levenberg-Marquardt iteration from the same start, both to
+    tol 1e-4.  The synthetic bases leave objectives of 1e3..1e5 (no basis
+    state solves the problem).  Every Armijo test on the device compares
+    objectives summed by the same kernels in the same order, so where the
+    decrease asked for is many ulps of the objective the device takes the
+    oracle's steps: same status and step count, the objective within 1e-9
+    and the iterate within 1e-5.  Instances 3 and 6 (objectives 7.1e4 and
+    3.9e4) end below that floor: in the oracle's own last ten steps
+    -c1 alpha g.dz is under one ulp of J and steps are accepted on exact
+    ties of J, which no other summation reproduces; for them both sides
+    must only reach the same minimiser (objective within 1e-10, iterate
+    within 1e-6)."""
     import torch
     from oracle import eq as oeq
     from oracle import gn as ogn
@@ -377,7 +385,7 @@ def test_batched_solve_with_source_matches_oracle():
     b.plain_start(mu, z)
     info = b.info_buffer(dev)
     _say("batched solve, space-time Burgers with source")
-    b.solve(mu, z, info, lam=LAM, max_it=60, tol=1e-3)
+    b.solve(mu, z, info, lam=LAM, max_it=60, tol=1e-4)
     torch.cuda.synchronize()
     out = b.info_array(info)
     zb = b.unpack(z)
@@ -386,14 +394,65 @@ def test_batched_solve_with_source_matches_oracle():
     orom = oeq.ROM(ors.Problem(wl), wl.Phi, wl.Psi, wl.eq_elem, wl.eq_rho)
     for i in range(P):
         w0, t0 = oeq.plain_start(wl, wl.mus[i])
-        w, tau, oinfo = ogn.lm_solve(orom, wl.mus[i], w0, t0, LAM, 1e-3, 60)
+        w, tau, oinfo = ogn.lm_solve(orom, wl.mus[i], w0, t0, LAM, 1e-4, 60)
         Jo = orom.jacobian(wl.mus[i], w, tau)["J"]
         _say(f"  instance {i}: batched status {out['status'][i]} steps {out['iterations'][i]} J {out['J_new'][i]:.12e}; "
-             f"oracle {oinfo['status']} steps {oinfo['iterations']} J {Jo:.12e}")
+             f"oracle {oinfo['status']} steps {oinfo['iterations']} J {Jo:.12e} rel z {rel(zb[i], np.r_[w, tau]):.2e}")
+        if i in SOURCE_BELOW_FLOOR:
+            assert abs(out["J_new"][i] - Jo) <= 1e-10 * Jo
+            assert rel(zb[i], np.r_[w, tau]) < 1e-6
+            continue
         assert oinfo["status"] == "converged" and out["converged"][i] == 1
-        assert abs(int(out["iterations"][i]) - oinfo["iterations"]) <= 1
+        assert int(out["iterations"][i]) == oinfo["iterations"]
         assert abs(out["J_new"][i] - Jo) <= 1e-9 * Jo
-        assert rel(zb[i], np.r_[w, tau]) < 1e-4
+        assert rel(zb[i], np.r_[w, tau]) < 1e-5
+
+
+# instances of the module's batch that converge from the plain start within
+# 50 steps (the angle-0 instance starts converged; the 7-element EQ set and
+# the n = 20, m = 5 instance need 50 and more steps)
+EULER_SOLVE_INSTANCES = (0, 1, 2, 5)
+
+
+def test_batched_euler_solves_match_oracle(setup):
+    """Batched solves of the P2 Euler instances (16x8 cells; n, m, EQ sets
+    and inflow angles differ per instance) from the plain start to
+    |S~|, |T~| <= 1e-8, against the oracle's Levenberg-Marquardt iteration
+    from the same start (normal equations, Armijo backtracking): the same
+    status and step count, the objective within 1e-9 and the state within
+    1e-6 (the bound of the mixed-precision solves; two iterates that both
+    meet the tolerance may differ by |H^-1| 2 tol, and here the two follow
+    the same steps, so they differ by rounding)."""
+    import torch
+    from oracle import eq as oeq
+    from oracle import gn as ogn
+    from oracle import residual as ors
+    from paper_2305_15661_amd import ift
+    S = setup
+    insts = [S["insts"][i] for i in EULER_SOLVE_INSTANCES]
+    b = ift.Batch([c["rom"] for c in insts])
+    mu = torch.tensor(np.stack([c["mu"] for c in insts]), dtype=torch.float64, device=S["dev"])
+    z = torch.zeros(b.nz, dtype=torch.float64, device=S["dev"])
+    b.plain_start(mu, z)
+    info = b.info_buffer(S["dev"])
+    _say("batched Euler solves to 1e-8")
+    b.solve(mu, z, info, lam=LAM, max_it=50, tol=1e-8)
+    torch.cuda.synchronize()
+    out = b.info_array(info)
+    zb = b.unpack(z)
+    prob = ors.Problem(S["base"])
+    for i, c in enumerate(insts):
+        orom = oeq.ROM(prob, c["Phi"], c["Psi"], c["el"], c["rho"])
+        w, tau, oinfo = ogn.lm_solve(orom, c["mu"], c["w0"], c["tau0"], LAM, 1e-8, 50)
+        Jo = orom.jacobian(c["mu"], w, tau)["J"]
+        zo = np.r_[w, tau]
+        _say(f"  instance {EULER_SOLVE_INSTANCES[i]} (n={c['n']}, m={c['m']}, n_s={c['el'].size}): batched status "
+             f"{out['status'][i]} steps {out['iterations'][i]} J {out['J_new'][i]:.12e}; oracle {oinfo['status']} "
+             f"steps {oinfo['iterations']} J {Jo:.12e}; rel z {rel(zb[i], zo):.2e}")
+        assert oinfo["status"] == "converged" and out["converged"][i] == 1
+        assert int(out["iterations"][i]) == oinfo["iterations"]
+        assert abs(out["J_new"][i] - Jo) <= 1e-9 * Jo
+        assert rel(zb[i], zo) < 1e-6
 
 
 def test_full_size_batch_samples():
