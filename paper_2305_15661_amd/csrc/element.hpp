@@ -222,6 +222,21 @@ IFT_DEV R eta_reference(const RefTab& t, const R* X) {
   return R(4) * a;
 }
 
+// J / det J at volume point q, the inverse transpose of cof(J): it maps the
+// mapping derivative of the transformed flux onto the weights gp of the
+// state derivative (zero at an invalid point).  Only the point data of the
+// Jacobian path carry it.
+template <class D, class R>
+IFT_DEV void store_jn(Pts<D, R>& p, int q, R J00, R J01, R J10, R J11, bool invalid) {
+  const R idJ = invalid ? R(0) : R(1) / (J00 * J11 - J01 * J10);
+  p.Jn[q][0] = J00 * idJ;
+  p.Jn[q][1] = J01 * idJ;
+  p.Jn[q][2] = J10 * idJ;
+  p.Jn[q][3] = J11 * idJ;
+}
+template <class D, class R, class P>
+IFT_DEV void store_jn(P&, int, R, R, R, R, bool) {}
+
 // Volume point q: state, flux, cof(J) grad phi; seed = component seeded in
 // tangent mode (-1: none).  Returns the flux Jacobian column in Af.
 template <class D, class T, class R, class S>
@@ -256,15 +271,7 @@ IFT_DEV void vol_point(const RefTab& t, S& s, int q, int seed, const PhysConst& 
       s.p.gp[q][i][0] = J11 * a - J10 * b;
       s.p.gp[q][i][1] = J00 * b - J01 * a;
     }
-    {
-      // the inverse transpose of cof(J): maps the x-derivative of the
-      // transformed flux onto the same weights gp as the state derivative
-      const R idJ = (bad & BAD_GEOM) ? R(0) : R(1) / (J00 * J11 - J01 * J10);
-      s.p.Jn[q][0] = J00 * idJ;
-      s.p.Jn[q][1] = J01 * idJ;
-      s.p.Jn[q][2] = J10 * idJ;
-      s.p.Jn[q][3] = J11 * idJ;
-    }
+    store_jn<D, R>(s.p, q, J00, J01, J10, J11, (bad & BAD_GEOM) != 0);
     if constexpr (D::PDE == PDE_BURGERS) {
       // source at the mapped position x_q = sum_j x_j phi_j(xi_q)
       R xq = R(0);
