@@ -68,7 +68,9 @@ typedef enum {
   IFT_ENONPHYS = -5,    /* non-physical state at the evaluation point      */
   IFT_ESINGULAR = -6,   /* Gauss-Newton matrix not positive definite        */
   IFT_ELINESEARCH = -7, /* no sufficient decrease within max_backtrack      */
-  IFT_ENOTCONV = -8     /* iteration limit reached                          */
+  IFT_ENOTCONV = -8,    /* iteration limit reached                          */
+  IFT_ESCRATCH = -9     /* the workspace exceeds the fixed scratch of the
+                           no-allocation entry point                        */
 } ift_status;
 
 typedef enum { IFT_BURGERS2D = 0, IFT_EULER2D = 1 } ift_pde;
@@ -203,6 +205,24 @@ ift_status eq_assemble_residual(ift_rom* rom, const double* mu, const double* w,
 ift_status eq_assemble_jacobian(ift_rom* rom, const double* mu, const double* w, const double* tau,
                                 double* Jobj, double* g, double* H, double* Jt, int* n_bad,
                                 hipStream_t stream);
+
+/* eq_assemble_jacobian for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results (Jobj, g, H, n_bad as
+ * above; no Jt), with the workspace (point data, block partials, flag
+ * counts; eq_noalloc_scratch_bytes) in one static device array of
+ * IFT_NOALLOC_SCRATCH_BYTES that each device holds from the library's load
+ * until the process ends.  The call allocates nothing; mu is HOST [2], w, tau,
+ * Jobj, g, H, n_bad are DEVICE.  Every call on a device shares its array:
+ * calls that overlap on one device (other streams, other threads) race and
+ * must be serialised by the caller.  IFT_ESCRATCH when the ROM's workspace
+ * exceeds the array (about 5,000 sampled elements of a P2 Euler ROM),
+ * IFT_EINVAL on null outputs or a ROM whose D + 1 exceeds 48. */
+#define IFT_NOALLOC_SCRATCH_BYTES (32u << 20)
+ift_status eq_assemble_jacobian_noalloc(ift_rom* rom, const double* mu, const double* w, const double* tau,
+                                        double* Jobj, double* g, double* H, int* n_bad, hipStream_t stream);
+/* Bytes of that workspace for this ROM (0 for a NULL handle). */
+size_t eq_noalloc_scratch_bytes(const ift_rom* rom);
 
 /* The elemental reduced residuals of eq. (ift-eqp-res0), the data of the
  * EQ-weight training program eq. (eqp-lp)-(eqp-con): for every sampled

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -972,26 +973,41 @@ static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, int n
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
 }
 
+// Device workspace of one fused Jacobian assembly: the block partials, their
+// flag counts and the OR of the invalid flags (the point data go in EqArgs).
+struct FusedWork {
+  double* part;
+  int* part_bad;
+  int* flag_or;
+  double* Jobj;   // objective when the caller passes none
+};
+
+static FusedWork rom_fused_work(ift_rom* r) { return {r->d_fpart, r->d_fbad, r->d_flag_or, r->d_J}; }
+
 // Jacobian path through the fused assembly + Gram; rows: also leave the
 // rows of J~ and F~ in the workspace (d_Jt, d_Ft).
 static ift_status eq_jacobian_fused(ift_rom* r, const EqArgs& a, int n_pts, double* H, double* g, double* Jobj,
-                                    int* n_bad, bool rows, hipStream_t stream) {
+                                    int* n_bad, bool rows, hipStream_t stream, const FusedWork& w) {
   const FusedLayout L = fused_layout(r, n_pts);
   FusedArgs fa;
   fa.E = L.E;
   fa.nblk = L.nblk;
-  fa.part = r->d_fpart;
-  fa.part_bad = r->d_fbad;
+  fa.part = w.part;
+  fa.part_bad = w.part_bad;
   fa.rows = rows ? 1 : 0;
   ift_status s = dispatch_eq(r, a, true, n_pts, stream, &fa);
   if (s != IFT_OK) return s;
   const int D1 = r->D + 1;
   const int nbe = (D1 * (D1 + 1) / 2 + GF_ENT - 1) / GF_ENT;
   ProfScope ps(IFT_PROF_GRAM, stream, true);
-  hipLaunchKernelGGL(k_fused_final, dim3(nbe + 1, n_pts), dim3(256), 0, stream, (const double*)r->d_fpart,
-                     (const int*)r->d_fbad, L.nblk, r->fused_nt, r->D, H, g, Jobj ? Jobj : r->d_J, n_bad,
-                     r->d_flag_or);
+  hipLaunchKernelGGL(k_fused_final, dim3(nbe + 1, n_pts), dim3(256), 0, stream, (const double*)w.part,
+                     (const int*)w.part_bad, L.nblk, r->fused_nt, r->D, H, g, Jobj ? Jobj : w.Jobj, n_bad, w.flag_or);
   return hipGetLastError() == hipSuccess ? IFT_OK : IFT_EDEVICE;
+}
+
+static ift_status eq_jacobian_fused(ift_rom* r, const EqArgs& a, int n_pts, double* H, double* g, double* Jobj,
+                                    int* n_bad, bool rows, hipStream_t stream) {
+  return eq_jacobian_fused(r, a, n_pts, H, g, Jobj, n_bad, rows, stream, rom_fused_work(r));
 }
 
 extern "C" ift_status eq_assemble_residual(ift_rom* r, const double* mu, const double* w, const double* tau,
@@ -1053,6 +1069,77 @@ extern "C" ift_status eq_assemble_jacobian(ift_rom* r, const double* mu, const d
   if (s != IFT_OK) return s;
   if (Jt) HIP_TRY(hipMemcpyAsync(Jt, r->d_Jt, (size_t)r->nrows * r->D * sizeof(double), hipMemcpyDeviceToDevice, stream));
   return IFT_OK;
+}
+
+// ------------------------------------------- assembly without allocation
+// eq_assemble_jacobian_noalloc keeps its workspace (point data, block
+// partials, flag counts) in one static device array of fixed size instead of
+// the ROM's lazily allocated buffers.  Each device holds its own copy of the
+// array; its address on a device is taken once, with that device current, on
+// the first call there, and only that address is ever handed to kernels.
+// Every call on a device shares that device's array: calls that overlap on
+// one device race.  Nothing in it needs clearing: every byte a call reads was
+// written earlier in the same call.
+static __device__ __align__(256) unsigned char scratch[IFT_NOALLOC_SCRATCH_BYTES];
+
+static constexpr int SCRATCH_MAX_DEV = 64;
+static void* g_scratch_ptr[SCRATCH_MAX_DEV] = {};
+static std::mutex g_scratch_mu;
+
+static ift_status scratch_on_device(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEV) return IFT_EDEVICE;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return IFT_EDEVICE;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return IFT_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+extern "C" size_t eq_noalloc_scratch_bytes(const ift_rom* r) {
+  if (!r || r->fused_nt < 1) return 0;
+  const FusedLayout L = fused_layout(r, 1);
+  const size_t nh = (size_t)r->fused_nt * (r->fused_nt + 1) / 2;
+  return align256((size_t)r->n_s * pts_bytes(r->prob)) + align256((size_t)L.nblk * nh * 256 * sizeof(double)) +
+         align256((size_t)L.nblk * 2 * sizeof(int)) + align256(sizeof(int)) + align256(sizeof(double));
+}
+
+extern "C" ift_status eq_assemble_jacobian_noalloc(ift_rom* r, const double* mu, const double* w, const double* tau,
+                                                   double* Jobj, double* g, double* H, int* n_bad,
+                                                   hipStream_t stream) {
+  if (!r || !w || (r->m > 0 && !tau) || !Jobj || !g || !H || !finite_mu(r->prob, mu) || r->fused_nt < 1)
+    return IFT_EINVAL;
+  if (eq_noalloc_scratch_bytes(r) > (size_t)IFT_NOALLOC_SCRATCH_BYTES) return IFT_ESCRATCH;
+  void* base = nullptr;
+  ift_status s = scratch_on_device(&base);
+  if (s != IFT_OK) return s;
+  const FusedLayout L = fused_layout(r, 1);
+  const size_t nh = (size_t)r->fused_nt * (r->fused_nt + 1) / 2;
+  unsigned char* p = static_cast<unsigned char*>(base);
+  EqArgs a = eq_args(r, mu, w, tau);
+  a.pts = p;
+  p += align256((size_t)r->n_s * pts_bytes(r->prob));
+  FusedWork fw;
+  fw.part = reinterpret_cast<double*>(p);
+  p += align256((size_t)L.nblk * nh * 256 * sizeof(double));
+  fw.part_bad = reinterpret_cast<int*>(p);
+  p += align256((size_t)L.nblk * 2 * sizeof(int));
+  fw.flag_or = reinterpret_cast<int*>(p);
+  p += align256(sizeof(int));
+  fw.Jobj = reinterpret_cast<double*>(p);
+  // the Jacobian-path kernels read only the point data, the gathered
+  // operands and the point bases; the row outputs stay off
+  a.Jt = nullptr;
+  a.Ft = nullptr;
+  a.Jpart = nullptr;
+  a.flags = nullptr;
+  return eq_jacobian_fused(r, a, 1, H, g, Jobj, n_bad, false, stream, fw);
 }
 
 extern "C" ift_status eq_element_contributions(ift_rom* r, const double* mu, const double* w, const double* tau,

@@ -19,8 +19,11 @@ LIB_PATH = os.path.join(_PKG, "libift.so")
 
 IFT_OK, IFT_EINVAL, IFT_ENOMEM, IFT_EDEVICE = 0, -1, -2, -3
 IFT_EBADMESH, IFT_ENONPHYS, IFT_ESINGULAR, IFT_ELINESEARCH, IFT_ENOTCONV = -4, -5, -6, -7, -8
+IFT_ESCRATCH = -9
+NOALLOC_SCRATCH_BYTES = 32 << 20   # IFT_NOALLOC_SCRATCH_BYTES of include/ift.h
 STATUS_NAMES = {0: "IFT_OK", -1: "IFT_EINVAL", -2: "IFT_ENOMEM", -3: "IFT_EDEVICE", -4: "IFT_EBADMESH",
-                -5: "IFT_ENONPHYS", -6: "IFT_ESINGULAR", -7: "IFT_ELINESEARCH", -8: "IFT_ENOTCONV"}
+                -5: "IFT_ENONPHYS", -6: "IFT_ESINGULAR", -7: "IFT_ELINESEARCH", -8: "IFT_ENOTCONV",
+                -9: "IFT_ESCRATCH"}
 PDE = {"burgers": 0, "euler": 1}
 PRECISION = {"fp64": 0, "fp32": 1, "mixed": 2}
 
@@ -75,6 +78,8 @@ EXPORTS = {
     "ift_rom_get_gathers": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "eq_assemble_residual": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P]),
     "eq_assemble_jacobian": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "eq_assemble_jacobian_noalloc": (ctypes.c_int, [_P, _D, _P, _P, _P, _P, _P, _P, _P]),
+    "eq_noalloc_scratch_bytes": (ctypes.c_size_t, [_P]),
     "rom_gauss_newton_step": (ctypes.c_int, [_P, _D, _P, _P, ctypes.POINTER(GNParams), ctypes.POINTER(GNInfo), _P]),
     "ift_rom_reserve": (ctypes.c_int, [_P, ctypes.c_int]),
     "eq_assemble_residual_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
@@ -285,6 +290,20 @@ class ROM:
                                         _ptr(Jt, self.nrows * self.D, f64), _ptr(n_bad, 1, torch.int32),
                                         _stream(stream))
         _check(st, "eq_assemble_jacobian")
+
+    def eq_assemble_jacobian_noalloc(self, mu, w, tau, Jobj, g, H, n_bad=None, stream=None):
+        """eq_assemble_jacobian_noalloc: the same outputs (no Jt) with the
+        library's static device scratch instead of allocated workspaces."""
+        import torch
+        f64 = torch.float64
+        st = lib().eq_assemble_jacobian_noalloc(self.handle, _mu(mu), _ptr(w, self.n, f64), _ptr(tau, self.m, f64),
+                                                _ptr(Jobj, 1, f64), _ptr(g, self.D, f64),
+                                                _ptr(H, self.D * self.D, f64), _ptr(n_bad, 1, torch.int32),
+                                                _stream(stream))
+        _check(st, "eq_assemble_jacobian_noalloc")
+
+    def noalloc_scratch_bytes(self):
+        return int(lib().eq_noalloc_scratch_bytes(self.handle))
 
     def element_contributions(self, mu, w, tau, C, stream=None):
         """eq_element_contributions: C [n_s, n+m] device tensor of the

@@ -22,7 +22,7 @@ def _lib():
 def test_every_declared_symbol_is_exported():
     ift, L = _lib()
     hdr = open(os.path.join(ROOT, "include", "ift.h")).read()
-    names = set(re.findall(r"^(?:ift_status|void)\s+(\w+)\s*\(", hdr, flags=re.M))
+    names = set(re.findall(r"^(?:ift_status|void|size_t)\s+(\w+)\s*\(", hdr, flags=re.M))
     assert names == set(ift.EXPORTS), names ^ set(ift.EXPORTS)
     for n in names:
         assert hasattr(L, n)
