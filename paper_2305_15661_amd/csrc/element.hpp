@@ -88,7 +88,6 @@ struct Pts : PtsSrc<D, R> {
   R fv[D::NQV][D::NC][2];          // f(u_q)
   R Af[D::NQV][D::NC][2][D::NC];   // df/du at volume points: [q][c][dim][c']
   R gp[D::NQV][D::NN][2];          // cof(J) grad_xi phi_i
-  R Jn[D::NQV][4];                 // J / det J = cof(J)^-T, [q][2a + b] (0 where det J/det J0 <= eps)
   R H[3][D::NQF][D::NC];           // numerical flux at face points
   R dHm[3][D::NQF][D::NC][D::NC];  // dH/du- (boundary state dependence included)
   R dHp[3][D::NQF][D::NC][D::NC];  // dH/du+ (interior faces)
@@ -222,21 +221,6 @@ IFT_DEV R eta_reference(const RefTab& t, const R* X) {
   return R(4) * a;
 }
 
-// J / det J at volume point q, the inverse transpose of cof(J): it maps the
-// mapping derivative of the transformed flux onto the weights gp of the
-// state derivative (zero at an invalid point).  Only the point data of the
-// Jacobian path carry it.
-template <class D, class R>
-IFT_DEV void store_jn(Pts<D, R>& p, int q, R J00, R J01, R J10, R J11, bool invalid) {
-  const R idJ = invalid ? R(0) : R(1) / (J00 * J11 - J01 * J10);
-  p.Jn[q][0] = J00 * idJ;
-  p.Jn[q][1] = J01 * idJ;
-  p.Jn[q][2] = J10 * idJ;
-  p.Jn[q][3] = J11 * idJ;
-}
-template <class D, class R, class P>
-IFT_DEV void store_jn(P&, int, R, R, R, R, bool) {}
-
 // Volume point q: state, flux, cof(J) grad phi; seed = component seeded in
 // tangent mode (-1: none).  Returns the flux Jacobian column in Af.
 template <class D, class T, class R, class S>
@@ -271,7 +255,6 @@ IFT_DEV void vol_point(const RefTab& t, S& s, int q, int seed, const PhysConst& 
       s.p.gp[q][i][0] = J11 * a - J10 * b;
       s.p.gp[q][i][1] = J00 * b - J01 * a;
     }
-    store_jn<D, R>(s.p, q, J00, J01, J10, J11, (bad & BAD_GEOM) != 0);
     if constexpr (D::PDE == PDE_BURGERS) {
       // source at the mapped position x_q = sum_j x_j phi_j(xi_q)
       R xq = R(0);
