@@ -72,31 +72,187 @@ TRAFFIC_KIB = {"points": (4512.0, 74017.0), "eq_jac": (45552.0, 3088.0), "gram":
 HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, budget_s: float):
-    """The oracle's EQ Jacobian assembly on the host (single thread)."""
-    from threadpoolctl import threadpool_limits
+def batch_work(bw, n_inst, mixed=False):
+    """Algorithmic bytes and flops of one batched Jacobian phase, summed over
+    the instances (n_s, n, m of each; nue = 24, nun = 36, nxe = 12):
+    bytes: the gathered operands Phi_e, Phi_e', Psi_e, X_e and rho/ids (FP64;
+    with mixed precision Phi in BF16 and Psi, X in FP32); projection flops
+    A^U 2*24*60*n + A^x 2*24*12*m; Gram flops H 2*24*D^2 + g 2*24*D."""
+    by = proj = gram = 0.0
+    for i in range(n_inst):
+        ns = bw.inst_elem[i].size
+        n, m = bw.pool_nm[bw.inst_pool[i]]
+        D = n + m
+        bphi, bpsi = (2, 4) if mixed else (8, 8)
+        by += ns * (bphi * 60 * n + bpsi * (12 * m + 12) + 24)
+        proj += ns * (2 * 24 * 60 * n + 2 * 24 * 12 * m)
+        gram += ns * (2 * 24 * D * D + 2 * 24 * D)
+    return by, proj, gram
 
+
+def batch_roofline(b, mu, z, by, proj, gram, reps, mixed=False):
+    """Per-kernel HIP-event times of the batched Jacobian phase (points,
+    projection + Gram, final sums) and their roofline fractions."""
+    import torch
+    from paper_2305_15661_amd import ift
+    dev = z.device
+    J = torch.zeros(b.n_inst, dtype=torch.float64, device=dev)
+    g = torch.zeros(b.nz, dtype=torch.float64, device=dev)
+    H = torch.zeros(b.nh, dtype=torch.float64, device=dev)
+    b.eq_assemble_jacobian(mu, z, J, g, H)
+    torch.cuda.synchronize()
+    ift.profile_enable(True)
+    ift.profile_reset()
+    for _ in range(reps):
+        b.eq_assemble_jacobian(mu, z, J, g, H)
+    torch.cuda.synchronize()
+    ift.profile_enable(False)
+    t = {k: ift.profile_read(k)[1] * 1e-3 / reps for k in ("points", "eq_jac", "gram")}
+    pts_gbs = by / t["points"] / 1e9
+    proj_peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
+    out = {"kernels_us": {k: v * 1e6 for k, v in t.items()},
+           "phase_us": sum(t.values()) * 1e6,
+           "algorithmic_bytes": by, "projection_flops": proj, "gram_flops": gram,
+           "points": {"bound": "hbm", "achieved": pts_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": pts_gbs / PEAK_HBM_GBS},
+           "projection": {"bound": "mfma", "unit": "TFLOP/s",
+                          "projection_achieved": proj / t["eq_jac"] / 1e12, "projection_peak": proj_peak,
+                          "projection_frac": proj / t["eq_jac"] / 1e12 / proj_peak,
+                          "gram_achieved": gram / t["eq_jac"] / 1e12, "gram_peak": PEAK_FP64_TFLOPS,
+                          "gram_frac": gram / t["eq_jac"] / 1e12 / PEAK_FP64_TFLOPS},
+           "phase_hbm_frac": by / sum(t.values()) / 1e9 / PEAK_HBM_GBS}
+    if not mixed:
+        tf = (proj + gram) / t["eq_jac"] / 1e12
+        out["projection"].update({"achieved": tf, "peak": PEAK_FP64_TFLOPS, "frac": tf / PEAK_FP64_TFLOPS})
+    return out
+
+
+def host_info():
+    """The host the oracle runs on: core count, CPU model, BLAS and versions."""
+    import platform
+
+    import scipy
+    from threadpoolctl import threadpool_info
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_count": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "machine": platform.machine(), "numpy": np.__version__, "scipy": scipy.__version__,
+            "blas": [{"api": d.get("internal_api"), "threads": d.get("num_threads"), "version": d.get("version")}
+                     for d in threadpool_info()]}
+
+
+def _timed(fn, budget_s: float, min_runs: int = 1, max_runs: int = 5):
+    """Median wall time of fn() over up to max_runs runs after one warm-up,
+    stopping once budget_s is spent (at least min_runs runs)."""
+    fn()
+    ts = []
+    t_all = time.perf_counter()
+    while len(ts) < max_runs and (len(ts) < min_runs or time.perf_counter() - t_all < budget_s):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts)), len(ts)
+
+
+def cpu_baseline(wl, budget_s: float, full: bool = False):
+    """The oracle (plain FP64 NumPy/SciPy, vectorised over elements, not tuned)
+    on the host cores, with one BLAS thread and with the host's default
+    thread count: the C1 EQ Jacobian assembly (the headline unit), a sample
+    of the full-order assembly, and the C0 Gauss-Newton solve; with full=True
+    also a C1 solve and batched-workload instances solved one by one."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import synth
     from oracle import eq as oeq
+    from oracle import gn as ogn
     from oracle import residual as ors
-    with threadpool_limits(1):
-        orom = oeq.ROM(ors.Problem(wl), wl.Phi, wl.Psi, wl.eq_elem, wl.eq_rho)
-        orom.jacobian(wl.mus[0], wl.w_eval[0], wl.tau_eval[0])   # warm-up
-        t0 = time.perf_counter()
-        calls = 0
-        while True:
-            k = calls % wl.mus.shape[0]
-            orom.jacobian(wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
-            calls += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-        dt = time.perf_counter() - t0
-    return {"value": calls * wl.n_s / dt, "unit": "element-evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{calls} oracle eq_assemble_jacobian calls x {wl.n_s} EQ elements "
-                      f"(same 16384-element Euler P2 workload), {dt:.1f} s, one thread"}
+    prob = ors.Problem(wl)
+    orom = oeq.ROM(prob, wl.Phi, wl.Psi, wl.eq_elem, wl.eq_rho)
+    wl0 = synth.tiny_burgers()
+    orom0 = oeq.ROM(ors.Problem(wl0), wl0.Phi, wl0.Psi, wl0.eq_elem, wl0.eq_rho)
+    w00, t00 = oeq.plain_start(wl0, wl0.mus[0])
+    U = wl.Phi @ wl.w_eval[0]
+    x = wl.X + wl.Psi @ wl.tau_eval[0]
+    chunk = np.arange(1024)
+    Ue, Une, xe = prob.gather_state(chunk, U, x)
+    runs = {}
+    for label, limit in (("1_thread", 1), ("default_threads", None)):
+        with threadpool_limits(limit):
+            threads = max([d.get("num_threads") or 1 for d in threadpool_info()] or [1])
+            k = [0]
+
+            def jac():
+                j = k[0] % wl.mus.shape[0]
+                k[0] += 1
+                orom.jacobian(wl.mus[j], wl.w_eval[j], wl.tau_eval[j])
+            t_jac, n_jac = _timed(jac, budget_s / 2, min_runs=3, max_runs=50)
+            t_hdm, n_hdm = _timed(lambda: prob.evaluate(chunk, Ue, Une, xe, wl.mus[0], True), budget_s / 8, 1, 3)
+            t_c0, n_c0 = _timed(lambda: ogn.lm_solve(orom0, wl0.mus[0], w00, t00, 0.0, 1e-8, 20), budget_s / 8, 5, 5)
+            r = {"threads": threads,
+                 "eq_jacobian_c1": {"element_evals_per_s": wl.n_s / t_jac, "ms_per_call": t_jac * 1e3,
+                                    "runs": n_jac, "statistic": "median"},
+                 "hdm_assemble_c1_sample": {"elements": int(chunk.size), "element_evals_per_s": chunk.size / t_hdm,
+                                            "seconds_per_call_full_mesh_est": t_hdm * wl.mesh.n_elem / chunk.size,
+                                            "runs": n_hdm},
+                 "gn_solve_c0": {"ms_per_solve": t_c0 * 1e3, "solves_per_s": 1.0 / t_c0, "runs": n_c0,
+                                 "iterations": 20}}
+            if full:
+                t_c1, _ = _timed(lambda: ogn.lm_solve(orom, wl.mus[0], wl.w_eval[0], wl.tau_eval[0], 0.0, 1e-8, 60),
+                                 0.0, 1, 1)
+                r["gn_solve_c1"] = {"seconds_per_solve": t_c1, "solves_per_s": 1.0 / t_c1, "runs": 1}
+                if limit == 1:
+                    r["batched_loop"] = cpu_batched_loop(n=4)
+            runs[label] = r
+            log(f"cpu ({label}, {threads} threads): eq jacobian {wl.n_s / t_jac:.0f} evals/s, "
+                f"hdm sample {chunk.size / t_hdm:.0f} evals/s, C0 solve {t_c0 * 1e3:.0f} ms")
+    best = max(runs.values(), key=lambda r: r["eq_jacobian_c1"]["element_evals_per_s"])
+    return {"value": best["eq_jacobian_c1"]["element_evals_per_s"], "unit": "element-evals/s",
+            "cores": best["threads"], "kind": "oracle",
+            "sample": (f"oracle eq_assemble_jacobian on the same 16384-element Euler P2 workload (819 EQ elements, "
+                       f"median of {best['eq_jacobian_c1']['runs']} calls over the 16 evaluation points) with "
+                       f"{best['threads']} BLAS thread(s); also 1-thread and default-thread runs of a 1024-element "
+                       f"full-order sample and of the C0 Gauss-Newton solve"),
+            "host": host_info(), "runs": runs}
+
+
+def cpu_batched_loop(n: int):
+    """The oracle's Levenberg-Marquardt solves of the first n batched-workload
+    instances, one after the other (the count is stated, not extrapolated)."""
+    import dataclasses
+
+    import synth
+    from oracle import eq as oeq
+    from oracle import gn as ogn
+    from oracle import residual as ors
+    bw = synth.euler_batch(n_inst=max(n, 1))
+    prob = ors.Problem(bw.base)
+    t = time.perf_counter()
+    conv, its = 0, []
+    for i in range(n):
+        P, S = bw.pool[bw.inst_pool[i]]
+        wl = synth.with_eq(bw.base, bw.inst_elem[i], bw.inst_rho[i])
+        orom = oeq.ROM(prob, P, S, bw.inst_elem[i], bw.inst_rho[i])
+        w0, t0 = oeq.plain_start(dataclasses.replace(wl, Phi=P, Psi=S), bw.mus[i])
+        _, _, info = ogn.lm_solve(orom, bw.mus[i], w0, t0, BATCH_LAMBDA, 1e-8, BATCH_MAX_IT)
+        conv += info["status"] == "converged"
+        its.append(info["iterations"])
+    dt = time.perf_counter() - t
+    return {"instances": n, "converged": conv, "seconds": dt, "solves_per_s": conv / dt,
+            "mean_gn_iterations": float(np.mean(its))}
 
 
 BATCH_LAMBDA = 1e-10   # Levenberg-Marquardt weight on the mapping block
@@ -139,6 +295,11 @@ def batched_leg(n_inst: int, n_loop: int, dev):
         b.eq_assemble_jacobian(mu, z0, J, g, H)
     torch.cuda.synchronize()
     t_jac = (time.perf_counter() - t) / reps
+    by64, proj64, gram64 = batch_work(bw, n_inst)
+    roof2 = batch_roofline(b, mu, z0, by64, proj64, gram64, reps)
+    log(f"batched jacobian (FP64): points {roof2['kernels_us']['points']:.0f} us, projection + Gram "
+        f"{roof2['kernels_us']['eq_jac']:.0f} us ({roof2['projection']['frac']:.3f} of FP64), final "
+        f"{roof2['kernels_us']['gram']:.0f} us; phase {roof2['phase_hbm_frac']:.3f} of HBM")
     # solves (graph replay); the first call captures the graph
     info = b.info_buffer(dev)
     z = z0.clone()
@@ -159,6 +320,11 @@ def batched_leg(n_inst: int, n_loop: int, dev):
     romsm = [ift.ROM(prob, *pool[bw.inst_pool[i]], bw.inst_elem[i], bw.inst_rho[i], "mixed") for i in range(n_inst)]
     bm = ift.Batch(romsm)
     bm.autotune(mu, z0)
+    byb, projb, gramb = batch_work(bw, n_inst, mixed=True)
+    roof3 = batch_roofline(bm, mu, z0, byb, projb, gramb, reps, mixed=True)
+    log(f"batched jacobian (mixed): points {roof3['kernels_us']['points']:.0f} us, projection + Gram "
+        f"{roof3['kernels_us']['eq_jac']:.0f} us ({roof3['projection']['projection_frac']:.4f} of BF16, "
+        f"Gram {roof3['projection']['gram_frac']:.3f} of FP64); phase {roof3['phase_hbm_frac']:.3f} of HBM")
     infom = bm.info_buffer(dev)
     zm = z0.clone()
     bm.solve(mu, zm, infom, lam=BATCH_LAMBDA, max_it=BATCH_MAX_IT)
@@ -205,7 +371,7 @@ def batched_leg(n_inst: int, n_loop: int, dev):
              "mean_gn_iterations": float(om["iterations"].mean()),
              "mean_mixed_precision_iterations": float(om["mixed_iterations"].mean()),
              "speedup_vs_fp64_batch": (convm / t_mixed) / (conv / t_solve) if conv else None,
-             "error_vs_tight_fp64": acc}
+             "error_vs_tight_fp64": acc, "roofline_jacobian_phase": roof3}
     am = acc["mixed_tol_1e-8"] or {}
     af = acc["fp64_tol_1e-8"] or {}
     log(f"mixed: {convm} converged in {t_mixed:.3f} s ({convm / t_mixed:.1f} solves/s), "
@@ -294,12 +460,41 @@ def batched_leg(n_inst: int, n_loop: int, dev):
             "status_counts": {int(k): int(v) for k, v in zip(st, cnt)},
             "mean_gn_iterations": float(o["iterations"].mean()),
             "jacobian_evals_per_s": ns / t_jac, "jacobian_ms": t_jac * 1e3,
+            "roofline_jacobian_phase": roof2,
             "loop": {"instances": min(n_loop, n_inst), "converged": lconv, "seconds": t_loop,
                      "solves_per_s": loop_rate, "mean_gn_iterations": float(np.mean(lits))},
             "speedup_vs_loop": (conv / t_solve) / loop_rate if loop_rate > 0 else None,
             "with_w_only_initialisation": presolve,
             "greedy_indicator": greedy,
             "mixed_precision": mixed}
+
+
+def batch_jacobian_only(dev, n_inst: int, reps: int = 3):
+    """The batched Jacobian phase alone (FP64, then mixed precision) on the
+    batched workload at the plain start, each batch autotuned: what a
+    profiler run of the batched kernels needs."""
+    import torch
+    import synth
+    from paper_2305_15661_amd import ift
+    bw = synth.euler_batch(n_inst=n_inst)
+    prob = ift.Problem.from_workload(bw.base)
+    pool = [(torch.tensor(np.ascontiguousarray(P), device=dev), torch.tensor(np.ascontiguousarray(S), device=dev))
+            for P, S in bw.pool]
+    mu = torch.tensor(bw.mus, dtype=torch.float64, device=dev)
+    out = {"workload": f"{n_inst} instances of the batched P2 Euler workload, Jacobian phase at the plain start"}
+    for prec in ("fp64", "mixed"):
+        roms = [ift.ROM(prob, *pool[bw.inst_pool[i]], bw.inst_elem[i], bw.inst_rho[i],
+                        "mixed" if prec == "mixed" else "fp64") for i in range(n_inst)]
+        b = ift.Batch(roms)
+        z0 = torch.zeros(b.nz, dtype=torch.float64, device=dev)
+        b.plain_start(mu, z0)
+        E = b.autotune(mu, z0)
+        by, proj, gram = batch_work(bw, n_inst, mixed=prec == "mixed")
+        out[prec] = batch_roofline(b, mu, z0, by, proj, gram, reps, mixed=prec == "mixed")
+        out[prec]["elements_per_wave"] = E
+        log(f"{prec}: " + ", ".join(f"{k} {v:.0f} us" for k, v in out[prec]["kernels_us"].items()))
+        del b, roms
+    return out
 
 
 def warm_start_leg(dev, n_train: int = 4096, n_test: int = 1024, train_steps: int = 3000):
@@ -603,7 +798,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="the oracle also on a C1 solve and on batched instances one by one (minutes)")
+    ap.add_argument("--batch-jacobian-only", action="store_true",
+                    help="only the batched Jacobian phase (FP64 and mixed precision), for profilers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-solve", action="store_true", help="skip the solves/s leg")
     ap.add_argument("--no-hdm", action="store_true", help="skip the full-order leg")
@@ -638,6 +837,10 @@ def main():
 
     import synth
     from paper_2305_15661_amd import ift
+
+    if args.batch_jacobian_only:
+        print(json.dumps(_finite(batch_jacobian_only(dev, args.batch_inst)), allow_nan=False))
+        return
 
     t_setup = time.perf_counter()
     wl = synth.euler_p2()
@@ -804,7 +1007,7 @@ def main():
     # ------------------------------------------------------------ CPU leg
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.cpu_full)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.1f} evals/s")
     print(json.dumps(_finite(out), allow_nan=False))
 

@@ -131,8 +131,9 @@ struct ProfScope {
   hipStream_t st;
   hipEvent_t a = nullptr, b = nullptr;
   bool own_a = true;
-  ProfScope(int k, hipStream_t s, bool chain = false) : kind(k), st(s) {
-    if (!g_prof_on) return;
+  bool on;
+  ProfScope(int k, hipStream_t s, bool chain = false, bool enable = true) : kind(k), st(s), on(enable && g_prof_on) {
+    if (!on) return;
     if (chain && g_prof_tail && g_prof_tail_st == s) {
       a = g_prof_tail;
       own_a = false;
@@ -143,7 +144,7 @@ struct ProfScope {
     b = prof_event();
   }
   ~ProfScope() {
-    if (!g_prof_on || !a || !b) return;
+    if (!on || !a || !b) return;
     (void)hipEventRecord(b, st);
     g_prof_live.push_back({kind, a, b, own_a});
     g_prof_tail = b;
@@ -1515,6 +1516,7 @@ struct BatchLaunch {
   ift_batch* b;
   hipStream_t st;
   int phase;   // 0: Jacobian assembly of the JAC instances, 1: trial residuals of the SEARCH instances
+  bool prof = false;   // time the points, projection and final kernels separately (never under capture)
   template <class D, class R, int NT>
   void fused(const BatchLists& L, bool mixed) {
     if (!b->has_nt[NT]) return;
@@ -1536,12 +1538,16 @@ struct BatchLaunch {
     if (phase == 0) {
       hipLaunchKernelGGL(k_batch_compact, dim3(1), dim3(BC_THR), 0, st, (const BatchInst*)b->d_inst,
                          (const BatchState*)b->d_state, L, ni, (int)BS_JAC, want_prec, 1);
-      if constexpr (pair_layout<D>())
-        hipLaunchKernelGGL((k_points_batch2<D, R>), dim3(BATCH_GRID_PTS2), dim3(2 * NTHR_PTS), 0, st,
-                           (const BatchInst*)b->d_inst, L, ni);
-      else
-        hipLaunchKernelGGL((k_points_batch<D, R>), dim3(BATCH_GRID_PTS), dim3(NTHR_PTS), 0, st,
-                           (const BatchInst*)b->d_inst, L, ni);
+      {
+        ProfScope ps(IFT_PROF_POINTS, st, false, prof);
+        if constexpr (pair_layout<D>())
+          hipLaunchKernelGGL((k_points_batch2<D, R>), dim3(BATCH_GRID_PTS2), dim3(2 * NTHR_PTS), 0, st,
+                             (const BatchInst*)b->d_inst, L, ni);
+        else
+          hipLaunchKernelGGL((k_points_batch<D, R>), dim3(BATCH_GRID_PTS), dim3(NTHR_PTS), 0, st,
+                             (const BatchInst*)b->d_inst, L, ni);
+      }
+      ProfScope ps(IFT_PROF_EQ_JAC, st, true, prof);
       fused<D, R, 1>(L, mixed);
       fused<D, R, 2>(L, mixed);
       fused<D, R, 3>(L, mixed);
@@ -1566,16 +1572,19 @@ struct BatchLaunch {
     } else {
       group<D, double>(-1, false);
     }
-    if (phase == 0)
+    if (phase == 0) {
+      ProfScope ps(IFT_PROF_GRAM, st, true, prof);
       hipLaunchKernelGGL(k_final_batch, dim3(b->nbe_max + 1, ni), dim3(256), 0, st, (const BatchInst*)b->d_inst,
                          b->d_state);
-    else
+    } else
       hipLaunchKernelGGL(k_ls_batch, dim3(ni), dim3(256), 0, st, (const BatchInst*)b->d_inst, b->d_state,
                          (const BatchParams*)b->d_params);
   }
 };
 
-static void batch_phase(ift_batch* b, int phase, hipStream_t st) { with_disc(b->prob, BatchLaunch{b, st, phase}); }
+static void batch_phase(ift_batch* b, int phase, hipStream_t st, bool prof = false) {
+  with_disc(b->prob, BatchLaunch{b, st, phase, prof});
+}
 
 // `rounds` rounds of the solve: the Jacobian phase of the JAC instances,
 // their LM step (or stop), then BATCH_T line-search trials of the SEARCH
@@ -1622,10 +1631,7 @@ extern "C" ift_status eq_assemble_jacobian_batched(ift_batch* b, const double* m
   if (s != IFT_OK) return s;
   hipLaunchKernelGGL(k_batch_init, dim3((b->n_inst + 255) / 256), dim3(256), 0, stream, b->d_state, b->n_inst,
                      b->precision == IFT_MIXED_BF16 ? 1 : 0, 0, 0.0);
-  {
-    ProfScope ps(IFT_PROF_EQ_JAC, stream);
-    batch_phase(b, 0, stream);
-  }
+  batch_phase(b, 0, stream, true);
   HIP_TRY(hipGetLastError());
   const size_t Z = b->zoff[b->n_inst], HH = b->hoff[b->n_inst];
   HIP_TRY(hipMemcpyAsync(g, b->d_g, Z * sizeof(double), hipMemcpyDeviceToDevice, stream));

@@ -21,6 +21,31 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def rel_blocks(a, b, nblk):
+    """Largest per-block error of a against b, split into nblk equal blocks
+    (elements): |a_k - b_k| / (|b_k| + 1e-3 max_k |b_k|).  A block at least
+    1e-3 of the largest is checked relative to itself; smaller blocks (a
+    residual that cancels to rounding, a boundary block) against 1e-3 of the
+    largest block instead of the whole array's norm."""
+    a = np.asarray(a, dtype=np.float64).reshape(nblk, -1)
+    b = np.asarray(b, dtype=np.float64).reshape(nblk, -1)
+    nb = np.linalg.norm(b, axis=1)
+    floor = 1e-3 * nb.max() if nb.max() > 0 else 1.0
+    return float(np.max(np.linalg.norm(a - b, axis=1) / (nb + floor)))
+
+
+def gram_entry_err(H, g, Ho, go, Jo):
+    """Per-entry errors of the Gauss-Newton matrix and gradient, each on its
+    own scale: H = M^T M gives |H_ij| <= sqrt(H_ii H_jj), and g = M^T F
+    gives |g_i| <= sqrt(H_ii) |F| with |F|^2 = 2 J."""
+    d = np.sqrt(np.maximum(np.diag(Ho), 0.0))
+    sH = np.outer(d, d)
+    sg = d * np.sqrt(2.0 * Jo)
+    eH = np.abs(np.asarray(H) - Ho) / np.where(sH > 0, sH, 1.0)
+    eg = np.abs(np.asarray(g) - go) / np.where(sg > 0, sg, 1.0)
+    return float(eH.max()), float(eg.max())
+
+
 @pytest.fixture(scope="session")
 def tiny():
     import synth

@@ -13,7 +13,8 @@ same 2e-2.
 
 Solves: a mixed batch (mixed rounds until the gradient norms reach 1e-5,
 then FP64 refinement) must end within 1e-6 (relative, per instance) of the
-FP64 batch.  Two iterates that both meet |g| <= tol can differ by up to
+FP64 batch and of the oracle's Levenberg-Marquardt iteration (FP64 on the
+host) from the same start.  Two iterates that both meet |g| <= tol can differ by up to
 |H^-1| * 2 tol, and the mapping block of H is weakly curved here, so both
 solves run to tol = 1e-10 for this comparison.
 """
@@ -114,11 +115,17 @@ def test_mixed_batched_solve_within_1e6_of_fp64():
     rng = np.random.default_rng(77)
     shapes = [(20, 10, 60), (10, 5, 30), (30, 10, 90), (20, 5, 45), (30, 5, 20)]
     t = lambda a: torch.tensor(np.ascontiguousarray(a), device=dev)
+    from oracle import eq as oeq
+    from oracle import gn as ogn
+    from oracle import residual as ors
+    oprob = ors.Problem(base)
     roms = {"mixed": [], "fp64": []}
-    mus, starts = [], []
+    mus, starts, els, rhos = [], [], [], []
     for i, (n, m, ns) in enumerate(shapes):
         el = synth.eq_set_with_inflow(base.mesh, ns, rng)
         rho = rng.lognormal(0.0, 0.5, size=el.size)
+        els.append(el)
+        rhos.append(rho)
         mu = np.array([2.0 + 0.2 * i, -4.0 + 2.0 * i])
         for p in roms:
             roms[p].append(ift.ROM(prob, t(base.Phi[:, :n]), t(base.Psi[:, :m]), el, rho, p))
@@ -150,7 +157,14 @@ def test_mixed_batched_solve_within_1e6_of_fp64():
             assert inf_m["converged"][i] == 1
             assert inf_m["norm_S"][i] <= TOL and inf_m["norm_T"][i] <= TOL   # final check is FP64
             err = rel(zm[i], zf[i])
-            _say(f"  relative state error {err:.2e}")
-            assert err <= 1e-6
+            n, m = shapes[i][0], shapes[i][1]
+            orom = oeq.ROM(oprob, base.Phi[:, :n], base.Psi[:, :m], els[i], rhos[i])
+            w, tau, oinfo = ogn.lm_solve(orom, mus[i], starts[i][:n], starts[i][n:], LAM, TOL, 150)
+            zo = np.r_[w, tau]
+            err_o, err_fo = rel(zm[i], zo), rel(zf[i], zo)
+            _say(f"  relative state error vs FP64 batch {err:.2e}, vs oracle {err_o:.2e} (FP64 batch vs oracle "
+                 f"{err_fo:.2e}; oracle {oinfo['status']} in {oinfo['iterations']} steps)")
+            assert oinfo["status"] == "converged"
+            assert err <= 1e-6 and err_o <= 1e-6 and err_fo <= 1e-6
             n_conv += 1
     assert n_conv >= 3

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from conftest import rel
+from conftest import gram_entry_err, rel, rel_blocks
 
 pytestmark = pytest.mark.gpu
 
@@ -138,6 +138,16 @@ def test_hdm_assemble_parity(which, request):
         assert rel(g["N"], o["N"]) < 1e-12
         for key in ("dRdU", "dRdUn", "dRdx", "dNdx"):
             assert rel(g[key], o[key].ravel()) < 1e-12, key
+        # element by element: R_e and every Jacobian block on its own scale
+        Ne = wl.mesh.n_elem
+        for key, ref in (("R", o["R"]), ("dRdU", o["dRdU"]), ("dRdUn", o["dRdUn"]), ("dRdx", o["dRdx"]),
+                         ("dNdx", o["dNdx"])):
+            assert rel_blocks(g[key], ref, Ne) < 1e-11, key
+        # N_e is a difference of two integrals of size ~4 kappa |Omega_e|:
+        # its rounding is bounded on that scale, element by element
+        X = wl.mesh.X.reshape(-1, 2)
+        area_e = np.ptp(X[:, 0]) * np.ptp(X[:, 1]) / Ne
+        assert np.abs(g["N"] - o["N"]).max() <= 1e-12 * 4.0 * wl.kappa * area_e
         assert int(g["n_bad"][0]) == o["n_bad"] == 0
 
 
@@ -197,7 +207,11 @@ def test_eq_assembly_parity(which, request):
         assert abs(g["Jr"] - oj["J"]) <= 1e-12 * oj["J"]
         assert rel(g["g"], oj["g"]) < 1e-12
         assert rel(g["H"], oj["H"]) < 1e-12
+        eH, eg = gram_entry_err(g["H"].reshape(oj["H"].shape), g["g"], oj["H"], oj["g"], oj["J"])
+        assert eH < 1e-12 and eg < 1e-12, (eH, eg)
         assert rel(g["Jt"], oj["Jt"]) < 1e-12
+        nr = case.rom.n_s * case.prob.nue
+        assert rel_blocks(g["Jt"][:nr], oj["Jt"][:nr], case.rom.n_s) < 1e-11
         assert rel(g["Ft"], orr["Ft"]) < 1e-12
         assert rel(g["PhiT_r"], orr["PhiT_r"]) < 1e-12
         assert g["n_bad"] == 0
