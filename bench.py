@@ -62,11 +62,15 @@ KNAMES = {"points": "k_points_eq2<Euler P2, fp64>", "eq_jac": "k_eq_fused<Euler 
 # HBM traffic per launch of each kernel from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) on this workload, scaled by what the same
 # counters read for a plain copy kernel of known size (a 512 MiB copy reads
-# back as 256 MiB fetched and 512 MiB written).  An entry is None until the
-# counters have been taken on the kernel as it now stands.
+# back as 256 MiB fetched and 512 MiB written:
+# profiles/hbm_counter_calibration_copy_512mib.md).  These are the counters
+# of profiles/eq_jacobian_euler_p2_819x16.md, taken on the kernels as they
+# now stand; an entry must become None when its kernel changes.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-# Measured on this workload (profiles/eq_jacobian_euler_p2_819x16.md).
-TRAFFIC_KIB = {"points": (4512.0, 74017.0), "eq_jac": (45552.0, 3088.0), "gram": (2458.0, 291.0)}
+TRAFFIC_KIB = {"points": (4508.1, 74017.3), "eq_jac": (45555.7, 3088.0), "gram": (2457.5, 290.7)}
+TRAFFIC_SOURCE = "profiles/eq_jacobian_euler_p2_819x16.md"
+# the full-order kernel (profiles/hdm_assemble_euler_p2_16384.md)
+HDM_TRAFFIC_KIB = (9057.8, 226304.0)
 # Full-order loop with Jacobians: reads U_e, the neighbour traces, x_e, X_e
 # and connectivity; writes R_e, N_e, dR/dU_e, dR/dU_e', dR/dx_e, dN/dx_e.
 HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)
@@ -904,7 +908,8 @@ def main():
                     "frac": tf / PEAK_FP64_TFLOPS}
     tr = TRAFFIC_KIB.get(dom)
     traffic = None if tr is None else FETCH_SCALE * tr[0] * 1024 + WRITE_SCALE * tr[1] * 1024
-    roofline.update({"traffic": traffic, "kernel": KNAMES[dom], "launch_avg_us": t_dom * 1e6,
+    roofline.update({"traffic": traffic, "traffic_source": TRAFFIC_SOURCE if traffic else None,
+                     "kernel": KNAMES[dom], "launch_avg_us": t_dom * 1e6,
                      "launches_per_step": launches[dom], "element_evals_per_launch": units,
                      "algorithmic_bytes_per_launch": KBYTES[dom] * units,
                      "algorithmic_flops_per_launch": (KFLOPS[dom] or 0) * units,
@@ -997,8 +1002,11 @@ def main():
         c2, ms2 = ift.profile_read("points")
         t_avg = (ms + ms2) / c * 1e-3
         gbs = HDM_BYTES_PER_ELEM * Ne / t_avg / 1e9
+        hdm_traffic = FETCH_SCALE * HDM_TRAFFIC_KIB[0] * 1024 + WRITE_SCALE * HDM_TRAFFIC_KIB[1] * 1024
         out["hdm_assemble"] = {"evals_per_s": Ne / t_avg, "launch_avg_us": t_avg * 1e6, "bound": "hbm",
                                "achieved_GBs": gbs, "frac": gbs / PEAK_HBM_GBS,
+                               "traffic": hdm_traffic, "traffic_GBs": hdm_traffic / t_avg / 1e9,
+                               "traffic_source": "profiles/hdm_assemble_euler_p2_16384.md",
                                "points_us": ms2 / c2 * 1e3 if c2 else None, "assembly_us": ms / c * 1e3,
                                "kernels": "one pass (point physics and blocks)" if not c2 else "points + assembly"}
         log(f"hdm_assemble: {t_avg * 1e6:.1f} us, {Ne / t_avg:.3e} evals/s, {gbs:.0f} GB/s")
