@@ -202,7 +202,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchIn
 
 // Fused assembly + Gram of the JAC instances with NT column tiles.
 template <class D, class R, int NT>
-__global__ __launch_bounds__(NTHR, NT == 1 ? 3 : (NT == 3 ? 2 : 1)) void k_fused_batch(const BatchInst* I, BatchLists L, int n_inst, int E) {
+__global__ __launch_bounds__(NTHR, (fused_blocks_per_cu<D, NT>())) void k_fused_batch(const BatchInst* I, BatchLists L, int n_inst, int E) {
   __shared__ FusedShared<D, R, NT> sh;
   fused_load_tab<D, R, NT>(sh, threadIdx.x);
   const int* off = L.off + NT * (n_inst + 1);

@@ -980,11 +980,28 @@ IFT_DEV void wave_sync() {
 
 // LDS of the fused kernel: the reference table, one point-data slot per
 // wave (reused for the cross-wave reduction) and the flag counts.
+// Elements a wave assembles side by side (their MFMA and A-operand chains
+// interleave, which hides the FP64 latencies at two waves per SIMD): two for
+// the four-component discretisations up to two column tiles, one otherwise
+// (three tiles of two elements do not fit 256 registers).
+template <class D, int NT>
+constexpr int fused_np() {
+  return D::NC == 4 && NT <= 2 ? 2 : 1;
+}
+
+// Workgroups per CU the fused kernels are compiled for: two waves per SIMD
+// (a 256-VGPR budget) when elements are assembled in pairs; otherwise as
+// many as the single-element body allows at its width.
+template <class D, int NT>
+constexpr int fused_blocks_per_cu() {
+  return fused_np<D, NT>() == 2 ? 2 : (NT == 1 ? 3 : (NT == 3 ? 2 : 1));
+}
+
 template <class D, class R, int NT>
 struct FusedShared {
   RefTab tab;
   union {
-    FusedSlot<D, R> w[NTHR / 64];
+    FusedSlot<D, R> w[NTHR / 64][fused_np<D, NT>()];
     double red[NTHR / 64 - 1][256];
   } u;
   int sbad[NTHR / 64][2];
@@ -995,6 +1012,218 @@ IFT_DEV void fused_load_tab(FusedShared<D, R, NT>& sh, int tid) {
   const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
   int* dst = reinterpret_cast<int*>(&sh.tab);
   for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
+}
+
+// NP sampled elements k0, k0 + 1, ... of one wave, side by side, in the
+// four-component discretisations: M_e of each formed tile by tile on FP64
+// MFMA (A operands generated per lane from the element's point data in the
+// wave's LDS slot, B operands the point bases), scaled by sqrt(rho_e), with
+// the residual column and the distortion row inserted, and M_e^T M_e added
+// to the Gram tiles h.  The w steps (a quadrature point, or a (face, point)
+// pair, per step; the lane's column component is kl), then the x steps
+// (volume: entry ab = kl of J at point q; faces: column 4 ks' + kl of the
+// (face, point, direction) block), one loop per kind of step.  Each step
+// issues its MFMAs with the B values in bc and then reloads bc with the B
+// values of the next step (across the loops too), so those loads overlap
+// the A values of the next step; the elements' chains interleave.  Tiles
+// without w (x) columns skip the MFMAs of w (x) steps; the loads are issued
+// for every tile.
+template <class D, class R, int NT, int NP>
+IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const double* Bw, const double* Bx,
+                          const FusedArgs& f, int pt, int k0, dvec4 (&h)[NT * (NT + 1) / 2], int& nbad, int& bor) {
+  static_assert(D::NC == 4, "four-component discretisations");
+  using O = EqOp<D>;
+  constexpr int NUE = D::NUE;
+  constexpr int MT = (NUE + 1 + 15) / 16;           // row tiles (element rows + distortion row)
+  constexpr int RD_MT = NUE / 16, RD_K = (NUE % 16) % 4, RD_V = (NUE % 16) / 4;  // distortion row
+  static_assert(O::KW == O::KWP, "w steps are whole points");
+  constexpr int KWS = O::KWP / 4, KXS = O::KXP / 4;
+  const RefTab& tab = sh.tab;
+  const int n = a.n, m = a.m, Dd = a.D;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int kl = lane >> 4, li = lane & 15;
+  const long long nrow_e = (long long)a.n_s * NUE;
+  const long long po = (long long)pt * a.nrows;
+  const int KS = KWS + (m > 0 ? KXS : 0);
+  // per-lane row constants; rows past nue are multiplied by zero
+  int ri[MT], rc[MT];
+  double rm[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = 16 * mt + li;
+    rm[mt] = row < NUE ? 1.0 : 0.0;
+    ri[mt] = (row < NUE ? row : 0) / D::NC;
+    rc[mt] = (row < NUE ? row : 0) % D::NC;
+  }
+  int cw[NT], cx[NT];
+  bool won[NT], xon[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int c = 16 * nt + li, jx = c - n;
+    cw[nt] = c < n ? c : n;
+    cx[nt] = (jx >= 0 && jx < m) ? jx : m;
+    won[nt] = 16 * nt < n;
+    xon[nt] = 16 * nt + 16 > n && 16 * nt < n + m;
+  }
+  const Pts<D, R>* P[NP];
+  const double* bw[NP];
+  const double* bx[NP];
+  double sq[NP], rv[NP], dv[NP];
+  dvec4 acc[NP][MT][NT];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int k = k0 + i;
+    P[i] = &sh.u.w[wave][i].p;
+    bw[i] = Bw + (long long)k * O::KWP * (n + 1);
+    bx[i] = Bx + (long long)k * O::KXP * (m + 1);
+    sq[i] = a.srho[k];
+    // residual entry of row `lane` (row nue: the distortion), distortion
+    // row entry of x-column `lane`
+    rv[i] = 0.0;
+    dv[i] = 0.0;
+    if (lane < NUE) rv[i] = double(residual_entry_p<D, R>(*P[i], tab, lane));
+    else if (lane == NUE) rv[i] = double(P[i]->N);
+    if (lane < m) {
+      const double* Ps = a.Psi_s + (long long)k * D::NXE * m + lane;
+#pragma unroll
+      for (int c = 0; c < D::NXE; ++c) dv[i] += double(P[i]->dN[c]) * Ps[c * m];
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[i][mt][nt] = dvec4{0.0, 0.0, 0.0, 0.0};
+  }
+  double bc[NP][NT];
+  auto bload = [&](int st) {
+    st = st < KS ? st : KS - 1;
+    const bool xs = st >= KWS;
+    const int r = 4 * (xs ? st - KWS : st) + kl;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const double* base = xs ? bx[i] + (long long)r * (m + 1) : bw[i] + (long long)r * (n + 1);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) bc[i][nt] = base[xs ? cx[nt] : cw[nt]];
+    }
+  };
+  auto mfmas = [&](const double (*av)[MT], const bool* on) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if (on[nt]) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[i][mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][mt], bc[i][nt], acc[i][mt][nt], 0, 0, 0);
+      }
+    }
+  };
+  bload(0);
+#pragma unroll 1
+  for (int q = 0; q < D::NQV; ++q) {
+    double av[NP][MT];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) av[i][mt] = aw_vol<D, R>(tab, *P[i], ri[mt], rc[mt], q, kl) * rm[mt];
+    mfmas(av, won);
+    bload(q + 1);
+  }
+#pragma unroll 1
+  for (int pl = 0; pl < 2; ++pl) {
+#pragma unroll 1
+    for (int fq = 0; fq < 3 * D::NQF; ++fq) {
+      double av[NP][MT];
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          av[i][mt] = aw_face<D, R>(tab, *P[i], ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl) * rm[mt];
+      mfmas(av, won);
+      bload(D::NQV + 3 * D::NQF * pl + fq + 1);
+    }
+  }
+  if (m > 0) {
+#pragma unroll 1
+    for (int q = 0; q < D::NQV; ++q) {
+      double av[NP][MT];
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) av[i][mt] = ax_vol<D, R>(tab, *P[i], ri[mt], rc[mt], q, kl) * rm[mt];
+      mfmas(av, xon);
+      bload(KWS + q + 1);
+    }
+#pragma unroll 1
+    for (int ks = 0; ks < KXS - D::NQV; ++ks) {
+      const int cf0 = 4 * ks + kl;
+      const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
+      const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
+      double av[NP][MT];
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) av[i][mt] = ax_tail<D, R>(tab, *P[i], ri[mt], rc[mt], cf) * (rm[mt] * cm);
+      mfmas(av, xon);
+      bload(KWS + D::NQV + ks + 1);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int k = k0 + i;
+    // scale by sqrt(rho_e); insert the residual column and the distortion row
+    double dsrc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int jd = 16 * nt + li - n;
+      dsrc[nt] = __shfl(dv[i], (jd >= 0 && jd < 64) ? jd : 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * mt + kl + 4 * v;   // < 32
+        const double rsrc = __shfl(rv[i], row);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int c = 16 * nt + li, jd = c - n;
+          double x = sq[i] * acc[i][mt][nt][v];
+          if (c == Dd) x = sq[i] * rsrc;   // zero below the distortion row
+          else if (mt == RD_MT && kl == RD_K && v == RD_V && jd >= 0 && jd < m) x = sq[i] * dsrc[nt];
+          acc[i][mt][nt][v] = x;
+        }
+      }
+    if (f.rows) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * mt + kl + 4 * v, c = 16 * nt + li;
+            if (row > NUE || c > Dd) continue;
+            const long long gr = row < NUE ? (long long)k * NUE + row : nrow_e + k;
+            if (c < Dd) a.Jt[(po + gr) * Dd + c] = acc[i][mt][nt][v];
+            else a.Ft[po + gr] = acc[i][mt][nt][v];
+          }
+    }
+    // Gram: rows 4v..4v+3 of row tile mt are the k-block of one MFMA step
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (16 * mt + 4 * v > NUE) continue;
+        int t = 0;
+#pragma unroll
+        for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+          for (int tb = ta; tb < NT; ++tb, ++t)
+            h[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[i][mt][ta][v], acc[i][mt][tb][v], h[t], 0, 0, 0);
+      }
+    const int bad = P[i]->bad;
+    nbad += bad != 0;
+    bor |= bad;
+    if (f.rows && lane == 0) a.flags[(long long)pt * a.n_s + k] = bad;
+  }
 }
 
 // One block of the fused assembly: sampled elements [4E blk, 4E (blk + 1))
@@ -1021,151 +1250,97 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
   const long long nrow_e = (long long)a.n_s * NUE;
   const long long po = (long long)pt * a.nrows;
   const int kbeg = (blk * (NTHR / 64) + wave) * f.E;
-  FusedSlot<D, R>& S = u.w[wave];
-  // each wave owns its slot: the point data of element k + 1 are loaded into
-  // registers while element k is assembled, and only the wave synchronises
+  // each wave owns its slots: the point data of the next elements are loaded
+  // into registers while the current ones are assembled, and only the wave
+  // synchronises
   const Pts<D, R>* pbase = reinterpret_cast<const Pts<D, R>*>(a.pts) + (long long)pt * a.n_s;
-  typename PtsRegs<D, R>::W pre[PtsRegs<D, R>::PER];
-  if (kbeg < a.n_s) pts_regs_load<D, R>(pre, pbase + kbeg, lane);
-  __syncthreads();   // the table is loaded
-  for (int e = 0; e < f.E; ++e) {
-    const int k = kbeg + e;
-    if (k >= a.n_s) break;
-    wave_sync();     // the slot's previous contents are consumed
-    pts_regs_store<D, R>(pre, &S.p, lane);
-    if (e + 1 < f.E && k + 1 < a.n_s) pts_regs_load<D, R>(pre, pbase + k + 1, lane);
-    wave_sync();
-    const Pts<D, R>& p = S.p;
-    const double sq = a.srho[k];
-    // residual entry of row `lane` (row nue: the distortion), distortion
-    // row entry of x-column `lane`
-    double rv = 0.0, dv = 0.0;
-    if (lane < NUE) rv = double(residual_entry_p<D, R>(p, tab, lane));
-    else if (lane == NUE) rv = double(p.N);
-    if (lane < m) {
-      const double* Ps = a.Psi_s + (long long)k * D::NXE * m + lane;
+  if constexpr (D::NC == 4) {
+    // groups of NP elements: the point data of the next group are loaded
+    // into registers while the current group is assembled
+    constexpr int NP = fused_np<D, NT>();
+    typename PtsRegs<D, R>::W pre[NP][PtsRegs<D, R>::PER];
 #pragma unroll
-      for (int c = 0; c < D::NXE; ++c) dv += double(p.dN[c]) * Ps[c * m];
-    }
-    // M_e projection: columns [0, n) from Aw * Bw, [n, D) from Ax * Bx
-    dvec4 acc[MT][NT];
+    for (int i = 0; i < NP; ++i)
+      if (i < f.E && kbeg + i < a.n_s) pts_regs_load<D, R>(pre[i], pbase + kbeg + i, lane);
+    __syncthreads();   // the table is loaded
+    for (int e = 0; e < f.E;) {
+      const int k = kbeg + e;
+      if (k >= a.n_s) break;
+      const int np = (NP == 2 && e + 1 < f.E && k + 1 < a.n_s) ? 2 : 1;   // wave-uniform
+      wave_sync();     // the slots' previous contents are consumed
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+      for (int i = 0; i < NP; ++i)
+        if (i < np) pts_regs_store<D, R>(pre[i], &u.w[wave][i].p, lane);
+      const int en = e + np;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = dvec4{0.0, 0.0, 0.0, 0.0};
-    // per-lane row constants; rows past nue are multiplied by zero
-    int ri[MT], rc[MT];
-    double rm[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int row = 16 * mt + li;
-      rm[mt] = row < NUE ? 1.0 : 0.0;
-      ri[mt] = (row < NUE ? row : 0) / D::NC;
-      rc[mt] = (row < NUE ? row : 0) % D::NC;
-    }
-    const double* bw = Bw + (long long)k * O::KWP * (n + 1);
-    // one k-step of the w columns: A values av[mt] for columns 4 ks + kl
-    auto wstep = [&](int ks, const double* av) {
-      double bv[NT];   // loaded for every tile (tiles without w columns read the zero column)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int c = 16 * nt + li;
-        bv[nt] = bw[(4 * ks + kl) * (n + 1) + (c < n ? c : n)];
+      for (int i = 0; i < NP; ++i)
+        if (en + i < f.E && kbeg + en + i < a.n_s) pts_regs_load<D, R>(pre[i], pbase + kbeg + en + i, lane);
+      wave_sync();
+      if constexpr (NP == 2) {
+        if (np == 2) fused_elems4<D, R, NT, 2>(sh, a, Bw, Bx, f, pt, k, h, nbad, bor);
+        else fused_elems4<D, R, NT, 1>(sh, a, Bw, Bx, f, pt, k, h, nbad, bor);
+      } else {
+        fused_elems4<D, R, NT, 1>(sh, a, Bw, Bx, f, pt, k, h, nbad, bor);
       }
-      // every tile takes part (a tile without w columns adds zeros), so the
-      // k-loop is one basic block and the loads of later steps can be hoisted
+      e = en;
+    }
+  } else {
+    FusedSlot<D, R>& S = u.w[wave][0];
+    typename PtsRegs<D, R>::W pre[PtsRegs<D, R>::PER];
+    if (kbeg < a.n_s) pts_regs_load<D, R>(pre, pbase + kbeg, lane);
+    __syncthreads();   // the table is loaded
+    for (int e = 0; e < f.E; ++e) {
+      const int k = kbeg + e;
+      if (k >= a.n_s) break;
+      wave_sync();     // the slot's previous contents are consumed
+      pts_regs_store<D, R>(pre, &S.p, lane);
+      if (e + 1 < f.E && k + 1 < a.n_s) pts_regs_load<D, R>(pre, pbase + k + 1, lane);
+      wave_sync();
+      const Pts<D, R>& p = S.p;
+      const double sq = a.srho[k];
+      // residual entry of row `lane` (row nue: the distortion), distortion
+      // row entry of x-column `lane`
+      double rv = 0.0, dv = 0.0;
+      if (lane < NUE) rv = double(residual_entry_p<D, R>(p, tab, lane));
+      else if (lane == NUE) rv = double(p.N);
+      if (lane < m) {
+        const double* Ps = a.Psi_s + (long long)k * D::NXE * m + lane;
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
-    };
-    if constexpr (D::NC == 4) {
-      // The w steps (a quadrature point, or a (face, point) pair, per step;
-      // the lane's column component is kl), then the x steps (volume: entry
-      // ab = kl of J at point q; faces: column 4 ks' + kl of the (face,
-      // point, direction) block), one loop per kind of step.  Each step
-      // issues its MFMAs with the B values in bc and then reloads bc with
-      // the B values of the next step (across the loops too), so those loads
-      // overlap the A values of the next step.  Tiles without w (x) columns
-      // skip the MFMAs of w (x) steps; the loads are issued for every tile.
-      static_assert(O::KW == O::KWP, "w steps are whole points");
-      constexpr int KWS = O::KWP / 4, KXS = O::KXP / 4;
-      const int KS = KWS + (m > 0 ? KXS : 0);
-      const double* bx = Bx + (long long)k * O::KXP * (m + 1);
-      int cw[NT], cx[NT];
-      bool won[NT], xon[NT];
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int c = 16 * nt + li, jx = c - n;
-        cw[nt] = c < n ? c : n;
-        cx[nt] = (jx >= 0 && jx < m) ? jx : m;
-        won[nt] = 16 * nt < n;
-        xon[nt] = 16 * nt + 16 > n && 16 * nt < n + m;
+        for (int c = 0; c < D::NXE; ++c) dv += double(p.dN[c]) * Ps[c * m];
       }
-      double bc[NT];
-      auto bload = [&](int st) {
-        st = st < KS ? st : KS - 1;
-        const bool xs = st >= KWS;
-        const int r = 4 * (xs ? st - KWS : st) + kl;
-        const double* base = xs ? bx + (long long)r * (m + 1) : bw + (long long)r * (n + 1);
+      // M_e projection: columns [0, n) from Aw * Bw, [n, D) from Ax * Bx
+      dvec4 acc[MT][NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) bc[nt] = base[xs ? cx[nt] : cw[nt]];
-      };
-      auto mfmas = [&](const double* av, const bool* on) {
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = dvec4{0.0, 0.0, 0.0, 0.0};
+      // per-lane row constants; rows past nue are multiplied by zero
+      int ri[MT], rc[MT];
+      double rm[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int row = 16 * mt + li;
+        rm[mt] = row < NUE ? 1.0 : 0.0;
+        ri[mt] = (row < NUE ? row : 0) / D::NC;
+        rc[mt] = (row < NUE ? row : 0) % D::NC;
+      }
+      const double* bw = Bw + (long long)k * O::KWP * (n + 1);
+      // one k-step of the w columns: A values av[mt] for columns 4 ks + kl
+      auto wstep = [&](int ks, const double* av) {
+        double bv[NT];   // loaded for every tile (tiles without w columns read the zero column)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-          if (on[nt]) {
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-              acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bc[nt], acc[mt][nt], 0, 0, 0);
-          }
+          const int c = 16 * nt + li;
+          bv[nt] = bw[(4 * ks + kl) * (n + 1) + (c < n ? c : n)];
         }
+        // every tile takes part (a tile without w columns adds zeros), so the
+        // k-loop is one basic block and the loads of later steps can be hoisted
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
       };
-      bload(0);
-#pragma unroll 1
-      for (int q = 0; q < D::NQV; ++q) {
-        double av[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) av[mt] = aw_vol<D, R>(tab, p, ri[mt], rc[mt], q, kl) * rm[mt];
-        mfmas(av, won);
-        bload(q + 1);
-      }
-#pragma unroll 1
-      for (int pl = 0; pl < 2; ++pl) {
-#pragma unroll 1
-        for (int fq = 0; fq < 3 * D::NQF; ++fq) {
-          double av[MT];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-            av[mt] = aw_face<D, R>(tab, p, ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl) * rm[mt];
-          mfmas(av, won);
-          bload(D::NQV + 3 * D::NQF * pl + fq + 1);
-        }
-      }
-      if (m > 0) {
-#pragma unroll 1
-        for (int q = 0; q < D::NQV; ++q) {
-          double av[MT];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt) av[mt] = ax_vol<D, R>(tab, p, ri[mt], rc[mt], q, kl) * rm[mt];
-          mfmas(av, xon);
-          bload(KWS + q + 1);
-        }
-#pragma unroll 1
-        for (int ks = 0; ks < KXS - D::NQV; ++ks) {
-          const int cf0 = 4 * ks + kl;
-          const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
-          const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
-          double av[MT];
-#pragma unroll
-          for (int mt = 0; mt < MT; ++mt)
-            av[mt] = ax_tail<D, R>(tab, p, ri[mt], rc[mt], cf) * (rm[mt] * cm);
-          mfmas(av, xon);
-          bload(KWS + D::NQV + ks + 1);
-        }
-      }
-    } else {
 #pragma unroll 4
       for (int ks = 0; ks < O::KWP / 4; ++ks) {
         double av[MT];
@@ -1211,60 +1386,60 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
           xstep(D::NQV + ks, av);
         }
       }
-    }
-    // scale by sqrt(rho_e); insert the residual column and the distortion row
-    double dsrc[NT];
+      // scale by sqrt(rho_e); insert the residual column and the distortion row
+      double dsrc[NT];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int jd = 16 * nt + li - n;
-      dsrc[nt] = __shfl(dv, (jd >= 0 && jd < 64) ? jd : 0);
-    }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = 16 * mt + kl + 4 * v;   // < 32
-        const double rsrc = __shfl(rv, row);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const int c = 16 * nt + li, jd = c - n;
-          double x = sq * acc[mt][nt][v];
-          if (c == Dd) x = sq * rsrc;   // zero below the distortion row
-          else if (mt == RD_MT && kl == RD_K && v == RD_V && jd >= 0 && jd < m) x = sq * dsrc[nt];
-          acc[mt][nt][v] = x;
-        }
+      for (int nt = 0; nt < NT; ++nt) {
+        const int jd = 16 * nt + li - n;
+        dsrc[nt] = __shfl(dv, (jd >= 0 && jd < 64) ? jd : 0);
       }
-    if (f.rows) {
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * mt + kl + 4 * v;   // < 32
+          const double rsrc = __shfl(rv, row);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = 16 * mt + kl + 4 * v, c = 16 * nt + li;
-            if (row > NUE || c > Dd) continue;
-            const long long gr = row < NUE ? (long long)k * NUE + row : nrow_e + k;
-            if (c < Dd) a.Jt[(po + gr) * Dd + c] = acc[mt][nt][v];
-            else a.Ft[po + gr] = acc[mt][nt][v];
+          for (int nt = 0; nt < NT; ++nt) {
+            const int c = 16 * nt + li, jd = c - n;
+            double x = sq * acc[mt][nt][v];
+            if (c == Dd) x = sq * rsrc;   // zero below the distortion row
+            else if (mt == RD_MT && kl == RD_K && v == RD_V && jd >= 0 && jd < m) x = sq * dsrc[nt];
+            acc[mt][nt][v] = x;
           }
-    }
-    // Gram: rows 4v..4v+3 of row tile mt are the k-block of one MFMA step
+        }
+      if (f.rows) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        if (16 * mt + 4 * v > NUE) continue;
-        int t = 0;
+          for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-        for (int ta = 0; ta < NT; ++ta)
-#pragma unroll
-          for (int tb = ta; tb < NT; ++tb, ++t)
-            h[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[mt][ta][v], acc[mt][tb][v], h[t], 0, 0, 0);
+            for (int v = 0; v < 4; ++v) {
+              const int row = 16 * mt + kl + 4 * v, c = 16 * nt + li;
+              if (row > NUE || c > Dd) continue;
+              const long long gr = row < NUE ? (long long)k * NUE + row : nrow_e + k;
+              if (c < Dd) a.Jt[(po + gr) * Dd + c] = acc[mt][nt][v];
+              else a.Ft[po + gr] = acc[mt][nt][v];
+            }
       }
-    const int bad = p.bad;
-    nbad += bad != 0;
-    bor |= bad;
-    if (f.rows && lane == 0) a.flags[(long long)pt * a.n_s + k] = bad;
+      // Gram: rows 4v..4v+3 of row tile mt are the k-block of one MFMA step
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (16 * mt + 4 * v > NUE) continue;
+          int t = 0;
+#pragma unroll
+          for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+            for (int tb = ta; tb < NT; ++tb, ++t)
+              h[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[mt][ta][v], acc[mt][tb][v], h[t], 0, 0, 0);
+        }
+      const int bad = p.bad;
+      nbad += bad != 0;
+      bor |= bad;
+      if (f.rows && lane == 0) a.flags[(long long)pt * a.n_s + k] = bad;
+    }
   }
   // add the four waves in wave order; one partial per block
   __syncthreads();
@@ -1301,7 +1476,7 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
 }
 
 template <class D, class R, int NT>
-__global__ __launch_bounds__(NTHR, NT == 1 ? 3 : (NT == 3 ? 2 : 1)) void k_eq_fused(EqArgs a, const double* Bw, const double* Bx, FusedArgs f) {
+__global__ __launch_bounds__(NTHR, (fused_blocks_per_cu<D, NT>())) void k_eq_fused(EqArgs a, const double* Bw, const double* Bx, FusedArgs f) {
   __shared__ FusedShared<D, R, NT> sh;
   fused_load_tab<D, R, NT>(sh, threadIdx.x);
   fused_body<D, R, NT>(sh, a, Bw, Bx, f, blockIdx.x, blockIdx.y);

@@ -170,7 +170,7 @@ IFT_DEV void fused_body_mixed(FusedShared<D, float, NT>& sh, const EqArgs& a, co
   const long long nrow_e = (long long)a.n_s * NUE;
   const long long po = (long long)pt * a.nrows;
   const int kbeg = (blk * (NTHR / 64) + wave) * f.E;
-  FusedSlot<D, float>& S = u.w[wave];
+  FusedSlot<D, float>& S = u.w[wave][0];
   for (int e = 0; e < f.E; ++e) {
     const int k = kbeg + e;
     __syncthreads();
