@@ -313,7 +313,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
 // ------------------------------------------------ full-order assembly
 template <class D, class R>
 __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
-  __shared__ ElemLDS<D, R> s;
+  __shared__ ElemLDSJx<D, R> s;
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
   load_tab<D, R>(s, tid, NTHR);
