@@ -183,7 +183,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchIn
   const int total = L.cnt[0];
   const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
   int inst = 0;
-  load_tab<D, R>(s[h], t, NTHR_PTS);   // constant: visible after the first barrier
+  load_tab<D, R, NTHR_PTS>(s[h], t);   // constant: visible after the first barrier
   for (int i0 = 2 * blockIdx.x; i0 < total; i0 += 2 * gridDim.x) {
     const int item = i0 + min(h, total - 1 - i0);
     inst = __builtin_amdgcn_readfirstlane(batch_owner_from(L.off, n_inst, item, inst));
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchIn
     __syncthreads();
     phase_distortion<D, R>(s[h], t, R(a.kappa));
     __syncthreads();
-    if (item == i0 + h) copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + k, &s[h].p, t, NTHR_PTS);
+    if (item == i0 + h) copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + k, &s[h].p, t);
     __syncthreads();
   }
 }

@@ -120,12 +120,29 @@ struct ElemLDSJx : ElemLDS<D, R> {
   R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
 };
 
-template <class D, class R>
-IFT_DEV void load_tab(ElemLDS<D, R>& s, int tid, int nthr) {
-  const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
-  int* dst = reinterpret_cast<int*>(&s.tab);
-  constexpr int nw = sizeof(RefTab) / sizeof(int);
-  for (int i = tid; i < nw; i += nthr) dst[i] = src[i];
+// Copies an object of type T with NT threads in words of 8 bytes where its
+// size and alignment allow (else 4): a fixed trip count, and every load of a
+// thread issued before its first store, so the copy costs one memory latency
+// instead of one per word.
+template <class T, int NT>
+IFT_DEV void copy_obj(T* dst, const T* src, int tid) {
+  static_assert(sizeof(T) % 4 == 0 && alignof(T) >= 4, "whole 4-byte words");
+  using W = typename std::conditional<sizeof(T) % 8 == 0 && alignof(T) >= 8, unsigned long long, unsigned>::type;
+  constexpr int nw = (int)(sizeof(T) / sizeof(W)), it = (nw + NT - 1) / NT;
+  W* d = reinterpret_cast<W*>(dst);
+  const W* s = reinterpret_cast<const W*>(src);
+  W v[it];
+#pragma unroll
+  for (int i = 0; i < it; ++i)
+    if (tid + i * NT < nw) v[i] = s[tid + i * NT];
+#pragma unroll
+  for (int i = 0; i < it; ++i)
+    if (tid + i * NT < nw) d[tid + i * NT] = v[i];
+}
+
+template <class D, class R, int NT>
+IFT_DEV void load_tab(ElemLDS<D, R>& s, int tid) {
+  copy_obj<RefTab, NT>(&s.tab, &c_tab[D::P - 1], tid);
 }
 
 // ----------------------------------------------------------------- phase B

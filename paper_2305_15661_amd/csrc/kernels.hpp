@@ -80,15 +80,27 @@ IFT_DEV PhysConst phys_from_mu(const PhysConst& base, int pde, double bc_scale, 
   return pc;
 }
 
-template <class D, class R>
-IFT_DEV void copy_words(void* dst, const void* src, int tid, int nthr) {
-  constexpr int nw = sizeof(Pts<D, R>) / sizeof(int);
-  int* d = reinterpret_cast<int*>(dst);
-  const int* s = reinterpret_cast<const int*>(src);
-  for (int i = tid; i < nw; i += nthr) d[i] = s[i];
+// ------------------------------------------------------------------ loaders
+// acc + sum_j row[j] v[j], accumulated in index order.  The loads of a chunk
+// of terms are issued together: summed in a plain loop, each term would wait
+// for its own load (a cache round trip per basis coefficient).
+constexpr int LIFT_CHUNK = 16;
+IFT_DEV double lift_dot(const double* row, const double* v, int n, double acc) {
+  for (int j0 = 0; j0 < n; j0 += LIFT_CHUNK) {
+    double r[LIFT_CHUNK], c[LIFT_CHUNK];
+#pragma unroll
+    for (int u = 0; u < LIFT_CHUNK; ++u) {
+      const int j = min(j0 + u, n - 1);
+      r[u] = row[j];
+      c[u] = v[j];
+    }
+#pragma unroll
+    for (int u = 0; u < LIFT_CHUNK; ++u)
+      if (j0 + u < n) acc += r[u] * c[u];
+  }
+  return acc;
 }
 
-// ------------------------------------------------------------------ loaders
 template <class D, class R>
 IFT_DEV void load_hdm(ElemLDS<D, R>& s, const HdmArgs& a, int e, int tid, int nthr) {
   constexpr int ntask = D::NUE + D::NUN + 2 * D::NXE + 3;
@@ -133,14 +145,12 @@ IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid, 
   for (int t = tid; t < D::NUE + D::NUN + D::NXE; t += nthr) {
     if (t < D::NUE + D::NUN) {
       const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
-      double acc = 0.0;
-      for (int j = 0; j < n; ++j) acc += row[j] * w[j];
+      const double acc = lift_dot(row, w, n, 0.0);
       if (t < D::NUE) s.U[t] = R(acc);
       else s.Un[t - D::NUE] = R(acc);
     } else {
       const int q = t - D::NUE - D::NUN;
-      double acc = Xs[q];
-      for (int j = 0; j < m; ++j) acc += Ps[(long long)q * m + j] * tau[j];
+      const double acc = lift_dot(Ps + (long long)q * m, tau, m, Xs[q]);
       s.x[q] = R(acc);
       s.X[q] = R(Xs[q]);
     }
@@ -154,7 +164,7 @@ __global__ __launch_bounds__(NTHR) void k_hdm_val(HdmArgs a) {
   __shared__ ElemLDS<D, R> s;
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
-  load_tab<D, R>(s, tid, NTHR);
+  load_tab<D, R, NTHR>(s, tid);
   load_hdm<D, R>(s, a, e, tid, NTHR);
   __syncthreads();
   phase_points<D, R, false>(s, tid, a.pc, R(a.kappa), R(a.eps));
@@ -221,7 +231,7 @@ __global__ __launch_bounds__(NTHR_PTS) void k_hdm_fused(HdmArgs a) {
   __shared__ ElemLDS<D, R> s;
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
-  load_tab<D, R>(s, tid, NTHR_PTS);
+  load_tab<D, R, NTHR_PTS>(s, tid);
   load_hdm<D, R>(s, a, e, tid, NTHR_PTS);
   __syncthreads();
   phase_points<D, R, true>(s, tid, a.pc, R(a.kappa), R(a.eps));
@@ -240,7 +250,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_hdm_fused2(HdmArgs a) {
   const int e0 = 2 * blockIdx.x;
   const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
   const int e = e0 + min(h, a.n_elem - 1 - e0);
-  load_tab<D, R>(s[h], t, NTHR_PTS);
+  load_tab<D, R, NTHR_PTS>(s[h], t);
   load_hdm<D, R>(s[h], a, e, t, NTHR_PTS);
   __syncthreads();
   phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return a.pc; }, R(a.eps));
@@ -255,7 +265,7 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
   __shared__ ElemLDS<D, R> s;
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
-  load_tab<D, R>(s, tid, NTHR_PTS);
+  load_tab<D, R, NTHR_PTS>(s, tid);
   load_hdm<D, R>(s, a, e, tid, NTHR_PTS);
   __syncthreads();
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
@@ -263,13 +273,13 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
   __syncthreads();
   phase_distortion<D, R>(s, tid, R(a.kappa));
   __syncthreads();
-  copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + e, &s.p, tid, NTHR_PTS);
+  copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + e, &s.p, tid);
 }
 
 // Point data of sampled element k at evaluation point pt (one block).
 template <class D, class R>
 IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
-  load_tab<D, R>(s, tid, NTHR_PTS);
+  load_tab<D, R, NTHR_PTS>(s, tid);
   load_eq<D, R>(s, a, k, pt, tid, NTHR_PTS);
   __syncthreads();
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
@@ -278,7 +288,7 @@ IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, in
   __syncthreads();
   phase_distortion<D, R>(s, tid, R(a.kappa));
   __syncthreads();
-  copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s.p, tid, NTHR_PTS);
+  copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s.p, tid);
 }
 
 template <class D, class R>
@@ -299,7 +309,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   if (k0 >= a.n_s) return;   // padding blocks (whole block)
   const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
   const int k = k0 + min(h, a.n_s - 1 - k0);
-  load_tab<D, R>(s[h], t, NTHR_PTS);
+  load_tab<D, R, NTHR_PTS>(s[h], t);
   load_eq<D, R>(s[h], a, k, pt, t, NTHR_PTS);   // ends with a barrier
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return pc; }, R(a.eps));
@@ -307,7 +317,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   phase_distortion<D, R>(s[h], t, R(a.kappa));
   __syncthreads();
   if (k == k0 + h)
-    copy_words<D, R>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s[h].p, t, NTHR_PTS);
+    copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s[h].p, t);
 }
 
 // ------------------------------------------------ full-order assembly
@@ -316,8 +326,8 @@ __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
   __shared__ ElemLDSJx<D, R> s;
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
-  load_tab<D, R>(s, tid, NTHR);
-  copy_words<D, R>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + e, tid, NTHR);
+  load_tab<D, R, NTHR>(s, tid);
+  copy_obj<Pts<D, R>, NTHR>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + e, tid);
   __syncthreads();
   if constexpr (D::NC == 4) {
     hdm_write_blocks<D, R>(s, a, e, tid, NTHR);
@@ -383,10 +393,7 @@ struct ResShared {
 
 template <class D, class R>
 IFT_DEV void res_load_tab(ResShared<D, R>& sh, int tid) {
-  const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
-  int* dst = reinterpret_cast<int*>(&sh.tab);
-  constexpr int nw = sizeof(RefTab) / sizeof(int);
-  for (int i = tid; i < nw; i += RV_THR) dst[i] = src[i];
+  copy_obj<RefTab, RV_THR>(&sh.tab, &c_tab[D::P - 1], tid);
 }
 
 // One element (k, pt) per lane group; `act` is false for the groups of a
@@ -411,14 +418,12 @@ IFT_DEV void res_group_body(ResShared<D, R>& sh, ElemVal<D, R>& e, const EqArgs&
     for (int t = j; t < D::NUE + D::NUN + D::NXE; t += RV_LANES) {
       if (t < D::NUE + D::NUN) {
         const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
-        double acc = 0.0;
-        for (int i = 0; i < n; ++i) acc += row[i] * w[i];
+        const double acc = lift_dot(row, w, n, 0.0);
         if (t < D::NUE) e.U[t] = R(acc);
         else e.Un[t - D::NUE] = R(acc);
       } else {
         const int q = t - D::NUE - D::NUN;
-        double acc = Xs[q];
-        for (int i = 0; i < m; ++i) acc += Ps[(long long)q * m + i] * tau[i];
+        const double acc = lift_dot(Ps + (long long)q * m, tau, m, Xs[q]);
         e.x[q] = R(acc);
         e.X[q] = R(Xs[q]);
       }
@@ -531,19 +536,13 @@ __global__ __launch_bounds__(RV_THR) void k_hdm_res_rom(HdmRomArgs a) {
     for (int t = j; t < D::NUE + D::NUN + D::NXE; t += RV_LANES) {
       if (t < D::NUE + D::NUN) {
         const long long row = t < D::NUE ? (long long)e * D::NUE + t : (long long)a.Pn[(long long)e * D::NUN + t - D::NUE];
-        double acc = 0.0;
-        if (row >= 0) {
-          const double* ph = a.Phi + row * n;
-          for (int i = 0; i < n; ++i) acc += ph[i] * w[i];
-        }
+        const double acc = row >= 0 ? lift_dot(a.Phi + row * n, w, n, 0.0) : 0.0;
         if (t < D::NUE) el.U[t] = R(acc);
         else el.Un[t - D::NUE] = R(acc);
       } else {
         const int r = t - D::NUE - D::NUN;
         const long long c = 2LL * a.gn[(long long)e * D::NN + r / 2] + (r & 1);
-        double acc = a.X[c];
-        const double* ps = a.Psi + c * m;
-        for (int i = 0; i < m; ++i) acc += ps[i] * tau[i];
+        const double acc = lift_dot(a.Psi + c * m, tau, m, a.X[c]);
         el.x[r] = R(acc);
         el.X[r] = R(a.X[c]);
       }
@@ -846,7 +845,7 @@ __global__ __launch_bounds__(NTHR) void k_eq_asm(EqArgs a, const double* Bw, con
     int* dst = reinterpret_cast<int*>(&s.tab);
     for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
   }
-  copy_words<D, R>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), tid, NTHR);
+  copy_obj<Pts<D, R>, NTHR>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), tid);
   __syncthreads();
   const double sq = a.srho[k];
   const long long nrow_e = (long long)a.n_s * D::NUE;
@@ -1009,9 +1008,7 @@ struct FusedShared {
 
 template <class D, class R, int NT>
 IFT_DEV void fused_load_tab(FusedShared<D, R, NT>& sh, int tid) {
-  const int* src = reinterpret_cast<const int*>(&c_tab[D::P - 1]);
-  int* dst = reinterpret_cast<int*>(&sh.tab);
-  for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
+  copy_obj<RefTab, NTHR>(&sh.tab, &c_tab[D::P - 1], tid);
 }
 
 // NP sampled elements k0, k0 + 1, ... of one wave, side by side, in the
