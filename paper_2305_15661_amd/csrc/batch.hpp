@@ -190,12 +190,12 @@ __global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchIn
     const int k = item - L.off[inst];
     const EqArgs& a = I[inst].a;
     if (t == 0) spc[h] = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu) : a.pc;
-    load_eq<D, R>(s[h], a, k, 0, t, NTHR_PTS);   // ends with a barrier
+    load_eq<D, R>(s[h], a, k, 0, t);   // ends with a barrier
     phase_points_pair<D, R>(s, tid, [&](int e) -> const PhysConst& { return spc[e]; }, R(a.eps));
     __syncthreads();
     phase_distortion<D, R>(s[h], t, R(a.kappa));
     __syncthreads();
-    if (item == i0 + h) copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + k, &s[h].p, t);
+    if (item == i0 + h) copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + k, &s[h].p, t);
     __syncthreads();
   }
 }

@@ -107,9 +107,11 @@ struct ElemLDS {
   R x[D::NXE];
   R X[D::NXE];
   int face[3];
-  Pts<D, R> p;
+  alignas(16) Pts<D, R> p;   // 16-byte aligned: copied out in 16-byte words where its size allows
   R Re[D::NUE];
   R deta[D::NQV][5];   // per volume point: distortion integrand and its J-gradient
+  R eta_ref;           // distortion of the reference element X_e (precomputed per element; the loaders fill it)
+  double cf[2][64];    // lift coefficients (w, tau), zero-padded, one vector per loading wave
 };
 
 // With the explicit element Jacobian (the assembly kernel that writes its
@@ -120,14 +122,17 @@ struct ElemLDSJx : ElemLDS<D, R> {
   R Jx[D::NUE][D::NDIR];   // [dR/dU_e | dR/dU_e' | dR/dx_e]
 };
 
-// Copies an object of type T with NT threads in words of 8 bytes where its
-// size and alignment allow (else 4): a fixed trip count, and every load of a
-// thread issued before its first store, so the copy costs one memory latency
-// instead of one per word.
-template <class T, int NT>
+// Copies an object of type T with NT threads in the widest words (16, 8 or
+// 4 bytes) that its size and ALIGN, the alignment both ends guarantee,
+// allow: a fixed trip count, and every load of a thread issued before its
+// first store, so the copy costs one memory latency instead of one per word
+// (and fewer, wider accesses).
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+template <class T, int NT, int ALIGN = alignof(T)>
 IFT_DEV void copy_obj(T* dst, const T* src, int tid) {
-  static_assert(sizeof(T) % 4 == 0 && alignof(T) >= 4, "whole 4-byte words");
-  using W = typename std::conditional<sizeof(T) % 8 == 0 && alignof(T) >= 8, unsigned long long, unsigned>::type;
+  static_assert(sizeof(T) % 4 == 0 && ALIGN >= 4, "whole 4-byte words");
+  using W8 = typename std::conditional<sizeof(T) % 8 == 0 && ALIGN >= 8, unsigned long long, unsigned>::type;
+  using W = typename std::conditional<sizeof(T) % 16 == 0 && ALIGN >= 16, u32x4, W8>::type;
   constexpr int nw = (int)(sizeof(T) / sizeof(W)), it = (nw + NT - 1) / NT;
   W* d = reinterpret_cast<W*>(dst);
   const W* s = reinterpret_cast<const W*>(src);
@@ -385,7 +390,7 @@ IFT_DEV void phase_points(ElemLDS<D, R>& s, int tid, const PhysConst& pc, R kapp
         face_point<D, R, R>(s.tab, s, r / D::NQF, r % D::NQF, -1, pc);
       } else {
         Tan<R> eta = eta_elem<D, R>(s.tab, s.x, s.X, eps, -1);
-        s.p.N = kappa * (eta.v - eta_reference<D, R>(s.tab, s.X));
+        s.p.N = kappa * (eta.v - s.eta_ref);
       }
     }
   } else {
@@ -470,7 +475,7 @@ IFT_DEV void phase_distortion(ElemLDS<D, R>& s, int tid, R kappa) {
     R eta = R(0);
 #pragma unroll
     for (int q = 0; q < D::NQV; ++q) eta += s.deta[q][0];
-    s.p.N = kappa * (eta - eta_reference<D, R>(s.tab, s.X));
+    s.p.N = kappa * (eta - s.eta_ref);
   }
 }
 

@@ -45,6 +45,7 @@ struct ift_problem {
   int* d_Pn = nullptr;
   double* d_X = nullptr;
   int* d_flags = nullptr;
+  double* d_eta_ref = nullptr;   // distortion of each reference element [n_elem]
   void* d_pts = nullptr;   // point-data workspace of the Jacobian path [n_elem]
   double* d_hn_part = nullptr;   // residual-norm block sums [points][blocks] (grown on demand)
   int* d_hn_bad = nullptr;
@@ -63,6 +64,10 @@ struct ift_rom {
   double* d_Phin_s = nullptr;
   double* d_Psi_s = nullptr;
   double* d_X_s = nullptr;
+  int* d_face_s = nullptr;    // [n_s][3]: face codes of the sampled elements
+  double* d_eta_ref_s = nullptr;   // [n_s]: distortion of each sampled reference element
+  double* d_LiftU = nullptr;  // [n_s][n][nue + nun]: the gathered Phi rows, column-major per element
+  double* d_LiftX = nullptr;  // [n_s][m][nxe]: the gathered Psi rows, column-major per element
   double* d_Bw = nullptr;   // reduced state basis at the quadrature points [n_s][KWP][n]
   double* d_Bx = nullptr;   // mapping-basis geometry derivatives [n_s][KXP][m]
   short* d_Bw16 = nullptr;  // BF16 copies, column-major per element (mixed precision)
@@ -378,6 +383,16 @@ static void with_disc(const ift_problem* pr, F&& f) {
   }
 }
 
+// Distortion of every reference element (the reference term of N_e).
+struct EtaRef {
+  ift_problem* pr;
+  template <class D>
+  void run() {
+    hipLaunchKernelGGL((k_eta_ref<D>), dim3((pr->n_elem + 255) / 256), dim3(256), 0, 0, (const double*)pr->d_X,
+                       (const int*)pr->d_gn, pr->n_elem, pr->d_eta_ref);
+  }
+};
+
 // ------------------------------------------------------------------- problem
 extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem** out) {
   if (!d || !out) return IFT_EINVAL;
@@ -459,7 +474,8 @@ extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem*
       (st = dalloc(&pr->d_face, pr->h_face.size())) != IFT_OK ||
       (st = dalloc(&pr->d_Pn, pn32.size())) != IFT_OK ||
       (st = dalloc(&pr->d_X, pr->h_X.size())) != IFT_OK ||
-      (st = dalloc(&pr->d_flags, (size_t)Ne)) != IFT_OK) {
+      (st = dalloc(&pr->d_flags, (size_t)Ne)) != IFT_OK ||
+      (st = dalloc(&pr->d_eta_ref, (size_t)Ne)) != IFT_OK) {
     ift_problem_destroy(pr);
     return st;
   }
@@ -474,6 +490,11 @@ extern "C" ift_status ift_problem_create(const ift_problem_desc* d, ift_problem*
     ift_problem_destroy(pr);
     return IFT_EDEVICE;
   }
+  with_disc(pr, EtaRef{pr});
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    ift_problem_destroy(pr);
+    return IFT_EDEVICE;
+  }
   *out = pr;
   return IFT_OK;
 }
@@ -485,6 +506,7 @@ extern "C" void ift_problem_destroy(ift_problem* pr) {
   dfree(pr->d_Pn);
   dfree(pr->d_X);
   dfree(pr->d_flags);
+  dfree(pr->d_eta_ref);
   dfree(pr->d_hn_part);
   dfree(pr->d_hn_bad);
   if (pr->d_pts) (void)hipFree(pr->d_pts);
@@ -554,6 +576,7 @@ extern "C" ift_status hdm_assemble(ift_problem* pr, const double* mu, const doub
   a.dRdx = dRdx;
   a.dNdx = dNdx;
   a.flags = pr->d_flags;
+  a.eta_ref = pr->d_eta_ref;
   a.pts = pr->d_pts;
   a.pc = phys_const(pr, mu);
   a.kappa = pr->kappa;
@@ -636,6 +659,10 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   dfree(r->d_Phin_s);
   dfree(r->d_Psi_s);
   dfree(r->d_X_s);
+  dfree(r->d_face_s);
+  dfree(r->d_eta_ref_s);
+  dfree(r->d_LiftU);
+  dfree(r->d_LiftX);
   dfree(r->d_Jt);
   dfree(r->d_Ft);
   dfree(r->d_Jpart);
@@ -804,10 +831,12 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   r->gram_rows_per = (int)std::min<long long>(cap, std::max<long long>(4, (r->nrows + 255) / 256));
   r->n_gram_blk = (int)((r->nrows + r->gram_rows_per - 1) / r->gram_rows_per);
   r->fused_nt = (r->D + 1 + 15) / 16 <= FUSED_MAXNT ? (r->D + 1 + 15) / 16 : 0;
-  std::vector<long long> rows_u((size_t)n_s * nue), rows_n((size_t)n_s * nun), rows_x((size_t)n_s * nxe);
+  std::vector<long long> rows_u((size_t)n_s * nue), rows_n((size_t)n_s * nun), rows_x((size_t)n_s * nxe), rows_e(n_s);
   std::vector<double> hXs((size_t)n_s * nxe), hsr(n_s);
+  std::vector<int> hfs((size_t)n_s * 3);
   for (int k = 0; k < n_s; ++k) {
     const int e = eq_elem[k];
+    for (int f = 0; f < 3; ++f) hfs[(size_t)k * 3 + f] = pr->h_face[(size_t)e * 3 + f];
     for (int i = 0; i < nue; ++i) rows_u[(size_t)k * nue + i] = (long long)e * nue + i;
     for (int i = 0; i < nun; ++i) rows_n[(size_t)k * nun + i] = pr->h_Pn[(size_t)e * nun + i];
     for (int i = 0; i < nxe; ++i) {
@@ -816,6 +845,7 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
       hXs[(size_t)k * nxe + i] = pr->h_X[gi];
     }
     hsr[k] = std::sqrt(eq_rho[k]);
+    rows_e[k] = e;
   }
   ift_status st;
   long long* d_rows = nullptr;
@@ -834,11 +864,16 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
   ALLOC(r->d_Phin_s, (size_t)n_s * nun * n);
   ALLOC(r->d_Psi_s, (size_t)n_s * nxe * std::max(m, 1));
   ALLOC(r->d_X_s, (size_t)n_s * nxe);
+  ALLOC(r->d_face_s, (size_t)n_s * 3);
+  ALLOC(r->d_eta_ref_s, (size_t)n_s);
+  ALLOC(r->d_LiftU, (size_t)n_s * n * (nue + nun));
+  ALLOC(r->d_LiftX, (size_t)n_s * std::max(m, 1) * nxe);
 #undef ALLOC
   bool ok = hipMemcpy(r->d_eq, eq_elem, n_s * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(r->d_rho, eq_rho, n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(r->d_srho, hsr.data(), n_s * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(r->d_X_s, hXs.data(), hXs.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess;
+            hipMemcpy(r->d_X_s, hXs.data(), hXs.size() * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(r->d_face_s, hfs.data(), hfs.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
   auto gather = [&](const double* src, int ncol, const std::vector<long long>& rows, double* dst) {
     if (!ok || ncol == 0) return;
     ok = hipMemcpy(d_rows, rows.data(), rows.size() * sizeof(long long), hipMemcpyHostToDevice) == hipSuccess;
@@ -859,7 +894,15 @@ extern "C" ift_status ift_rom_create(ift_problem* pr, int n, int m, const double
     }
   }
   gather(Psi, m, rows_x, r->d_Psi_s);
+  gather(pr->d_eta_ref, 1, rows_e, r->d_eta_ref_s);
   dfree(d_rows);
+  if (ok) {
+    const long long tot = (long long)n_s * (n * (nue + nun) + m * nxe);
+    hipLaunchKernelGGL(k_lift_bases, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, 0, (const double*)r->d_Phi_s,
+                       (const double*)r->d_Phin_s, (const double*)r->d_Psi_s, nue, nun, nxe, n, m, (long long)n_s,
+                       r->d_LiftU, r->d_LiftX);
+    ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  }
   if (ok) ok = build_point_bases(r);
   if (!ok) {
     ift_rom_destroy(r);
@@ -890,14 +933,16 @@ static EqArgs eq_args(ift_rom* r, const double* mu, const double* w, const doubl
   a.D = r->D;
   a.nrows = r->nrows;
   a.mu = nullptr;
-  a.eq_elem = r->d_eq;
-  a.face = pr->d_face;
+  a.face_s = r->d_face_s;
+  a.eta_ref_s = r->d_eta_ref_s;
   a.rho = r->d_rho;
   a.srho = r->d_srho;
   a.Phi_s = r->d_Phi_s;
   a.Phin_s = r->d_Phin_s;
   a.Psi_s = r->d_Psi_s;
   a.X_s = r->d_X_s;
+  a.LiftU = r->d_LiftU;
+  a.LiftX = r->d_LiftX;
   a.w = w;
   a.tau = tau;
   a.Jt = r->d_Jt;

@@ -33,6 +33,7 @@ struct HdmArgs {
   double* dNdx;
   int* flags;        // [Ne]
   void* pts;         // [Ne] point-data workspace
+  const double* eta_ref;   // [Ne]: distortion of each reference element
   PhysConst pc;
   double kappa, eps;
   int n_elem;
@@ -43,14 +44,16 @@ struct HdmArgs {
 struct EqArgs {
   int n_s, n, m, D;
   long long nrows;       // n_s*nue + n_s
-  const int* eq_elem;    // [n_s]
-  const int* face;       // [Ne][3]
+  const int* face_s;     // [n_s][3]: face codes of the sampled elements
   const double* rho;     // [n_s]
   const double* srho;    // [n_s] sqrt(rho)
   const double* Phi_s;   // [n_s][nue][n]
   const double* Phin_s;  // [n_s][nun][n]
   const double* Psi_s;   // [n_s][nxe][m]
   const double* X_s;     // [n_s][nxe]
+  const double* eta_ref_s;   // [n_s]: distortion of each sampled reference element
+  const double* LiftU;   // [n_s][n][nue + nun]: Phi_s then Phin_s rows, column-major per element
+  const double* LiftX;   // [n_s][m][nxe]: Psi_s, column-major per element
   const double* w;       // [pt][n]
   const double* tau;     // [pt][m]
   const double* mu;      // [pt][2] on the device, or null: use pc
@@ -80,22 +83,33 @@ IFT_DEV PhysConst phys_from_mu(const PhysConst& base, int pde, double bc_scale, 
   return pc;
 }
 
+// Copies one element's point data between LDS (ElemLDS::p, 16-byte aligned)
+// and the point workspace, whose element slots start at multiples of the
+// FP64 point-data size from a 256-byte aligned base: 16-byte words where
+// both sizes are multiples of 16.
+template <class D, class R, int NT>
+IFT_DEV void copy_pts(Pts<D, R>* dst, const Pts<D, R>* src, int tid) {
+  constexpr int A = sizeof(Pts<D, R>) % 16 == 0 && sizeof(Pts<D, double>) % 16 == 0 ? 16 : alignof(Pts<D, R>);
+  copy_obj<Pts<D, R>, NT, A>(dst, src, tid);
+}
+
 // ------------------------------------------------------------------ loaders
-// acc + sum_j row[j] v[j], accumulated in index order.  The loads of a chunk
-// of terms are issued together: summed in a plain loop, each term would wait
-// for its own load (a cache round trip per basis coefficient).
-constexpr int LIFT_CHUNK = 16;
-IFT_DEV double lift_dot(const double* row, const double* v, int n, double acc) {
-  for (int j0 = 0; j0 < n; j0 += LIFT_CHUNK) {
-    double r[LIFT_CHUNK], c[LIFT_CHUNK];
+// acc + sum_j row[j * stride] v[j], accumulated in index order.  The loads
+// of a chunk of CH terms are issued together: summed in a plain loop, each
+// term would wait for its own load (a cache round trip per basis
+// coefficient).  CH trades those round trips against registers.
+template <int CH = 16>
+IFT_DEV double lift_dot(const double* row, int stride, const double* v, int n, double acc) {
+  for (int j0 = 0; j0 < n; j0 += CH) {
+    double r[CH], c[CH];
 #pragma unroll
-    for (int u = 0; u < LIFT_CHUNK; ++u) {
+    for (int u = 0; u < CH; ++u) {
       const int j = min(j0 + u, n - 1);
-      r[u] = row[j];
+      r[u] = row[(long long)j * stride];
       c[u] = v[j];
     }
 #pragma unroll
-    for (int u = 0; u < LIFT_CHUNK; ++u)
+    for (int u = 0; u < CH; ++u)
       if (j0 + u < n) acc += r[u] * c[u];
   }
   return acc;
@@ -103,7 +117,7 @@ IFT_DEV double lift_dot(const double* row, const double* v, int n, double acc) {
 
 template <class D, class R>
 IFT_DEV void load_hdm(ElemLDS<D, R>& s, const HdmArgs& a, int e, int tid, int nthr) {
-  constexpr int ntask = D::NUE + D::NUN + 2 * D::NXE + 3;
+  constexpr int ntask = D::NUE + D::NUN + 2 * D::NXE + 4;
   for (int k = tid; k < ntask; k += nthr) {
     if (k < D::NUE) {
       s.U[k] = R(a.U[(long long)e * D::NUE + k]);
@@ -121,39 +135,98 @@ IFT_DEV void load_hdm(ElemLDS<D, R>& s, const HdmArgs& a, int e, int tid, int nt
       s.X[r] = R(a.X[2 * g + (r & 1)]);
     } else {
       int f = k - D::NUE - D::NUN - 2 * D::NXE;
-      s.face[f] = a.face[e * 3 + f];
+      if (f < 3) s.face[f] = a.face[e * 3 + f];
+      else s.eta_ref = R(a.eta_ref[e]);
     }
   }
   if (tid == 0) s.p.bad = 0;
 }
 
-// Lift U_e = Phi_e w, U_e' = Phi_e' w, x_e = X_e + Psi_e tau from the
-// gathered bases (rows are contiguous in global memory): one thread per row,
-// a serial dot product.  Ends with a barrier: everything it wrote is
-// visible to the block.
-template <class D, class R>
-IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid, int nthr) {
-  const int n = a.n, m = a.m;
-  const double* w = a.w + (long long)pt * n;
-  const double* tau = a.tau + (long long)pt * m;
-  const double* Ph = a.Phi_s + (long long)k * D::NUE * n;
-  const double* Pn = a.Phin_s + (long long)k * D::NUN * n;
-  const double* Ps = a.Psi_s + (long long)k * D::NXE * m;
-  const double* Xs = a.X_s + (long long)k * D::NXE;
-  if (tid < 3) s.face[tid] = a.face[a.eq_elem[k] * 3 + tid];
-  if (tid == 0) s.p.bad = 0;
-  for (int t = tid; t < D::NUE + D::NUN + D::NXE; t += nthr) {
-    if (t < D::NUE + D::NUN) {
-      const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
-      const double acc = lift_dot(row, w, n, 0.0);
-      if (t < D::NUE) s.U[t] = R(acc);
-      else s.Un[t - D::NUE] = R(acc);
-    } else {
-      const int q = t - D::NUE - D::NUN;
-      const double acc = lift_dot(Ps + (long long)q * m, tau, m, Xs[q]);
-      s.x[q] = R(acc);
-      s.X[q] = R(Xs[q]);
+// Buffer resource over nbytes bytes from p (raw, unswizzled, the untyped
+// data format of gfx9); its base and size must be uniform across the wave.
+IFT_DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int nbytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
+}
+
+// acc + sum_j B_j c_j over a column-major block (column j at byte offset
+// j * cstride, this lane's entry at lane_bytes within it), accumulated in
+// index order; with PAIR the lane holds two adjacent entries (16 bytes) and
+// accumulates both, acc2 for the second.  c: the coefficients in LDS, 64
+// slots, zero from n on (n <= 64).  The loads of CH columns (CH divides 64)
+// are in flight together, addressed by one lane offset shared by all of
+// them and a scalar column offset each; the chunk is branch-free: a column
+// past n reloads column n - 1, in bounds, and enters with weight zero, which
+// leaves the sum unchanged.
+template <int CH, bool PAIR = false>
+IFT_DEV void lift_col_dot(__amdgpu_buffer_rsrc_t B, int lane_bytes, int cstride, const double* c, int n,
+                          double& acc, double& acc2) {
+  static_assert(64 % CH == 0, "chunks tile the 64 coefficient slots");
+  for (int j0 = 0; j0 < n; j0 += CH) {
+    double r[CH], r2[CH], cc[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int col = min(j0 + u, n - 1);
+      if constexpr (PAIR) {
+        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(B, lane_bytes, col * cstride, 0);
+        r[u] = __builtin_bit_cast(double, (unsigned long long)q.x | ((unsigned long long)q.y << 32));
+        r2[u] = __builtin_bit_cast(double, (unsigned long long)q.z | ((unsigned long long)q.w << 32));
+      } else {
+        r[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(B, lane_bytes, col * cstride, 0));
+        r2[u] = 0.0;
+      }
+      cc[u] = c[j0 + u];
     }
+    __builtin_amdgcn_sched_barrier(0);   // every load of the chunk issues before the first product
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      acc += r[u] * cc[u];
+      if constexpr (PAIR) acc2 += r2[u] * cc[u];
+    }
+  }
+}
+
+template <class D, class R, int CH = 16>
+IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
+  constexpr int RU = D::NUE + D::NUN;
+  constexpr bool PAIR = RU % 2 == 0;          // two U rows per lane (16-byte loads)
+  constexpr int NU = PAIR ? RU / 2 : RU;      // lanes of the U rows
+  constexpr int XOFF = 64;                    // first thread of the x rows: the second wave
+  static_assert(NU <= 64 && XOFF + D::NXE + 4 <= NTHR_PTS, "U rows in the first wave, the rest in the second");
+  const int n = a.n, m = a.m;
+  const int ku = __builtin_amdgcn_readfirstlane(k);
+  // each wave's coefficient vector (w for the U rows' wave, tau for the x
+  // rows') into its LDS slots, zero-padded to 64, by the whole wave; the
+  // same wave reads it back (LDS operations of a wave complete in order)
+  const int lane = tid & 63;
+  const bool xw = tid >= XOFF;
+  const int nv = xw ? m : n;
+  const double* cv = xw ? a.tau + (long long)pt * m : a.w + (long long)pt * n;
+  double* cl = s.cf[xw ? 1 : 0];
+  cl[lane] = lane < nv ? cv[lane] : 0.0;
+  if (tid < NU) {
+    const auto B = buf_rsrc(a.LiftU + (long long)ku * n * RU, n * RU * 8);
+    const int r0 = PAIR ? 2 * tid : tid;
+    double acc = 0.0, acc2 = 0.0;
+    lift_col_dot<CH, PAIR>(B, r0 * 8, RU * 8, cl, n, acc, acc2);
+    if (r0 < D::NUE) s.U[r0] = R(acc);
+    else s.Un[r0 - D::NUE] = R(acc);
+    if (PAIR) {
+      if (r0 + 1 < D::NUE) s.U[r0 + 1] = R(acc2);
+      else s.Un[r0 + 1 - D::NUE] = R(acc2);
+    }
+  } else if (tid >= XOFF && tid < XOFF + D::NXE) {
+    const int q = tid - XOFF;
+    const double X = a.X_s[(long long)ku * D::NXE + q];
+    const auto B = buf_rsrc(a.LiftX + (long long)ku * m * D::NXE, m * D::NXE * 8);
+    double acc = X, unused = 0.0;
+    lift_col_dot<CH>(B, q * 8, D::NXE * 8, cl, m, acc, unused);
+    s.x[q] = R(acc);
+    s.X[q] = R(X);
+  } else if (tid >= XOFF + D::NXE && tid < XOFF + D::NXE + 3) {
+    s.face[tid - XOFF - D::NXE] = a.face_s[ku * 3 + tid - XOFF - D::NXE];
+  } else if (tid == XOFF + D::NXE + 3) {
+    s.p.bad = 0;
+    s.eta_ref = R(a.eta_ref_s[ku]);
   }
   __syncthreads();
 }
@@ -273,14 +346,14 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
   __syncthreads();
   phase_distortion<D, R>(s, tid, R(a.kappa));
   __syncthreads();
-  copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + e, &s.p, tid);
+  copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + e, &s.p, tid);
 }
 
 // Point data of sampled element k at evaluation point pt (one block).
 template <class D, class R>
 IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R, NTHR_PTS>(s, tid);
-  load_eq<D, R>(s, a, k, pt, tid, NTHR_PTS);
+  load_eq<D, R>(s, a, k, pt, tid);
   __syncthreads();
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
@@ -288,7 +361,7 @@ IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, in
   __syncthreads();
   phase_distortion<D, R>(s, tid, R(a.kappa));
   __syncthreads();
-  copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s.p, tid);
+  copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s.p, tid);
 }
 
 template <class D, class R>
@@ -310,14 +383,14 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
   const int k = k0 + min(h, a.n_s - 1 - k0);
   load_tab<D, R, NTHR_PTS>(s[h], t);
-  load_eq<D, R>(s[h], a, k, pt, t, NTHR_PTS);   // ends with a barrier
+  load_eq<D, R, sizeof(R) == 8 ? 32 : 16>(s[h], a, k, pt, t);   // ends with a barrier; FP32 takes 16-column chunks (three waves per SIMD)
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return pc; }, R(a.eps));
   __syncthreads();
   phase_distortion<D, R>(s[h], t, R(a.kappa));
   __syncthreads();
   if (k == k0 + h)
-    copy_obj<Pts<D, R>, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s[h].p, t);
+    copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s[h].p, t);
 }
 
 // ------------------------------------------------ full-order assembly
@@ -327,7 +400,7 @@ __global__ __launch_bounds__(NTHR) void k_hdm_asm(HdmArgs a) {
   const int e = blockIdx.x;
   const int tid = threadIdx.x;
   load_tab<D, R, NTHR>(s, tid);
-  copy_obj<Pts<D, R>, NTHR>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + e, tid);
+  copy_pts<D, R, NTHR>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + e, tid);
   __syncthreads();
   if constexpr (D::NC == 4) {
     hdm_write_blocks<D, R>(s, a, e, tid, NTHR);
@@ -383,6 +456,7 @@ struct ElemVal {
   int face[3];
   PtsVal<D, R> p;
   R Re[D::NUE];
+  R eta_ref;   // distortion of the reference element
 };
 
 template <class D, class R>
@@ -407,23 +481,23 @@ IFT_DEV void res_group_body(ResShared<D, R>& sh, ElemVal<D, R>& e, const EqArgs&
   const RefTab& tab = sh.tab;
   const int n = a.n, m = a.m;
   if (act) {
-    if (j < 3) e.face[j] = a.face[a.eq_elem[k] * 3 + j];
+    if (j < 3) e.face[j] = a.face_s[k * 3 + j];
     if (j == 0) e.p.bad = 0;
+    if (j == 1) e.eta_ref = R(a.eta_ref_s[k]);
     const double* w = a.w + (long long)pt * n;
     const double* tau = a.tau + (long long)pt * m;
-    const double* Ph = a.Phi_s + (long long)k * D::NUE * n;
-    const double* Pn = a.Phin_s + (long long)k * D::NUN * n;
-    const double* Ps = a.Psi_s + (long long)k * D::NXE * m;
+    constexpr int RU = D::NUE + D::NUN;
+    const double* Lu = a.LiftU + (long long)k * n * RU;
+    const double* Lx = a.LiftX + (long long)k * m * D::NXE;
     const double* Xs = a.X_s + (long long)k * D::NXE;
-    for (int t = j; t < D::NUE + D::NUN + D::NXE; t += RV_LANES) {
-      if (t < D::NUE + D::NUN) {
-        const double* row = t < D::NUE ? Ph + (long long)t * n : Pn + (long long)(t - D::NUE) * n;
-        const double acc = lift_dot(row, w, n, 0.0);
+    for (int t = j; t < RU + D::NXE; t += RV_LANES) {
+      if (t < RU) {
+        const double acc = lift_dot(Lu + t, RU, w, n, 0.0);
         if (t < D::NUE) e.U[t] = R(acc);
         else e.Un[t - D::NUE] = R(acc);
       } else {
-        const int q = t - D::NUE - D::NUN;
-        const double acc = lift_dot(Ps + (long long)q * m, tau, m, Xs[q]);
+        const int q = t - RU;
+        const double acc = lift_dot(Lx + q, D::NXE, tau, m, Xs[q]);
         e.x[q] = R(acc);
         e.X[q] = R(Xs[q]);
       }
@@ -439,7 +513,7 @@ IFT_DEV void res_group_body(ResShared<D, R>& sh, ElemVal<D, R>& e, const EqArgs&
       face_point<D, R, R>(tab, e, r / D::NQF, r % D::NQF, -1, pc);
     } else if (j == D::NQV + 3 * D::NQF) {
       const Tan<R> eta = eta_elem<D, R>(tab, e.x, e.X, R(a.eps), -1);
-      e.p.N = R(a.kappa) * (eta.v - eta_reference<D, R>(tab, e.X));
+      e.p.N = R(a.kappa) * (eta.v - e.eta_ref);
     }
   }
   __syncthreads();
@@ -536,13 +610,13 @@ __global__ __launch_bounds__(RV_THR) void k_hdm_res_rom(HdmRomArgs a) {
     for (int t = j; t < D::NUE + D::NUN + D::NXE; t += RV_LANES) {
       if (t < D::NUE + D::NUN) {
         const long long row = t < D::NUE ? (long long)e * D::NUE + t : (long long)a.Pn[(long long)e * D::NUN + t - D::NUE];
-        const double acc = row >= 0 ? lift_dot(a.Phi + row * n, w, n, 0.0) : 0.0;
+        const double acc = row >= 0 ? lift_dot(a.Phi + row * n, 1, w, n, 0.0) : 0.0;
         if (t < D::NUE) el.U[t] = R(acc);
         else el.Un[t - D::NUE] = R(acc);
       } else {
         const int r = t - D::NUE - D::NUN;
         const long long c = 2LL * a.gn[(long long)e * D::NN + r / 2] + (r & 1);
-        const double acc = lift_dot(a.Psi + c * m, tau, m, a.X[c]);
+        const double acc = lift_dot(a.Psi + c * m, 1, tau, m, a.X[c]);
         el.x[r] = R(acc);
         el.X[r] = R(a.X[c]);
       }
@@ -845,7 +919,7 @@ __global__ __launch_bounds__(NTHR) void k_eq_asm(EqArgs a, const double* Bw, con
     int* dst = reinterpret_cast<int*>(&s.tab);
     for (int i = tid; i < (int)(sizeof(RefTab) / sizeof(int)); i += NTHR) dst[i] = src[i];
   }
-  copy_obj<Pts<D, R>, NTHR>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), tid);
+  copy_pts<D, R, NTHR>(&s.p, reinterpret_cast<const Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), tid);
   __syncthreads();
   const double sq = a.srho[k];
   const long long nrow_e = (long long)a.n_s * D::NUE;
@@ -1791,6 +1865,38 @@ __global__ void k_gather_rows(const double* src, int ncol, const long long* rows
   const int c = (int)(i - r * ncol);
   const long long sr = rows[r];
   dst[i] = sr >= 0 ? src[sr * ncol + c] : 0.0;
+}
+
+// Column-major copies of the gathered bases for the lift: column j of
+// sampled element k holds Phi_e's rows then Phi_e''s rows (LU, [k][j][nue +
+// nun]), and Psi_e's rows (LX, [k][j][nxe]).  One thread per entry.
+__global__ void k_lift_bases(const double* Phi_s, const double* Phin_s, const double* Psi_s, int nue, int nun,
+                             int nxe, int n, int m, long long n_s, double* LU, double* LX) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int ru = nue + nun;
+  const long long nu = n_s * n * ru, nx = n_s * m * nxe;
+  if (i < nu) {
+    const long long k = i / ((long long)n * ru);
+    const int rem = (int)(i - k * n * ru), j = rem / ru, r = rem % ru;
+    LU[i] = r < nue ? Phi_s[(k * nue + r) * n + j] : Phin_s[(k * nun + r - nue) * n + j];
+  } else if (i < nu + nx) {
+    const long long ix = i - nu;
+    const long long k = ix / ((long long)m * nxe);
+    const int rem = (int)(ix - k * m * nxe), j = rem / nxe, r = rem % nxe;
+    LX[ix] = Psi_s[(k * nxe + r) * m + j];
+  }
+}
+
+// Distortion of each reference element (X_e in the mapping; only the mesh
+// and the reference table enter), one thread per element.
+template <class D>
+__global__ __launch_bounds__(256) void k_eta_ref(const double* X, const int* gn, int n_elem, double* out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_elem) return;
+  double Xe[D::NXE];
+#pragma unroll
+  for (int r = 0; r < D::NXE; ++r) Xe[r] = X[2LL * gn[(long long)e * D::NN + r / 2] + (r & 1)];
+  out[e] = eta_reference<D, double>(c_tab[D::P - 1], Xe);
 }
 
 // ------------------------------------------------- LM step (dense, FP64)
