@@ -148,85 +148,116 @@ IFT_DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int nbytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, nbytes, 0x00020000);
 }
 
-// acc + sum_j B_j c_j over a column-major block (column j at byte offset
-// j * cstride, this lane's entry at lane_bytes within it), accumulated in
-// index order; with PAIR the lane holds two adjacent entries (16 bytes) and
-// accumulates both, acc2 for the second.  c: the coefficients in LDS, 64
-// slots, zero from n on (n <= 64).  The loads of CH columns (CH divides 64)
-// are in flight together, addressed by one lane offset shared by all of
-// them and a scalar column offset each; the chunk is branch-free: a column
-// past n reloads column n - 1, in bounds, and enters with weight zero, which
-// leaves the sum unchanged.
+// acc = init + sum_j B_j v_j over a column-major block (column j at byte
+// offset j * cstride, this lane's entry at lane_bytes within it),
+// accumulated in index order; with PAIR the lane holds two adjacent entries
+// (16 bytes) and accumulates both from zero, acc2 for the second.  init
+// enters after the first chunk's loads issue (a load still in flight there
+// costs no wait ahead of them).  Run by a whole wave; only lanes with
+// `own` load (the address unit's time goes by active lanes), the others
+// compute on whatever their registers hold and must drop the result.  The
+// loads of CH columns (CH divides 64) are in flight together, addressed by
+// one lane offset shared by all of them and a scalar column offset each.
+// In chunks of 32, groups of 8 columns wholly past n are skipped (one
+// uniform branch per group); otherwise a column past n reloads column
+// n - 1, in bounds, with weight zero, which leaves the sum unchanged.  The coefficients v (n
+// <= 64) go through cl, 64 LDS slots of this wave: lane j writes v_j (zero
+// from n on) once the first chunk's loads are issued, and the products read
+// them back as broadcasts (LDS operations of a wave complete in order).
 template <int CH, bool PAIR = false>
-IFT_DEV void lift_col_dot(__amdgpu_buffer_rsrc_t B, int lane_bytes, int cstride, const double* c, int n,
-                          double& acc, double& acc2) {
+IFT_DEV void lift_col_dot(__amdgpu_buffer_rsrc_t B, bool own, int lane_bytes, int cstride, const double* v, double* cl,
+                          int n, double init, double& acc, double& acc2) {
   static_assert(64 % CH == 0, "chunks tile the 64 coefficient slots");
+  const int lane = threadIdx.x & 63;
+  acc = 0.0;
+  acc2 = 0.0;
   for (int j0 = 0; j0 < n; j0 += CH) {
+    constexpr int G = CH > 16 ? 8 : CH;   // (grouping smaller chunks costs the batched kernels registers)
     double r[CH], r2[CH], cc[CH];
+    if (own) {
 #pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int col = min(j0 + u, n - 1);
-      if constexpr (PAIR) {
-        const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(B, lane_bytes, col * cstride, 0);
-        r[u] = __builtin_bit_cast(double, (unsigned long long)q.x | ((unsigned long long)q.y << 32));
-        r2[u] = __builtin_bit_cast(double, (unsigned long long)q.z | ((unsigned long long)q.w << 32));
-      } else {
-        r[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(B, lane_bytes, col * cstride, 0));
-        r2[u] = 0.0;
+      for (int u = 0; u < CH; ++u) {
+        if (u % G == 0 && j0 + u >= n) break;
+        const int col = min(j0 + u, n - 1);
+        if constexpr (PAIR) {
+          const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(B, lane_bytes, col * cstride, 0);
+          r[u] = __builtin_bit_cast(double, (unsigned long long)q.x | ((unsigned long long)q.y << 32));
+          r2[u] = __builtin_bit_cast(double, (unsigned long long)q.z | ((unsigned long long)q.w << 32));
+        } else {
+          r[u] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(B, lane_bytes, col * cstride, 0));
+          r2[u] = 0.0;
+        }
       }
-      cc[u] = c[j0 + u];
     }
+    if (j0 == 0) cl[lane] = lane < n ? v[lane] : 0.0;
     __builtin_amdgcn_sched_barrier(0);   // every load of the chunk issues before the first product
+    if (j0 == 0) acc = init;
 #pragma unroll
     for (int u = 0; u < CH; ++u) {
+      if (u % G == 0 && j0 + u >= n) break;
+      cc[u] = cl[j0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      if (u % G == 0 && j0 + u >= n) break;
       acc += r[u] * cc[u];
       if constexpr (PAIR) acc2 += r2[u] * cc[u];
     }
   }
+  if (n <= 0) acc = init;
 }
 
+// Lift U_e = Phi_e w, U_e' = Phi_e' w, x_e = X_e + Psi_e tau for one
+// element of NTHR_PTS threads (two waves): one lane per row, a serial dot
+// product in index order over the column-major copies of the gathered bases,
+// so that the lanes of a wave read adjacent entries of a column.  The first
+// wave takes the U rows (two per lane where their count is even: 16-byte
+// loads), the second the x rows, the face codes, the reference distortion
+// and the flag; every lane of a wave runs the lift (surplus lanes on a
+// clamped row; only the rows' own lanes load), so nothing in it waits
+// behind a divergent branch, and each wave's loads cost one round trip for
+// n <= CH (x rows: m <= 16).  k must be uniform across
+// each wave.  Ends with a barrier: everything it wrote is visible to the
+// block.
 template <class D, class R, int CH = 16>
 IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   constexpr int RU = D::NUE + D::NUN;
   constexpr bool PAIR = RU % 2 == 0;          // two U rows per lane (16-byte loads)
   constexpr int NU = PAIR ? RU / 2 : RU;      // lanes of the U rows
-  constexpr int XOFF = 64;                    // first thread of the x rows: the second wave
-  static_assert(NU <= 64 && XOFF + D::NXE + 4 <= NTHR_PTS, "U rows in the first wave, the rest in the second");
+  static_assert(NTHR_PTS == 128 && NU <= 64 && D::NXE + 4 <= 64, "U rows in the first wave, the rest in the second");
   const int n = a.n, m = a.m;
   const int ku = __builtin_amdgcn_readfirstlane(k);
-  // each wave's coefficient vector (w for the U rows' wave, tau for the x
-  // rows') into its LDS slots, zero-padded to 64, by the whole wave; the
-  // same wave reads it back (LDS operations of a wave complete in order)
   const int lane = tid & 63;
-  const bool xw = tid >= XOFF;
-  const int nv = xw ? m : n;
-  const double* cv = xw ? a.tau + (long long)pt * m : a.w + (long long)pt * n;
-  double* cl = s.cf[xw ? 1 : 0];
-  cl[lane] = lane < nv ? cv[lane] : 0.0;
-  if (tid < NU) {
+  if (tid < 64) {
+    const int r0 = PAIR ? 2 * min(lane, NU - 1) : min(lane, NU - 1);
     const auto B = buf_rsrc(a.LiftU + (long long)ku * n * RU, n * RU * 8);
-    const int r0 = PAIR ? 2 * tid : tid;
-    double acc = 0.0, acc2 = 0.0;
-    lift_col_dot<CH, PAIR>(B, r0 * 8, RU * 8, cl, n, acc, acc2);
-    if (r0 < D::NUE) s.U[r0] = R(acc);
-    else s.Un[r0 - D::NUE] = R(acc);
-    if (PAIR) {
-      if (r0 + 1 < D::NUE) s.U[r0 + 1] = R(acc2);
-      else s.Un[r0 + 1 - D::NUE] = R(acc2);
+    double acc, acc2;
+    lift_col_dot<CH, PAIR>(B, lane < NU, r0 * 8, RU * 8, a.w + (long long)pt * n, s.cf[0], n, 0.0, acc, acc2);
+    if (lane < NU) {
+      if (r0 < D::NUE) s.U[r0] = R(acc);
+      else s.Un[r0 - D::NUE] = R(acc);
+      if (PAIR) {
+        if (r0 + 1 < D::NUE) s.U[r0 + 1] = R(acc2);
+        else s.Un[r0 + 1 - D::NUE] = R(acc2);
+      }
     }
-  } else if (tid >= XOFF && tid < XOFF + D::NXE) {
-    const int q = tid - XOFF;
+  } else {
+    const int q = min(lane, D::NXE - 1);
     const double X = a.X_s[(long long)ku * D::NXE + q];
+    const int fc = a.face_s[ku * 3 + min(max(lane - D::NXE, 0), 2)];
+    const double er = a.eta_ref_s[ku];
     const auto B = buf_rsrc(a.LiftX + (long long)ku * m * D::NXE, m * D::NXE * 8);
-    double acc = X, unused = 0.0;
-    lift_col_dot<CH>(B, q * 8, D::NXE * 8, cl, m, acc, unused);
-    s.x[q] = R(acc);
-    s.X[q] = R(X);
-  } else if (tid >= XOFF + D::NXE && tid < XOFF + D::NXE + 3) {
-    s.face[tid - XOFF - D::NXE] = a.face_s[ku * 3 + tid - XOFF - D::NXE];
-  } else if (tid == XOFF + D::NXE + 3) {
-    s.p.bad = 0;
-    s.eta_ref = R(a.eta_ref_s[ku]);
+    double acc, unused;
+    lift_col_dot<16>(B, lane < D::NXE, q * 8, D::NXE * 8, a.tau + (long long)pt * m, s.cf[1], m, X, acc, unused);
+    if (lane < D::NXE) {
+      s.x[q] = R(acc);
+      s.X[q] = R(X);
+    } else if (lane < D::NXE + 3) {
+      s.face[lane - D::NXE] = fc;
+    } else if (lane == D::NXE + 3) {
+      s.p.bad = 0;
+      s.eta_ref = R(er);
+    }
   }
   __syncthreads();
 }
