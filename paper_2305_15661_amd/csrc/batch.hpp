@@ -175,9 +175,10 @@ __global__ __launch_bounds__(NTHR_PTS, 2) void k_points_batch(const BatchInst* I
 // The same with two listed items per 256-thread block (four-component P2,
 // phase_points_pair); the two may belong to different instances, so each
 // half keeps its physical constants in LDS.  An odd item count leaves the
-// last block one item, computed twice and written once.
+// last block one item, computed twice and written once.  (FP32: three
+// waves per SIMD, the budget its physics fits.)
 template <class D, class R>
-__global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchInst* I, BatchLists L, int n_inst) {
+__global__ __launch_bounds__(2 * NTHR_PTS, sizeof(R) == 4 ? 3 : 2) void k_points_batch2(const BatchInst* I, BatchLists L, int n_inst) {
   __shared__ ElemLDS<D, R> s[2];
   __shared__ PhysConst spc[2];
   const int total = L.cnt[0];
@@ -193,8 +194,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS, 2) void k_points_batch2(const BatchIn
     load_eq<D, R>(s[h], a, k, 0, t);   // ends with a barrier
     phase_points_pair<D, R>(s, tid, [&](int e) -> const PhysConst& { return spc[e]; }, R(a.eps));
     __syncthreads();
-    phase_distortion<D, R>(s[h], t, R(a.kappa));
-    __syncthreads();
+    phase_distortion_eq<D, R>(s[h], a, k, t);
     if (item == i0 + h) copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + k, &s[h].p, t);
     __syncthreads();
   }

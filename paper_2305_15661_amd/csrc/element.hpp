@@ -93,6 +93,7 @@ struct Pts : PtsSrc<D, R> {
   R dHp[3][D::NQF][D::NC][D::NC];  // dH/du+ (interior faces)
   R dHn[3][D::NQF][D::NC][2];      // dH/dn~ (wall state dependence included)
   R dN[D::NXE];                    // dN_e/dx_e
+  R dv[64];                        // EQ kernels: distortion row of the projection, dN_e Psi_e (entries j < m)
   R N;
   int bad;
   int pad_;

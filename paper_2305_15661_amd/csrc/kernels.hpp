@@ -381,6 +381,32 @@ __global__ __launch_bounds__(NTHR_PTS) void k_points_hdm(HdmArgs a) {
 }
 
 // Point data of sampled element k at evaluation point pt (one block).
+// After the point physics and its barrier, for the EQ point kernels (one
+// element of NTHR_PTS threads, two waves): the distortion terms
+// (phase_distortion, first wave) and the distortion row of the projection,
+// dv_j = sum_c dN_c Psi_e[c][j] for j < m (second wave, whose column loads
+// issue while the first wave forms dN).  Ends with a barrier.
+template <class D, class R>
+IFT_DEV void phase_distortion_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int t) {
+  const int m = a.m, j = t - 64;
+  const bool own = j >= 0 && j < m;
+  double ps[D::NXE];
+  if (own) {
+    const double* col = a.LiftX + ((long long)k * m + j) * D::NXE;
+#pragma unroll
+    for (int c = 0; c < D::NXE; ++c) ps[c] = col[c];
+  }
+  phase_distortion<D, R>(s, t, R(a.kappa));
+  __syncthreads();
+  if (own) {
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < D::NXE; ++c) acc += double(s.p.dN[c]) * ps[c];
+    s.p.dv[j] = R(acc);
+  }
+  __syncthreads();
+}
+
 template <class D, class R>
 IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R, NTHR_PTS>(s, tid);
@@ -390,8 +416,7 @@ IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, in
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
   phase_points<D, R, true>(s, tid, pc, R(a.kappa), R(a.eps));
   __syncthreads();
-  phase_distortion<D, R>(s, tid, R(a.kappa));
-  __syncthreads();
+  phase_distortion_eq<D, R>(s, a, k, tid);
   copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s.p, tid);
 }
 
@@ -418,8 +443,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
   phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return pc; }, R(a.eps));
   __syncthreads();
-  phase_distortion<D, R>(s[h], t, R(a.kappa));
-  __syncthreads();
+  phase_distortion_eq<D, R>(s[h], a, k, t);
   if (k == k0 + h)
     copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + ((long long)pt * a.n_s + k), &s[h].p, t);
 }
@@ -1170,7 +1194,7 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
   const Pts<D, R>* P[NP];
   const double* bw[NP];
   const double* bx[NP];
-  double sq[NP], rv[NP], dv[NP];
+  double sq[NP], rv[NP];
   dvec4 acc[NP][MT][NT];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
@@ -1179,17 +1203,10 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
     bw[i] = Bw + (long long)k * O::KWP * (n + 1);
     bx[i] = Bx + (long long)k * O::KXP * (m + 1);
     sq[i] = a.srho[k];
-    // residual entry of row `lane` (row nue: the distortion), distortion
-    // row entry of x-column `lane`
+    // residual entry of row `lane` (row nue: the distortion)
     rv[i] = 0.0;
-    dv[i] = 0.0;
     if (lane < NUE) rv[i] = double(residual_entry_p<D, R>(*P[i], tab, lane));
     else if (lane == NUE) rv[i] = double(P[i]->N);
-    if (lane < m) {
-      const double* Ps = a.Psi_s + (long long)k * D::NXE * m + lane;
-#pragma unroll
-      for (int c = 0; c < D::NXE; ++c) dv[i] += double(P[i]->dN[c]) * Ps[c * m];
-    }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -1273,11 +1290,12 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
   for (int i = 0; i < NP; ++i) {
     const int k = k0 + i;
     // scale by sqrt(rho_e); insert the residual column and the distortion row
+    // (its entry for x-column j: dv_j of the point data)
     double dsrc[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int jd = 16 * nt + li - n;
-      dsrc[nt] = __shfl(dv[i], (jd >= 0 && jd < 64) ? jd : 0);
+      dsrc[nt] = (jd >= 0 && jd < m) ? double(P[i]->dv[jd]) : 0.0;
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -1402,14 +1420,10 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
       const double sq = a.srho[k];
       // residual entry of row `lane` (row nue: the distortion), distortion
       // row entry of x-column `lane`
-      double rv = 0.0, dv = 0.0;
+      double rv = 0.0;
       if (lane < NUE) rv = double(residual_entry_p<D, R>(p, tab, lane));
       else if (lane == NUE) rv = double(p.N);
-      if (lane < m) {
-        const double* Ps = a.Psi_s + (long long)k * D::NXE * m + lane;
-#pragma unroll
-        for (int c = 0; c < D::NXE; ++c) dv += double(p.dN[c]) * Ps[c * m];
-      }
+      const double dv = lane < m ? double(p.dv[lane]) : 0.0;   // distortion row entry of x-column `lane`
       // M_e projection: columns [0, n) from Aw * Bw, [n, D) from Ax * Bx
       dvec4 acc[MT][NT];
 #pragma unroll

@@ -179,16 +179,10 @@ IFT_DEV void fused_body_mixed(FusedShared<D, float, NT>& sh, const EqArgs& a, co
     if (k >= a.n_s) continue;
     const Pts<D, float>& p = S.p;
     const float sq = float(a.srho[k]);
-    float rv = 0.f, dv = 0.f;
+    float rv = 0.f;
     if (lane < NUE) rv = residual_entry_p<D, float>(p, tab, lane);
     else if (lane == NUE) rv = p.N;
-    if (lane < m) {
-      const double* Ps = a.Psi_s + (long long)k * D::NXE * m + lane;
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < D::NXE; ++c) acc += double(p.dN[c]) * Ps[c * m];
-      dv = float(acc);
-    }
+    const float dv = lane < m ? p.dv[lane] : 0.f;   // distortion row entry of x-column `lane`
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
