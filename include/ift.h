@@ -216,7 +216,7 @@ ift_status eq_assemble_jacobian(ift_rom* rom, const double* mu, const double* w,
  * Jobj, g, H, n_bad are DEVICE.  Every call on a device shares its array:
  * calls that overlap on one device (other streams, other threads) race and
  * must be serialised by the caller.  IFT_ESCRATCH when the ROM's workspace
- * exceeds the array (about 5,000 sampled elements of a P2 Euler ROM),
+ * exceeds the array (about 4,900 sampled elements of a P2 Euler ROM),
  * IFT_EINVAL on null outputs or a ROM whose D + 1 exceeds 48. */
 #define IFT_NOALLOC_SCRATCH_BYTES (32u << 20)
 ift_status eq_assemble_jacobian_noalloc(ift_rom* rom, const double* mu, const double* w, const double* tau,
