@@ -218,6 +218,7 @@ __global__ __launch_bounds__(NTHR, (fused_blocks_per_cu<D, NT>())) void k_fused_
     f.part = bi.part;
     f.part_bad = bi.part_bad;
     f.rows = 0;
+    f.pts2 = 0;
     fused_body<D, R, NT>(sh, bi.a, bi.Bw, bi.Bx, f, blk, 0);
   }
 }

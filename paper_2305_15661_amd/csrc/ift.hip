@@ -735,13 +735,26 @@ struct FusedLayout {
   int E, nblk;
 };
 static constexpr long long FUSED_TARGET_WAVES = 2048;   // waves resident at two per SIMD
-static FusedLayout fused_layout(const ift_rom* r, int n_pts) {
-  const long long ns = r->n_s;
-  int E = (int)std::max<long long>(1, (ns * n_pts + FUSED_TARGET_WAVES - 1) / FUSED_TARGET_WAVES);
+static FusedLayout fused_layout_units(long long ns, long long groups) {
+  int E = (int)std::max<long long>(1, (ns * groups + FUSED_TARGET_WAVES - 1) / FUSED_TARGET_WAVES);
   int nblk = (int)((ns + 4LL * E - 1) / (4LL * E));
   if (nblk > 8) nblk = (nblk + 7) / 8 * 8;
   E = (int)((ns + 4LL * nblk - 1) / (4LL * nblk));
   return {E, nblk};
+}
+static FusedLayout fused_layout(const ift_rom* r, int n_pts) { return fused_layout_units(r->n_s, n_pts); }
+
+// Multi-point FP64 calls of the four-component P2 discretisation take two
+// points of an element per wave (k_eq_fused_pts2): the work items are
+// (element, point pair), and the blocks of a pair write one partial per
+// point.
+static bool fused_pts2_used(const ift_rom* r, int n_pts, bool rows) {
+  const ift_problem* pr = r->prob;
+  return !rows && n_pts >= 2 && r->precision == IFT_FP64 && pr->nc == 4 && pr->p == 2 && r->fused_nt >= 1 &&
+         r->fused_nt <= 2;
+}
+static FusedLayout fused_layout_pts2(const ift_rom* r, int n_pts) {
+  return fused_layout_units(r->n_s, (n_pts + 1) / 2);
 }
 
 // (Re)allocates every workspace that scales with the number of evaluation
@@ -787,7 +800,10 @@ static ift_status reserve_points(ift_rom* r, int max_pts) {
   if (hipMalloc(&r->d_pts, P * ns * pts_bytes(pr)) != hipSuccess) return IFT_ENOMEM;
   if (r->fused_nt > 0) {
     size_t nb = 0;
-    for (int q = 1; q <= max_pts; ++q) nb = std::max(nb, (size_t)q * fused_layout(r, q).nblk);
+    for (int q = 1; q <= max_pts; ++q) {
+      nb = std::max(nb, (size_t)q * fused_layout(r, q).nblk);
+      if (fused_pts2_used(r, q, false)) nb = std::max(nb, (size_t)q * fused_layout_pts2(r, q).nblk);
+    }
     const size_t nh = (size_t)r->fused_nt * (r->fused_nt + 1) / 2;
     if ((st = dalloc(&r->d_fpart, nb * nh * 256)) != IFT_OK || (st = dalloc(&r->d_fbad, nb * 2)) != IFT_OK) return st;
   }
@@ -978,6 +994,13 @@ struct EqLaunch {
   const short* Bx16;
   template <class D, int NT>
   void fused() {
+    if constexpr (std::is_same<R, double>::value && fused_pts2_ok<D, NT>()) {
+      if (fa->pts2) {
+        hipLaunchKernelGGL((k_eq_fused_pts2<D, NT>), dim3(fa->nblk, (n_pts + 1) / 2), dim3(NTHR), 0, st, a, Bw, Bx,
+                           *fa, n_pts);
+        return;
+      }
+    }
     if constexpr (std::is_same<R, float>::value) {
       if (Bw16) {
         hipLaunchKernelGGL((k_eq_fused_mixed<D, NT>), dim3(fa->nblk, n_pts), dim3(NTHR), 0, st, a, Bw16, Bx16, *fa);
@@ -1034,13 +1057,15 @@ static FusedWork rom_fused_work(ift_rom* r) { return {r->d_fpart, r->d_fbad, r->
 // rows of J~ and F~ in the workspace (d_Jt, d_Ft).
 static ift_status eq_jacobian_fused(ift_rom* r, const EqArgs& a, int n_pts, double* H, double* g, double* Jobj,
                                     int* n_bad, bool rows, hipStream_t stream, const FusedWork& w) {
-  const FusedLayout L = fused_layout(r, n_pts);
+  const bool pts2 = fused_pts2_used(r, n_pts, rows);
+  const FusedLayout L = pts2 ? fused_layout_pts2(r, n_pts) : fused_layout(r, n_pts);
   FusedArgs fa;
   fa.E = L.E;
   fa.nblk = L.nblk;
   fa.part = w.part;
   fa.part_bad = w.part_bad;
   fa.rows = rows ? 1 : 0;
+  fa.pts2 = pts2 ? 1 : 0;
   ift_status s = dispatch_eq(r, a, true, n_pts, stream, &fa);
   if (s != IFT_OK) return s;
   const int D1 = r->D + 1;

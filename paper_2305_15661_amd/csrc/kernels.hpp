@@ -1035,6 +1035,7 @@ struct FusedArgs {
   double* part;       // [pt][nblk][NT(NT+1)/2][256]   (register-major tiles)
   int* part_bad;      // [pt][nblk][2]  (count, OR of the invalid flags)
   int rows;           // also store the rows of J~ and F~ (Jt, Ft)
+  int pts2;           // stacked points (k_eq_fused_pts2): blocks per point pair
 };
 
 template <class D, class R>
@@ -1346,6 +1347,49 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
   }
 }
 
+// The block partial of evaluation point pt: the waves' Gram tiles h added
+// in wave order through LDS (the slots' space: callers have finished with
+// the point data), and the invalid-flag count and OR of the waves.
+template <class D, class R, int NT>
+IFT_DEV void fused_write_partial(FusedShared<D, R, NT>& sh, const FusedArgs& f, const dvec4 (&h)[NT * (NT + 1) / 2],
+                                 int nbad, int bor, int pt, int blk) {
+  constexpr int NH = NT * (NT + 1) / 2;
+  auto& u = sh.u;
+  auto& sbad = sh.sbad;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  __syncthreads();
+  if (lane == 0) {
+    sbad[wave][0] = nbad;
+    sbad[wave][1] = bor;
+  }
+  double* part = f.part + ((long long)pt * f.nblk + blk) * NH * 256;
+#pragma unroll
+  for (int t = 0; t < NH; ++t) {
+    if (wave > 0)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) u.red[wave - 1][v * 64 + lane] = h[t][v];
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double x = h[t][v];
+#pragma unroll
+        for (int w = 0; w < NTHR / 64 - 1; ++w) x += u.red[w][v * 64 + lane];
+        part[t * 256 + v * 64 + lane] = x;
+      }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int c = 0, o = 0;
+    for (int w = 0; w < NTHR / 64; ++w) {
+      c += sbad[w][0];
+      o |= sbad[w][1];
+    }
+    f.part_bad[((long long)pt * f.nblk + blk) * 2] = c;
+    f.part_bad[((long long)pt * f.nblk + blk) * 2 + 1] = o;
+  }
+}
+
 // One block of the fused assembly: sampled elements [4E blk, 4E (blk + 1))
 // at evaluation point pt; writes the block's partial.  The table must be
 // loaded; the first barrier inside makes it visible.
@@ -1557,38 +1601,250 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
       if (f.rows && lane == 0) a.flags[(long long)pt * a.n_s + k] = bad;
     }
   }
-  // add the four waves in wave order; one partial per block
-  __syncthreads();
-  if (lane == 0) {
-    sbad[wave][0] = nbad;
-    sbad[wave][1] = bor;
+  fused_write_partial<D, R, NT>(sh, f, h, nbad, bor, pt, blk);
+}
+
+// ------------------------------------ multi-point calls: stacked points
+// The evaluation points of a call share each sampled element's point bases.
+// For a multi-point FP64 call a wave takes each of its elements at two
+// points p0 = 2 pp and p1 = 2 pp + 1 together: the two points' 2 nue
+// residual rows fill the MFMA row tiles (three for Euler P2, where two
+// elements at one point take four, their distortion rows padding a tile
+// each), and the B operands serve both.  A point's distortion row enters its
+// Gram as a k-block of its own after its residual rows: the k-blocks of
+// every element and point are those of the one-point kernel in the same
+// order, so each element's M_e and Gram term are the same; only the grouping
+// of elements into waves and blocks differs.
+template <class D, int NT>
+constexpr bool fused_pts2_ok() {
+  return D::NC == 4 && NT <= 2 && D::NUE % 4 == 0 && (2 * D::NUE) % 16 == 0 &&
+         (2 * D::NUE) / 16 < 2 * ((D::NUE + 1 + 15) / 16);
+}
+
+// Element k at the points in the wave's slots 0 and 1 (the slot-1 data may
+// repeat slot 0: a lone last point, whose h1 the caller drops).
+template <class D, int NT>
+IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, const EqArgs& a, const double* Bw, const double* Bx,
+                             int k, dvec4 (&h0)[NT * (NT + 1) / 2], dvec4 (&h1)[NT * (NT + 1) / 2], int (&nbad)[2],
+                             int (&bor)[2]) {
+  static_assert(fused_pts2_ok<D, NT>(), "stacked points");
+  using O = EqOp<D>;
+  using R = double;
+  constexpr int NUE = D::NUE;
+  constexpr int MT = 2 * NUE / 16;                 // row tiles of the two points' residual rows
+  constexpr int KWS = O::KWP / 4, KXS = O::KXP / 4;
+  const RefTab& tab = sh.tab;
+  const int n = a.n, m = a.m, Dd = a.D;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int kl = lane >> 4, li = lane & 15;
+  const int KS = KWS + (m > 0 ? KXS : 0);
+  const Pts<D, R>* P0 = &sh.u.w[wave][0].p;
+  const Pts<D, R>* P1 = &sh.u.w[wave][1].p;
+  // per-lane row constants: row 16 mt + li is row lr of point p
+  const Pts<D, R>* Pm[MT];
+  int ri[MT], rc[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int row = 16 * mt + li, p = row / NUE, lr = row - p * NUE;
+    Pm[mt] = p ? P1 : P0;
+    ri[mt] = lr / D::NC;
+    rc[mt] = lr % D::NC;
   }
-  double* part = f.part + ((long long)pt * f.nblk + blk) * NH * 256;
+  int cw[NT], cx[NT];
+  bool won[NT], xon[NT];
 #pragma unroll
-  for (int t = 0; t < NH; ++t) {
-    if (wave > 0)
+  for (int nt = 0; nt < NT; ++nt) {
+    const int c = 16 * nt + li, jx = c - n;
+    cw[nt] = c < n ? c : n;
+    cx[nt] = (jx >= 0 && jx < m) ? jx : m;
+    won[nt] = 16 * nt < n;
+    xon[nt] = 16 * nt + 16 > n && 16 * nt < n + m;
+  }
+  const double* bw = Bw + (long long)k * O::KWP * (n + 1);
+  const double* bx = Bx + (long long)k * O::KXP * (m + 1);
+  const double sq = a.srho[k];
+  // residual entry of row `lane` of each point
+  const double rv0 = lane < NUE ? double(residual_entry_p<D, R>(*P0, tab, lane)) : 0.0;
+  const double rv1 = lane < NUE ? double(residual_entry_p<D, R>(*P1, tab, lane)) : 0.0;
+  dvec4 acc[MT][NT];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) u.red[wave - 1][v * 64 + lane] = h[t][v];
-    __syncthreads();
-    if (wave == 0)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double x = h[t][v];
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = dvec4{0.0, 0.0, 0.0, 0.0};
+  double bc[NT];
+  auto bload = [&](int st) {
+    st = st < KS ? st : KS - 1;
+    const bool xs = st >= KWS;
+    const int r = 4 * (xs ? st - KWS : st) + kl;
+    const double* base = xs ? bx + (long long)r * (m + 1) : bw + (long long)r * (n + 1);
 #pragma unroll
-        for (int w = 0; w < NTHR / 64 - 1; ++w) x += u.red[w][v * 64 + lane];
-        part[t * 256 + v * 64 + lane] = x;
+    for (int nt = 0; nt < NT; ++nt) bc[nt] = base[xs ? cx[nt] : cw[nt]];
+  };
+  auto mfmas = [&](const double* av, const bool* on) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      if (on[nt]) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bc[nt], acc[mt][nt], 0, 0, 0);
       }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    int c = 0, o = 0;
-    for (int w = 0; w < NTHR / 64; ++w) {
-      c += sbad[w][0];
-      o |= sbad[w][1];
     }
-    f.part_bad[((long long)pt * f.nblk + blk) * 2] = c;
-    f.part_bad[((long long)pt * f.nblk + blk) * 2 + 1] = o;
+  };
+  bload(0);
+#pragma unroll 1
+  for (int q = 0; q < D::NQV; ++q) {
+    double av[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) av[mt] = aw_vol<D, R>(tab, *Pm[mt], ri[mt], rc[mt], q, kl);
+    mfmas(av, won);
+    bload(q + 1);
   }
+#pragma unroll 1
+  for (int pl = 0; pl < 2; ++pl) {
+#pragma unroll 1
+    for (int fq = 0; fq < 3 * D::NQF; ++fq) {
+      double av[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        av[mt] = aw_face<D, R>(tab, *Pm[mt], ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl);
+      mfmas(av, won);
+      bload(D::NQV + 3 * D::NQF * pl + fq + 1);
+    }
+  }
+  if (m > 0) {
+#pragma unroll 1
+    for (int q = 0; q < D::NQV; ++q) {
+      double av[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) av[mt] = ax_vol<D, R>(tab, *Pm[mt], ri[mt], rc[mt], q, kl);
+      mfmas(av, xon);
+      bload(KWS + q + 1);
+    }
+#pragma unroll 1
+    for (int ks = 0; ks < KXS - D::NQV; ++ks) {
+      const int cf0 = 4 * ks + kl;
+      const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
+      const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
+      double av[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) av[mt] = ax_tail<D, R>(tab, *Pm[mt], ri[mt], rc[mt], cf) * cm;
+      mfmas(av, xon);
+      bload(KWS + D::NQV + ks + 1);
+    }
+  }
+  // scale by sqrt(rho_e) and insert the residual column.  The row's point
+  // picks between two shuffled registers (a select, not a blend: a
+  // non-finite residual of one point must not reach the other's rows).
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * mt + kl + 4 * v, p = row / NUE, lr = row - p * NUE;
+      const double r0 = __shfl(rv0, lr), r1 = __shfl(rv1, lr);
+      const double rsrc = p ? r1 : r0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int c = 16 * nt + li;
+        double x = sq * acc[mt][nt][v];
+        if (c == Dd) x = sq * rsrc;
+        acc[mt][nt][v] = x;
+      }
+    }
+  // Gram: the k-blocks of rows 4v..4v+3 of tile mt, each within one point,
+  // then each point's distortion row [0, dN_e Psi_e, N_e] as a k-block
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int p = (16 * mt + 4 * v) / NUE;
+      int t = 0;
+#pragma unroll
+      for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+        for (int tb = ta; tb < NT; ++tb, ++t) {
+          if (p == 0) h0[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[mt][ta][v], acc[mt][tb][v], h0[t], 0, 0, 0);
+          else h1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[mt][ta][v], acc[mt][tb][v], h1[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const Pts<D, R>* Pp = p ? P1 : P0;
+    const double Nv = double(Pp->N);
+    double dk[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int c = 16 * nt + li, jd = c - n;
+      const bool xd = kl == 0 && jd >= 0 && jd < m;
+      const double dvv = double(Pp->dv[xd ? jd : 0]);
+      // every load executes; the entry is the exact blend of the two
+      const double sx = xd ? 1.0 : 0.0, sn = (kl == 0 && c == Dd) ? 1.0 : 0.0;
+      dk[nt] = sq * (dvv * sx + Nv * sn);
+    }
+    int t = 0;
+#pragma unroll
+    for (int ta = 0; ta < NT; ++ta)
+#pragma unroll
+      for (int tb = ta; tb < NT; ++tb, ++t) {
+        if (p == 0) h0[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(dk[ta], dk[tb], h0[t], 0, 0, 0);
+        else h1[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(dk[ta], dk[tb], h1[t], 0, 0, 0);
+      }
+  }
+  const int b0 = P0->bad, b1 = P1->bad;
+  nbad[0] += b0 != 0;
+  bor[0] |= b0;
+  nbad[1] += b1 != 0;
+  bor[1] |= b1;
+}
+
+// One block: sampled elements [4E blk, 4E (blk + 1)) at points 2 pp and
+// 2 pp + 1 (a lone last point is taken twice and written once); writes the
+// block's partial of each point.  The table must be loaded; the first
+// barrier inside makes it visible.
+template <class D, int NT>
+IFT_DEV void fused_pts2_body(FusedShared<D, double, NT>& sh, const EqArgs& a, const double* Bw, const double* Bx,
+                             const FusedArgs& f, int blk, int pp, int n_pts) {
+  constexpr int NH = NT * (NT + 1) / 2;
+  using PR = PtsRegs<D, double>;
+  const int p0 = 2 * pp, p1 = min(2 * pp + 1, n_pts - 1);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  dvec4 h0[NH], h1[NH];
+#pragma unroll
+  for (int t = 0; t < NH; ++t) h0[t] = h1[t] = dvec4{0.0, 0.0, 0.0, 0.0};
+  int nbad[2] = {0, 0}, bor[2] = {0, 0};
+  const int kbeg = (blk * (NTHR / 64) + wave) * f.E;
+  const Pts<D, double>* pb0 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p0 * a.n_s;
+  const Pts<D, double>* pb1 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p1 * a.n_s;
+  // the point data of the next element are loaded into registers while the
+  // current one is assembled; each wave owns its two slots
+  typename PR::W pre[2][PR::PER];
+  if (f.E > 0 && kbeg < a.n_s) {
+    pts_regs_load<D, double>(pre[0], pb0 + kbeg, lane);
+    pts_regs_load<D, double>(pre[1], pb1 + kbeg, lane);
+  }
+  __syncthreads();   // the table is loaded
+  for (int e = 0; e < f.E; ++e) {
+    const int k = kbeg + e;
+    if (k >= a.n_s) break;
+    wave_sync();     // the slots' previous contents are consumed
+    pts_regs_store<D, double>(pre[0], &sh.u.w[wave][0].p, lane);
+    pts_regs_store<D, double>(pre[1], &sh.u.w[wave][1].p, lane);
+    if (e + 1 < f.E && k + 1 < a.n_s) {
+      pts_regs_load<D, double>(pre[0], pb0 + k + 1, lane);
+      pts_regs_load<D, double>(pre[1], pb1 + k + 1, lane);
+    }
+    wave_sync();
+    fused_elem_pts2<D, NT>(sh, a, Bw, Bx, k, h0, h1, nbad, bor);
+  }
+  fused_write_partial<D, double, NT>(sh, f, h0, nbad[0], bor[0], p0, blk);
+  if (p1 != p0) fused_write_partial<D, double, NT>(sh, f, h1, nbad[1], bor[1], p1, blk);
+}
+
+template <class D, int NT>
+__global__ __launch_bounds__(NTHR, 2) void k_eq_fused_pts2(EqArgs a, const double* Bw, const double* Bx, FusedArgs f,
+                                                            int n_pts) {
+  __shared__ FusedShared<D, double, NT> sh;
+  fused_load_tab<D, double, NT>(sh, threadIdx.x);
+  fused_pts2_body<D, NT>(sh, a, Bw, Bx, f, blockIdx.x, blockIdx.y, n_pts);
 }
 
 template <class D, class R, int NT>
@@ -1602,6 +1858,26 @@ __global__ __launch_bounds__(NTHR, (fused_blocks_per_cu<D, NT>())) void k_eq_fus
 // augmented Gram (H, g and the objective); its 16 thread groups take the
 // blocks q, q + 16, ... and are then added in group order (fixed order).
 // The extra last workgroup reduces the invalid flags.
+// Count and OR of the invalid flags of nblk block partials (pairs in pb),
+// by one whole wave: lane l takes blocks l, l + 64, ... and the lanes
+// combine by shuffles (integers: the order does not matter).  Every lane
+// ends with the totals.
+IFT_DEV void flags_of_blocks(const int* pb, int nblk, int& c, int& o) {
+  const int lane = threadIdx.x & 63;
+  int cc = 0, oo = 0;
+  for (int b = lane; b < nblk; b += 64) {
+    cc += pb[2 * b];
+    oo |= pb[2 * b + 1];
+  }
+#pragma unroll
+  for (int sh = 32; sh > 0; sh >>= 1) {
+    cc += __shfl_xor(cc, sh);
+    oo |= __shfl_xor(oo, sh);
+  }
+  c = cc;
+  o = oo;
+}
+
 IFT_DEV void fused_final_body(const double* part, const int* part_bad, int nblk, int NT, int D, double* H, double* g,
                               double* Jobj, int* n_bad, int* flag_or, int bx, int pt, double (*red)[GF_ENT]) {
   const int tid = threadIdx.x;
@@ -1611,16 +1887,22 @@ IFT_DEV void fused_final_body(const double* part, const int* part_bad, int nblk,
   const int nbe = (nent + GF_ENT - 1) / GF_ENT;
   const int* pb = part_bad + (long long)pt * nblk * 2;
   if (bx == nbe) {
-    if (tid == 0) {
-      int c = 0, o = 0;
-      for (int b = 0; b < nblk; ++b) {
-        c += pb[2 * b];
-        o |= pb[2 * b + 1];
+    if (tid < 64) {
+      int c, o;
+      flags_of_blocks(pb, nblk, c, o);
+      if (tid == 0) {
+        if (n_bad) n_bad[pt] = c;
+        if (flag_or) flag_or[pt] = o;
       }
-      if (n_bad) n_bad[pt] = c;
-      if (flag_or) flag_or[pt] = o;
     }
     return;
+  }
+  // the workgroup of the objective entry (the last) needs the OR too; its
+  // thread is in the first wave
+  int obad = 0;
+  if (bx == (nent - 1) / GF_ENT && tid < 64) {
+    int c;
+    flags_of_blocks(pb, nblk, c, obad);
   }
   const int el = tid % GF_ENT, q = tid / GF_ENT;
   const int e = bx * GF_ENT + el;
@@ -1649,9 +1931,7 @@ IFT_DEV void fused_final_body(const double* part, const int* part_bad, int nblk,
   } else if (i < D) {
     g[(long long)pt * D + i] = v;
   } else {
-    int o = 0;   // objective; +inf when any sampled element is invalid
-    for (int b = 0; b < nblk; ++b) o |= pb[2 * b + 1];
-    Jobj[pt] = o ? __builtin_inf() : 0.5 * v;
+    Jobj[pt] = obad ? __builtin_inf() : 0.5 * v;   // objective; +inf when any sampled element is invalid
   }
 }
 

@@ -277,6 +277,37 @@ def test_batched_points_match_single_calls_and_oracle(which, request):
     assert all(np.isinf(J[k]) == (nb_o[k] > 0) for k in range(P))
 
 
+@pytest.mark.parametrize("P", [2, 7])
+def test_batched_points_pairs_and_lone_point(P, euler_case):
+    """Multi-point FP64 calls of the P2 Euler ROM take two points of an element
+    per wave; an odd point count leaves a lone last point.  Every point
+    against its single call and the oracle."""
+    import torch
+    case = euler_case
+    wl, r, d = case.wl, case.rom, case.dev
+    idx = [3, 0, 11, 5, 15, 8, 1][:P]
+    _say(f"batched eq assembly {wl.name} x{P} (stacked points)")
+    r.reserve(P)
+    mu2 = np.zeros((P, 2))
+    mu2[:, :wl.mus.shape[1]] = wl.mus[idx]
+    MU, W, T = _t(mu2, d), _t(wl.w_eval[idx], d), _t(wl.tau_eval[idx], d)
+    J, G, H = _z(P, d), _z(P * r.D, d), _z(P * r.D * r.D, d)
+    nb = _z(P, d, torch.int32)
+    r.eq_assemble_jacobian_batch(MU, W, T, J, G, H, nb)
+    torch.cuda.synchronize()
+    J, G, H = J.cpu().numpy(), G.cpu().numpy().reshape(P, r.D), H.cpu().numpy().reshape(P, r.D, r.D)
+    for j, k in enumerate(idx):
+        single = _eq_gpu(case, wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
+        oj = case.orom.jacobian(wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
+        assert rel(G[j], single["g"]) < 1e-14 and rel(H[j], single["H"]) < 1e-14
+        assert rel(G[j], oj["g"]) < 1e-12 and rel(H[j], oj["H"]) < 1e-12
+        if np.isinf(oj["J"]):
+            assert np.isinf(J[j])
+        else:
+            assert abs(J[j] - oj["J"]) <= 1e-12 * oj["J"]
+        assert nb.cpu().numpy()[j] == single["n_bad"]
+
+
 @pytest.mark.parametrize("which", ["tiny_case", "st_case"])
 def test_gauss_newton_steps_parity(which, request):
     """Twenty steps from the plain start; each GPU step is compared with the
