@@ -747,11 +747,12 @@ static FusedLayout fused_layout(const ift_rom* r, int n_pts) { return fused_layo
 // Multi-point FP64 calls of the four-component P2 discretisation take two
 // points of an element per wave (k_eq_fused_pts2): the work items are
 // (element, point pair), and the blocks of a pair write one partial per
-// point.
+// point.  Its iterations pair w and x steps (m > 0), and its B ring holds
+// both stripes of an iteration in one 1 KB slot (n + m <= 30).
 static bool fused_pts2_used(const ift_rom* r, int n_pts, bool rows) {
   const ift_problem* pr = r->prob;
   return !rows && n_pts >= 2 && r->precision == IFT_FP64 && pr->nc == 4 && pr->p == 2 && r->fused_nt >= 1 &&
-         r->fused_nt <= 2;
+         r->fused_nt <= 2 && r->m > 0 && r->n + r->m <= 30;
 }
 static FusedLayout fused_layout_pts2(const ift_rom* r, int n_pts) {
   return fused_layout_units(r->n_s, (n_pts + 1) / 2);
@@ -996,8 +997,15 @@ struct EqLaunch {
   void fused() {
     if constexpr (std::is_same<R, double>::value && fused_pts2_ok<D, NT>()) {
       if (fa->pts2) {
-        hipLaunchKernelGGL((k_eq_fused_pts2<D, NT>), dim3(fa->nblk, (n_pts + 1) / 2), dim3(NTHR), 0, st, a, Bw, Bx,
-                           *fa, n_pts);
+        if constexpr (NT == 2) {
+          if (pts2_tiles<NT>(a.n, a.m) == PTS2_TILES_N17) {
+            hipLaunchKernelGGL((k_eq_fused_pts2<D, NT, PTS2_TILES_N17>), dim3(fa->nblk, (n_pts + 1) / 2), dim3(NTHR),
+                               0, st, a, Bw, Bx, *fa, n_pts);
+            return;
+          }
+        }
+        hipLaunchKernelGGL((k_eq_fused_pts2<D, NT, pts2_tiles_all<NT>()>), dim3(fa->nblk, (n_pts + 1) / 2), dim3(NTHR),
+                           0, st, a, Bw, Bx, *fa, n_pts);
         return;
       }
     }

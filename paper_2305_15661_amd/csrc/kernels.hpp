@@ -76,8 +76,10 @@ IFT_DEV PhysConst phys_from_mu(const PhysConst& base, int pde, double bc_scale, 
   } else {
     const double M = mu[0], a = mu[1] * (M_PI / 180.0), c = sqrt(base.gamma);
     pc.uinf[0] = 1.0;
-    pc.uinf[1] = M * c * cos(a);
-    pc.uinf[2] = M * c * sin(a);
+    double sa, ca;
+    sincos(a, &sa, &ca);   // one shared argument reduction
+    pc.uinf[1] = M * c * ca;
+    pc.uinf[2] = M * c * sa;
     pc.uinf[3] = 1.0 / (base.gamma - 1.0) + 0.5 * base.gamma * M * M;
   }
   return pc;
@@ -799,6 +801,12 @@ IFT_DEV double aw_vol(const RefTab& t, const Pts<D, R>& p, int i, int c, int q, 
                      double(p.gp[q][i][1]) * double(p.Af[q][c][1][cc]));
 }
 
+// The same with the side fixed at compile time: one load, no blend.
+template <bool PLUS, class D, class R>
+IFT_DEV double aw_face_s(const RefTab& t, const Pts<D, R>& p, int i, int c, int f, int q, int cc) {
+  return t.wl[i][f][q] * double(PLUS ? p.dHp[f][q][c][cc] : p.dHm[f][q][c][cc]);
+}
+
 template <class D, class R>
 IFT_DEV double aw_face(const RefTab& t, const Pts<D, R>& p, int i, int c, bool plus, int f, int q, int cc) {
   const double hp = double(p.dHp[f][q][c][cc]);
@@ -823,6 +831,28 @@ IFT_DEV double ax_face(const RefTab& t, const Pts<D, R>& p, int i, int c, int f,
   // d/dt_d of n~ = (t_y, -t_x)
   const double h0 = double(p.dHn[f][q][c][0]), h1 = double(p.dHn[f][q][c][1]);
   return t.wl[i][f][q] * pick(-h1, h0, d == 0);
+}
+
+// ax_vol and ax_tail for the four-component discretisations with the
+// lane's choice of operand made on the index (one load each; the lane's ab,
+// d and cf are fixed over a kernel): the same values, in the same order of
+// operations, as the blends above.
+template <class D, class R>
+IFT_DEV double ax_vol_i(const RefTab& t, const Pts<D, R>& p, int i, int c, int q, int ab) {
+  static_assert(D::PDE != PDE_BURGERS, "no source term");
+  const double sgn = (ab == 0 || ab == 3) ? -1.0 : 1.0;
+  const double f = double(p.fv[q][c][ab < 2 ? 1 : 0]);
+  const double d = t.dphiv[q][i][(ab & 1) ? 0 : 1];
+  return (sgn * t.wv[q]) * f * d;
+}
+template <class D, class R>
+IFT_DEV double ax_tail_i(const RefTab& t, const Pts<D, R>& p, int i, int c, int cf) {
+  using O = EqOp<D>;
+  static_assert(O::KXQ == 0, "no source-position rows");
+  const int cff = cf < O::KXF ? cf : O::KXF - 1;
+  const int f = cff / (2 * D::NQF), q = (cff >> 1) % D::NQF, d = cff & 1;
+  const double h = double(p.dHn[f][q][c][d == 0 ? 1 : 0]);
+  return t.wl[i][f][q] * (d == 0 ? -h : h);
 }
 
 // Column cf of the rows after the volume block of Ax: the face rows
@@ -1615,17 +1645,116 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
 // every element and point are those of the one-point kernel in the same
 // order, so each element's M_e and Gram term are the same; only the grouping
 // of elements into waves and blocks differs.
+// Direct global-to-LDS loads (gfx950): lane l of the wave moves the 16 bytes
+// at src + 16 l to dst + 16 l, for the lanes below nl; dst is the same LDS
+// address in every lane.  They count in vmcnt like other vector loads and
+// return in order, so "at most N outstanding" means that every load issued
+// before the last N has landed.
+using lds_void_t = __attribute__((address_space(3))) void;
+using gbl_void_t = __attribute__((address_space(1))) void;
+IFT_DEV void dma16_at(const void* lane_src, void* dst, bool on) {
+  if (on) __builtin_amdgcn_global_load_lds((gbl_void_t*)lane_src, (lds_void_t*)dst, 16, 0, 0);
+}
+IFT_DEV void dma16(const void* src, void* dst, int lane, int nl) {
+  dma16_at(static_cast<const char*>(src) + 16 * lane, dst, lane < nl);
+}
+// Waits until at most N vector memory loads of the wave are outstanding (a
+// compiler memory barrier too, so no LDS read moves above it).
+template <int N>
+IFT_DEV void vm_wait() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// LDS of the stacked-point kernel: the fused kernel's, plus a ring per wave
+// of PTS2_RING slots filled PTS2_RING - 1 iterations ahead by direct loads
+// that hold no registers.  Iteration i of the kernel takes w step i and, for
+// i < KXP / 4, x step i; its slot holds the B stripe of each (four rows of Bw
+// and of Bx: 32 (n + 1) and 32 (m + 1) bytes), the x stripe right after the
+// w stripe, so one wave-wide load fills it when n + m <= 30.
+constexpr int PTS2_RING = 4;
+constexpr int PTS2_SLOT = 128;   // doubles: 32 (n + m + 2) bytes <= 1 KB
+template <class D, int NT>
+struct FusedShared2 {
+  FusedShared<D, double, NT> f;
+  alignas(16) double ring[NTHR / 64][PTS2_RING][PTS2_SLOT];
+};
+
 template <class D, int NT>
 constexpr bool fused_pts2_ok() {
   return D::NC == 4 && NT <= 2 && D::NUE % 4 == 0 && (2 * D::NUE) % 16 == 0 &&
          (2 * D::NUE) / 16 < 2 * ((D::NUE + 1 + 15) / 16);
 }
 
+// Where the B stripes of one sampled element start (byte addresses; rows
+// 4 i .. 4 i + 3 of its Bw and Bx blocks are iteration i's), and the lane's
+// part of an iteration's load: lanes below 2 (n + 1) take 16 bytes of the w
+// stripe, the next 2 (m + 1) lanes 16 bytes of the x stripe.
+struct Pts2Stripes {
+  unsigned long long w, x;   // this lane's word of iteration 0
+  int sw, sx;                // stripe bytes
+  bool lx;                   // the lane loads from the x stripe
+  int nw, nwx;               // lanes of the w stripe, of both
+};
+template <class D>
+IFT_DEV Pts2Stripes pts2_stripes(const double* Bw, const double* Bx, int n, int m, int k, int lane) {
+  using O = EqOp<D>;
+  Pts2Stripes b;
+  b.sw = 32 * (n + 1);
+  b.sx = 32 * (m + 1);
+  b.nw = 2 * (n + 1);
+  b.nwx = b.nw + 2 * (m + 1);
+  b.lx = lane >= b.nw;
+  b.w = reinterpret_cast<unsigned long long>(Bw + (long long)k * O::KWP * (n + 1)) + 16ull * (unsigned)lane;
+  b.x = reinterpret_cast<unsigned long long>(Bx + (long long)k * O::KXP * (m + 1)) +
+        16ull * (unsigned)(b.lx ? lane - b.nw : 0);
+  return b;
+}
+// Issues iteration it's stripes into its slot of the wave's ring (the x
+// stripe only while there are x steps).  The per-lane choice of stripe is a
+// mask blend of the two addresses.
+template <class D>
+IFT_DEV void pts2_bdma(const Pts2Stripes& b, double* ring, int it, int lane) {
+  constexpr int KXS = EqOp<D>::KXP / 4;
+  const bool hx = it < KXS;
+  const unsigned long long mx = b.lx ? ~0ull : 0ull;
+  const unsigned long long aw = b.w + (unsigned long long)(it * b.sw);
+  const unsigned long long ax = b.x + (unsigned long long)(it * b.sx);
+  dma16_at(reinterpret_cast<const void*>((aw & ~mx) | (ax & mx)), ring + PTS2_SLOT * (it & (PTS2_RING - 1)),
+           lane < (hx ? b.nwx : b.nw));
+}
+
+// Which column tiles the w and x steps reach (bit nt: w tile nt, bit NT + nt:
+// x tile nt), fixed at compile time so that the steps carry no branches: the
+// exact set for two tiles with n > 16, else every tile (a tile past the
+// block's columns multiplies the zero column of the padded B rows).
+template <int NT>
+constexpr int pts2_tiles_all() {
+  return (1 << (2 * NT)) - 1;
+}
+constexpr int PTS2_TILES_N17 = 0b1011;   // NT = 2, 16 < n: w tiles 0 and 1, x tile 1
+template <int NT>
+__host__ __device__ inline int pts2_tiles(int n, int m) {
+  return (NT == 2 && n > 16 && n + m < 32) ? PTS2_TILES_N17 : pts2_tiles_all<NT>();
+}
+template <int MT, int NT, int MASK>
+IFT_DEV void mfma_tiles(dvec4 (&acc)[MT][NT], const double* av, const double* b) {
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    if ((MASK >> nt) & 1) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], b[nt], acc[mt][nt], 0, 0, 0);
+    }
+  }
+}
+
 // Element k at the points in the wave's slots 0 and 1 (the slot-1 data may
 // repeat slot 0: a lone last point, whose h1 the caller drops).
-template <class D, int NT>
-IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, const EqArgs& a, const double* Bw, const double* Bx,
-                             int k, dvec4 (&h0)[NT * (NT + 1) / 2], dvec4 (&h1)[NT * (NT + 1) / 2], int (&nbad)[2],
+template <class D, int NT, int TILES>
+IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, double* ring, const EqArgs& a, const double* Bw,
+                             const double* Bx, int k,
+                             dvec4 (&h0)[NT * (NT + 1) / 2], dvec4 (&h1)[NT * (NT + 1) / 2], int (&nbad)[2],
                              int (&bor)[2]) {
   static_assert(fused_pts2_ok<D, NT>(), "stacked points");
   using O = EqOp<D>;
@@ -1637,7 +1766,6 @@ IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, const EqArgs& a, co
   const int n = a.n, m = a.m, Dd = a.D;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int kl = lane >> 4, li = lane & 15;
-  const int KS = KWS + (m > 0 ? KXS : 0);
   const Pts<D, R>* P0 = &sh.u.w[wave][0].p;
   const Pts<D, R>* P1 = &sh.u.w[wave][1].p;
   // per-lane row constants: row 16 mt + li is row lr of point p
@@ -1650,19 +1778,17 @@ IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, const EqArgs& a, co
     ri[mt] = lr / D::NC;
     rc[mt] = lr % D::NC;
   }
-  int cw[NT], cx[NT];
-  bool won[NT], xon[NT];
+  // the lane's B entry of each column tile within a step's stripe
+  constexpr int WT = TILES & ((1 << NT) - 1), XT = TILES >> NT;
+  int ow[NT], ox[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int c = 16 * nt + li, jx = c - n;
-    cw[nt] = c < n ? c : n;
-    cx[nt] = (jx >= 0 && jx < m) ? jx : m;
-    won[nt] = 16 * nt < n;
-    xon[nt] = 16 * nt + 16 > n && 16 * nt < n + m;
+    ow[nt] = kl * (n + 1) + (c < n ? c : n);
+    ox[nt] = kl * (m + 1) + ((jx >= 0 && jx < m) ? jx : m);
   }
-  const double* bw = Bw + (long long)k * O::KWP * (n + 1);
-  const double* bx = Bx + (long long)k * O::KXP * (m + 1);
   const double sq = a.srho[k];
+  const Pts2Stripes bst = pts2_stripes<D>(Bw, Bx, n, m, k, lane);
   // residual entry of row `lane` of each point
   const double rv0 = lane < NUE ? double(residual_entry_p<D, R>(*P0, tab, lane)) : 0.0;
   const double rv1 = lane < NUE ? double(residual_entry_p<D, R>(*P1, tab, lane)) : 0.0;
@@ -1671,66 +1797,87 @@ IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, const EqArgs& a, co
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = dvec4{0.0, 0.0, 0.0, 0.0};
-  double bc[NT];
-  auto bload = [&](int st) {
-    st = st < KS ? st : KS - 1;
-    const bool xs = st >= KWS;
-    const int r = 4 * (xs ? st - KWS : st) + kl;
-    const double* base = xs ? bx + (long long)r * (m + 1) : bw + (long long)r * (n + 1);
+  // B values of iteration it from its ring slot, after the stripes of
+  // iteration it + PTS2_RING - 1 are issued (the caller issued the first
+  // ones) and those of iteration it have landed.  The reads are volatile so
+  // that they issue with the step's A-operand reads instead of being sunk
+  // next to the MFMAs that use them.
+  double bc[NT], bcx[NT];
+  auto bstep = [&](int it, auto hx) {
+    static_assert(PTS2_RING == 4, "the waits below count three iterations ahead");
+    if (it + 3 < KWS) {
+      pts2_bdma<D>(bst, ring, it + 3, lane);
+      vm_wait<3>();
+    } else if (it + 2 < KWS) {
+      vm_wait<2>();
+    } else if (it + 1 < KWS) {
+      vm_wait<1>();
+    } else {
+      vm_wait<0>();
+    }
+    using lds_vdouble = const volatile __attribute__((address_space(3))) double;
+    lds_vdouble* rs = (lds_vdouble*)(ring + PTS2_SLOT * (it & (PTS2_RING - 1)));
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) bc[nt] = base[xs ? cx[nt] : cw[nt]];
-  };
-  auto mfmas = [&](const double* av, const bool* on) {
+    for (int nt = 0; nt < NT; ++nt) bc[nt] = (WT >> nt) & 1 ? rs[ow[nt]] : 0.0;
+    if constexpr (decltype(hx)::value) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      if (on[nt]) {
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bc[nt], acc[mt][nt], 0, 0, 0);
-      }
+      for (int nt = 0; nt < NT; ++nt) bcx[nt] = (XT >> nt) & 1 ? rs[4 * (n + 1) + ox[nt]] : 0.0;
     }
   };
-  bload(0);
+  const std::true_type with_x, plus_side;
+  const std::false_type w_only, minus_side;
+  // Iteration i: w step i and, while i < KXS, x step i (the kernel serves
+  // ROMs with m > 0).  Both kinds open with their NQV volume steps; the x
+  // face steps then run beside the first w face steps.  Each column tile adds
+  // its k-steps in this order.
+  constexpr int XF = KXS - D::NQV;   // x face steps
+  static_assert(XF >= 0 && XF <= 6 * D::NQF, "x face steps beside the w face steps");
 #pragma unroll 1
   for (int q = 0; q < D::NQV; ++q) {
-    double av[MT];
+    bstep(q, with_x);
+    double av[MT], ax[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) av[mt] = aw_vol<D, R>(tab, *Pm[mt], ri[mt], rc[mt], q, kl);
-    mfmas(av, won);
-    bload(q + 1);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) ax[mt] = ax_vol_i<D, R>(tab, *Pm[mt], ri[mt], rc[mt], q, kl);
+    mfma_tiles<MT, NT, WT>(acc, av, bc);
+    mfma_tiles<MT, NT, XT>(acc, ax, bcx);
+  }
+  // face steps fs = (side, face, point): the minus side's 3 NQF, then the
+  // plus side's; the side is a template argument of each loop
+  constexpr int NFS = 3 * D::NQF;
+  static_assert(XF <= NFS, "x face steps beside the minus-side w face steps");
+  auto wface = [&](auto plus, int fq, double* av) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      av[mt] = aw_face_s<decltype(plus)::value, D, R>(tab, *Pm[mt], ri[mt], rc[mt], fq / D::NQF, fq % D::NQF, kl);
+  };
+#pragma unroll 1
+  for (int fs = 0; fs < XF; ++fs) {
+    bstep(D::NQV + fs, with_x);
+    double av[MT], ax[MT];
+    wface(minus_side, fs, av);
+    const int cf0 = 4 * fs + kl;
+    const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
+    const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) ax[mt] = ax_tail_i<D, R>(tab, *Pm[mt], ri[mt], rc[mt], cf) * cm;
+    mfma_tiles<MT, NT, WT>(acc, av, bc);
+    mfma_tiles<MT, NT, XT>(acc, ax, bcx);
   }
 #pragma unroll 1
-  for (int pl = 0; pl < 2; ++pl) {
-#pragma unroll 1
-    for (int fq = 0; fq < 3 * D::NQF; ++fq) {
-      double av[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-        av[mt] = aw_face<D, R>(tab, *Pm[mt], ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl);
-      mfmas(av, won);
-      bload(D::NQV + 3 * D::NQF * pl + fq + 1);
-    }
+  for (int fs = XF; fs < NFS; ++fs) {
+    bstep(D::NQV + fs, w_only);
+    double av[MT];
+    wface(minus_side, fs, av);
+    mfma_tiles<MT, NT, WT>(acc, av, bc);
   }
-  if (m > 0) {
 #pragma unroll 1
-    for (int q = 0; q < D::NQV; ++q) {
-      double av[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) av[mt] = ax_vol<D, R>(tab, *Pm[mt], ri[mt], rc[mt], q, kl);
-      mfmas(av, xon);
-      bload(KWS + q + 1);
-    }
-#pragma unroll 1
-    for (int ks = 0; ks < KXS - D::NQV; ++ks) {
-      const int cf0 = 4 * ks + kl;
-      const double cm = cf0 < O::KX - O::KXV ? 1.0 : 0.0;
-      const int cf = cf0 < O::KX - O::KXV ? cf0 : 0;
-      double av[MT];
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) av[mt] = ax_tail<D, R>(tab, *Pm[mt], ri[mt], rc[mt], cf) * cm;
-      mfmas(av, xon);
-      bload(KWS + D::NQV + ks + 1);
-    }
+  for (int fs = 0; fs < NFS; ++fs) {
+    bstep(D::NQV + NFS + fs, w_only);
+    double av[MT];
+    wface(plus_side, fs, av);
+    mfma_tiles<MT, NT, WT>(acc, av, bc);
   }
   // scale by sqrt(rho_e) and insert the residual column.  The row's point
   // picks between two shuffled registers (a select, not a blend: a
@@ -1800,13 +1947,18 @@ IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, const EqArgs& a, co
 // 2 pp + 1 (a lone last point is taken twice and written once); writes the
 // block's partial of each point.  The table must be loaded; the first
 // barrier inside makes it visible.
-template <class D, int NT>
-IFT_DEV void fused_pts2_body(FusedShared<D, double, NT>& sh, const EqArgs& a, const double* Bw, const double* Bx,
+template <class D, int NT, int TILES>
+IFT_DEV void fused_pts2_body(FusedShared2<D, NT>& sh2, const EqArgs& a, const double* Bw, const double* Bx,
                              const FusedArgs& f, int blk, int pp, int n_pts) {
   constexpr int NH = NT * (NT + 1) / 2;
-  using PR = PtsRegs<D, double>;
+  constexpr int PB = (int)sizeof(Pts<D, double>);
+  static_assert(PB % 16 == 0, "point data in 16-byte words");
+  using O = EqOp<D>;
+  static_assert(O::KWP / 4 >= PTS2_RING - 1, "the first stripes are w steps");
+  FusedShared<D, double, NT>& sh = sh2.f;
   const int p0 = 2 * pp, p1 = min(2 * pp + 1, n_pts - 1);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* ring = &sh2.ring[wave][0][0];
   dvec4 h0[NH], h1[NH];
 #pragma unroll
   for (int t = 0; t < NH; ++t) h0[t] = h1[t] = dvec4{0.0, 0.0, 0.0, 0.0};
@@ -1814,37 +1966,37 @@ IFT_DEV void fused_pts2_body(FusedShared<D, double, NT>& sh, const EqArgs& a, co
   const int kbeg = (blk * (NTHR / 64) + wave) * f.E;
   const Pts<D, double>* pb0 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p0 * a.n_s;
   const Pts<D, double>* pb1 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p1 * a.n_s;
-  // the point data of the next element are loaded into registers while the
-  // current one is assembled; each wave owns its two slots
-  typename PR::W pre[2][PR::PER];
-  if (f.E > 0 && kbeg < a.n_s) {
-    pts_regs_load<D, double>(pre[0], pb0 + kbeg, lane);
-    pts_regs_load<D, double>(pre[1], pb1 + kbeg, lane);
-  }
   __syncthreads();   // the table is loaded
   for (int e = 0; e < f.E; ++e) {
     const int k = kbeg + e;
     if (k >= a.n_s) break;
-    wave_sync();     // the slots' previous contents are consumed
-    pts_regs_store<D, double>(pre[0], &sh.u.w[wave][0].p, lane);
-    pts_regs_store<D, double>(pre[1], &sh.u.w[wave][1].p, lane);
-    if (e + 1 < f.E && k + 1 < a.n_s) {
-      pts_regs_load<D, double>(pre[0], pb0 + k + 1, lane);
-      pts_regs_load<D, double>(pre[1], pb1 + k + 1, lane);
+    wave_sync();     // the slots' and the ring's previous contents are consumed
+    // the element's point data at both points straight into the wave's
+    // slots, then the first B stripes; wait for all but those stripes
+#pragma unroll
+    for (int o = 0; o < PB; o += 1024) {
+      dma16(reinterpret_cast<const char*>(pb0 + k) + o, reinterpret_cast<char*>(&sh.u.w[wave][0].p) + o, lane,
+            (PB - o) / 16);
+      dma16(reinterpret_cast<const char*>(pb1 + k) + o, reinterpret_cast<char*>(&sh.u.w[wave][1].p) + o, lane,
+            (PB - o) / 16);
     }
+    const Pts2Stripes bst = pts2_stripes<D>(Bw, Bx, a.n, a.m, k, lane);
+#pragma unroll
+    for (int it = 0; it < PTS2_RING - 1; ++it) pts2_bdma<D>(bst, ring, it, lane);
+    vm_wait<PTS2_RING - 1>();
     wave_sync();
-    fused_elem_pts2<D, NT>(sh, a, Bw, Bx, k, h0, h1, nbad, bor);
+    fused_elem_pts2<D, NT, TILES>(sh, ring, a, Bw, Bx, k, h0, h1, nbad, bor);
   }
   fused_write_partial<D, double, NT>(sh, f, h0, nbad[0], bor[0], p0, blk);
   if (p1 != p0) fused_write_partial<D, double, NT>(sh, f, h1, nbad[1], bor[1], p1, blk);
 }
 
-template <class D, int NT>
+template <class D, int NT, int TILES>
 __global__ __launch_bounds__(NTHR, 2) void k_eq_fused_pts2(EqArgs a, const double* Bw, const double* Bx, FusedArgs f,
                                                             int n_pts) {
-  __shared__ FusedShared<D, double, NT> sh;
-  fused_load_tab<D, double, NT>(sh, threadIdx.x);
-  fused_pts2_body<D, NT>(sh, a, Bw, Bx, f, blockIdx.x, blockIdx.y, n_pts);
+  __shared__ FusedShared2<D, NT> sh;
+  fused_load_tab<D, double, NT>(sh.f, threadIdx.x);
+  fused_pts2_body<D, NT, TILES>(sh, a, Bw, Bx, f, blockIdx.x, blockIdx.y, n_pts);
 }
 
 template <class D, class R, int NT>
