@@ -754,8 +754,16 @@ static bool fused_pts2_used(const ift_rom* r, int n_pts, bool rows) {
   return !rows && n_pts >= 2 && r->precision == IFT_FP64 && pr->nc == 4 && pr->p == 2 && r->fused_nt >= 1 &&
          r->fused_nt <= 2 && r->m > 0 && r->n + r->m <= 30;
 }
+// Its blocks: two per CU in all (the kernel's occupancy), a multiple of 8 per
+// point pair, each block's elements split over its four waves (E is the most
+// any wave takes).
 static FusedLayout fused_layout_pts2(const ift_rom* r, int n_pts) {
-  return fused_layout_units(r->n_s, (n_pts + 1) / 2);
+  const long long ns = r->n_s, groups = (n_pts + 1) / 2;
+  long long nblk = (FUSED_TARGET_WAVES / 4 + groups - 1) / groups;
+  nblk = std::min(nblk, (ns + 3) / 4);
+  nblk = std::max(8LL, (nblk + 7) / 8 * 8);
+  const long long bmax = (ns + nblk - 1) / nblk;
+  return {(int)std::max(1LL, (bmax + 3) / 4), (int)nblk};
 }
 
 // (Re)allocates every workspace that scales with the number of evaluation

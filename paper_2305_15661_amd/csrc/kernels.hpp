@@ -1943,9 +1943,9 @@ IFT_DEV void fused_elem_pts2(FusedShared<D, double, NT>& sh, double* ring, const
   bor[1] |= b1;
 }
 
-// One block: sampled elements [4E blk, 4E (blk + 1)) at points 2 pp and
-// 2 pp + 1 (a lone last point is taken twice and written once); writes the
-// block's partial of each point.  The table must be loaded; the first
+// One block: its share of the sampled elements at points 2 pp and 2 pp + 1
+// (a lone last point is taken twice and written once); writes the block's
+// partial of each point.  The table must be loaded; the first
 // barrier inside makes it visible.
 template <class D, int NT, int TILES>
 IFT_DEV void fused_pts2_body(FusedShared2<D, NT>& sh2, const EqArgs& a, const double* Bw, const double* Bx,
@@ -1963,13 +1963,22 @@ IFT_DEV void fused_pts2_body(FusedShared2<D, NT>& sh2, const EqArgs& a, const do
 #pragma unroll
   for (int t = 0; t < NH; ++t) h0[t] = h1[t] = dvec4{0.0, 0.0, 0.0, 0.0};
   int nbad[2] = {0, 0}, bor[2] = {0, 0};
-  const int kbeg = (blk * (NTHR / 64) + wave) * f.E;
+  // Block blk takes the same elements at every point pair: the pair's n_s
+  // elements split as evenly as the blocks allow, then as evenly over the
+  // four waves.  Where they do not split evenly, the wave that takes one
+  // more element rotates with the block's round of 256 workgroups, so that
+  // two blocks sharing a CU put their longer waves on different SIMDs.
+  const int nb = gridDim.x;
+  const int bcnt = a.n_s / nb + (blk < a.n_s % nb ? 1 : 0);
+  const int bbeg = blk * (a.n_s / nb) + min(blk, a.n_s % nb);
+  const int wr = (wave - (int)((pp * nb + blk) >> 8)) & 3;   // the wave's rank within its block
+  const int ecnt = bcnt / 4 + (wr < bcnt % 4 ? 1 : 0);
+  const int kbeg = bbeg + wr * (bcnt / 4) + min(wr, bcnt % 4);
   const Pts<D, double>* pb0 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p0 * a.n_s;
   const Pts<D, double>* pb1 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p1 * a.n_s;
   __syncthreads();   // the table is loaded
-  for (int e = 0; e < f.E; ++e) {
+  for (int e = 0; e < ecnt; ++e) {
     const int k = kbeg + e;
-    if (k >= a.n_s) break;
     wave_sync();     // the slots' and the ring's previous contents are consumed
     // the element's point data at both points straight into the wave's
     // slots, then the first B stripes; wait for all but those stripes
