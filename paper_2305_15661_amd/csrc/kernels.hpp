@@ -1278,8 +1278,9 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
     mfmas(av, won);
     bload(q + 1);
   }
-#pragma unroll 1
-  for (int pl = 0; pl < 2; ++pl) {
+  // face steps: the minus side's, then the plus side's (the side a template
+  // argument of each loop)
+  auto wface = [&](auto plus, int pl) {
 #pragma unroll 1
     for (int fq = 0; fq < 3 * D::NQF; ++fq) {
       double av[NP][MT];
@@ -1287,11 +1288,14 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
       for (int i = 0; i < NP; ++i)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          av[i][mt] = aw_face<D, R>(tab, *P[i], ri[mt], rc[mt], pl == 1, fq / D::NQF, fq % D::NQF, kl) * rm[mt];
+          av[i][mt] = aw_face_s<decltype(plus)::value, D, R>(tab, *P[i], ri[mt], rc[mt], fq / D::NQF, fq % D::NQF,
+                                                             kl) * rm[mt];
       mfmas(av, won);
       bload(D::NQV + 3 * D::NQF * pl + fq + 1);
     }
-  }
+  };
+  wface(std::false_type(), 0);
+  wface(std::true_type(), 1);
   if (m > 0) {
 #pragma unroll 1
     for (int q = 0; q < D::NQV; ++q) {
@@ -1299,7 +1303,7 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
 #pragma unroll
       for (int i = 0; i < NP; ++i)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) av[i][mt] = ax_vol<D, R>(tab, *P[i], ri[mt], rc[mt], q, kl) * rm[mt];
+        for (int mt = 0; mt < MT; ++mt) av[i][mt] = ax_vol_i<D, R>(tab, *P[i], ri[mt], rc[mt], q, kl) * rm[mt];
       mfmas(av, xon);
       bload(KWS + q + 1);
     }
@@ -1312,7 +1316,7 @@ IFT_DEV void fused_elems4(FusedShared<D, R, NT>& sh, const EqArgs& a, const doub
 #pragma unroll
       for (int i = 0; i < NP; ++i)
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) av[i][mt] = ax_tail<D, R>(tab, *P[i], ri[mt], rc[mt], cf) * (rm[mt] * cm);
+        for (int mt = 0; mt < MT; ++mt) av[i][mt] = ax_tail_i<D, R>(tab, *P[i], ri[mt], rc[mt], cf) * (rm[mt] * cm);
       mfmas(av, xon);
       bload(KWS + D::NQV + ks + 1);
     }
