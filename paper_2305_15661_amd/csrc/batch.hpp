@@ -167,7 +167,7 @@ __global__ __launch_bounds__(NTHR_PTS, 2) void k_points_batch(const BatchInst* I
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     inst = __builtin_amdgcn_readfirstlane(batch_owner_from(L.off, n_inst, item, inst));
     const int k = item - L.off[inst];
-    points_eq_body<D, R>(s, I[inst].a, k, 0, threadIdx.x);
+    points_eq_body<D, R, true>(s, I[inst].a, k, 0, threadIdx.x);
     __syncthreads();
   }
 }

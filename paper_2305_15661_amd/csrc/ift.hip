@@ -84,6 +84,7 @@ struct ift_rom {
   double* d_PTR = nullptr;
   double* d_gram_part = nullptr;
   void* d_pts = nullptr;
+  PhysConst* d_pcs = nullptr;   // physical constants of the points of a multi-point call [max_pts]
   int fused_nt = 0;             // column tiles of the fused assembly + Gram (0: two-kernel path)
   double* d_fpart = nullptr;    // fused block partials
   int* d_fbad = nullptr;
@@ -684,6 +685,7 @@ extern "C" void ift_rom_destroy(ift_rom* r) {
   dfree(r->d_nbad);
   dfree(r->d_flag_or);
   if (r->d_pts) (void)hipFree(r->d_pts);
+  dfree(r->d_pcs);
   dfree(r->d_Bw);
   dfree(r->d_Bx);
   dfree(r->d_Bw16);
@@ -794,6 +796,7 @@ static ift_status reserve_points(ift_rom* r, int max_pts) {
   dfree(r->d_tt);
   dfree(r->d_nbad);
   dfree(r->d_flag_or);
+  dfree(r->d_pcs);
   r->max_pts = 0;
   ift_status st;
   if ((st = dalloc(&r->d_Jt, P * r->nrows * D)) != IFT_OK || (st = dalloc(&r->d_Ft, P * r->nrows)) != IFT_OK ||
@@ -804,7 +807,8 @@ static ift_status reserve_points(ift_rom* r, int max_pts) {
       (st = dalloc(&r->d_J, P)) != IFT_OK || (st = dalloc(&r->d_Jtrial, P)) != IFT_OK ||
       (st = dalloc(&r->d_dz, P * D)) != IFT_OK || (st = dalloc(&r->d_solve_out, P * 8)) != IFT_OK ||
       (st = dalloc(&r->d_wt, P * r->n)) != IFT_OK || (st = dalloc(&r->d_tt, P * std::max(r->m, 1))) != IFT_OK ||
-      (st = dalloc(&r->d_nbad, P)) != IFT_OK || (st = dalloc(&r->d_flag_or, P)) != IFT_OK)
+      (st = dalloc(&r->d_nbad, P)) != IFT_OK || (st = dalloc(&r->d_flag_or, P)) != IFT_OK ||
+      (st = dalloc(&r->d_pcs, P)) != IFT_OK)
     return st;
   if (hipMalloc(&r->d_pts, P * ns * pts_bytes(pr)) != hipSuccess) return IFT_ENOMEM;
   if (r->fused_nt > 0) {
@@ -958,6 +962,7 @@ static EqArgs eq_args(ift_rom* r, const double* mu, const double* w, const doubl
   a.D = r->D;
   a.nrows = r->nrows;
   a.mu = nullptr;
+  a.pcs = nullptr;
   a.face_s = r->d_face_s;
   a.eta_ref_s = r->d_eta_ref_s;
   a.rho = r->d_rho;
@@ -1030,6 +1035,9 @@ struct EqLaunch {
     if (jac) {
       {
         ProfScope ps(IFT_PROF_POINTS, st);
+        if (a.mu)   // the points' physical constants, which the point kernels read (dispatch_eq checks a.pcs)
+          hipLaunchKernelGGL(k_phys_points, dim3((n_pts + 63) / 64), dim3(64), 0, st, a.pc, D::PDE, a.bc_mu_scale,
+                             a.mu, n_pts, const_cast<PhysConst*>(a.pcs));
         if constexpr (pair_layout<D>())
           hipLaunchKernelGGL((k_points_eq2<D, R>), dim3(xcd_pad((a.n_s + 1) / 2), n_pts), dim3(2 * NTHR_PTS), 0, st, a);
         else
@@ -1051,6 +1059,9 @@ struct EqLaunch {
 
 static ift_status dispatch_eq(const ift_rom* r, const EqArgs& a, bool jac, int n_pts, hipStream_t st,
                               const FusedArgs* fa = nullptr) {
+  // the point kernels of the Jacobian path take a call's per-point constants
+  // from a.pcs, which their launch fills from a.mu
+  if (jac && a.mu && !a.pcs) return IFT_EINVAL;
   if (r->precision != IFT_FP64)
     with_disc(r->prob, EqLaunch<float>{a, jac, n_pts, st, r->d_Bw, r->d_Bx, fa, r->fused_nt, r->d_Bw16, r->d_Bx16});
   else
@@ -1272,6 +1283,7 @@ extern "C" ift_status eq_assemble_jacobian_batch(ift_rom* r, int n_pts, const do
   double mu0[2] = {1.0, 0.0};
   EqArgs a = eq_args(r, mu0, w, tau);
   a.mu = mu;
+  a.pcs = r->d_pcs;   // filled by the point kernels' launch
   if (r->fused_nt > 0) return eq_jacobian_fused(r, a, n_pts, H, g, Jobj, n_bad, false, stream);
   ift_status s = dispatch_eq(r, a, true, n_pts, stream);
   if (s != IFT_OK) return s;

@@ -57,6 +57,8 @@ struct EqArgs {
   const double* w;       // [pt][n]
   const double* tau;     // [pt][m]
   const double* mu;      // [pt][2] on the device, or null: use pc
+  const PhysConst* pcs;  // [pt]: the points' physical constants for the point kernels (filled by
+                         // k_phys_points from mu), or null: use pc
   double* Jt;            // [pt][nrows][D]
   double* Ft;            // [pt][nrows] (may be null for the residual kernel)
   double* Jpart;         // [pt][n_s]
@@ -83,6 +85,15 @@ IFT_DEV PhysConst phys_from_mu(const PhysConst& base, int pde, double bc_scale, 
     pc.uinf[3] = 1.0 / (base.gamma - 1.0) + 0.5 * base.gamma * M * M;
   }
   return pc;
+}
+
+// The physical constants of every evaluation point of a multi-point call,
+// once per call: the point kernels then read them with scalar loads instead
+// of each block forming them on the vector unit before its physics.
+__global__ __launch_bounds__(64) void k_phys_points(PhysConst base, int pde, double bc_scale, const double* mu,
+                                                    int n_pts, PhysConst* out) {
+  const int p = blockIdx.x * 64 + threadIdx.x;
+  if (p < n_pts) out[p] = phys_from_mu(base, pde, bc_scale, mu + 2 * p);
 }
 
 // Copies one element's point data between LDS (ElemLDS::p, 16-byte aligned)
@@ -409,12 +420,16 @@ IFT_DEV void phase_distortion_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int t
   __syncthreads();
 }
 
-template <class D, class R>
+// One element at point pt.  The point's physical constants: a.pcs[pt] (or
+// a.pc) in the multi-point calls, formed from a.mu when FROM_MU (the batched
+// kernel, whose items each carry their instance's mu).
+template <class D, class R, bool FROM_MU = false>
 IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
   load_tab<D, R, NTHR_PTS>(s, tid);
   load_eq<D, R>(s, a, k, pt, tid);
   __syncthreads();
-  const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
+  const PhysConst pc = FROM_MU ? (a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc)
+                               : (a.pcs ? a.pcs[pt] : a.pc);
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
   phase_points<D, R, true>(s, tid, pc, R(a.kappa), R(a.eps));
   __syncthreads();
@@ -442,7 +457,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   const int k = k0 + min(h, a.n_s - 1 - k0);
   load_tab<D, R, NTHR_PTS>(s[h], t);
   load_eq<D, R, sizeof(R) == 8 ? 32 : 16>(s[h], a, k, pt, t);   // ends with a barrier; FP32 takes 16-column chunks (three waves per SIMD)
-  const PhysConst pc = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc;
+  const PhysConst pc = a.pcs ? a.pcs[pt] : a.pc;
   phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return pc; }, R(a.eps));
   __syncthreads();
   phase_distortion_eq<D, R>(s[h], a, k, t);
