@@ -57,7 +57,7 @@ KBYTES = {"points": 8 * (24 * 20 + 36 * 20 + 12 * 10 + 12) + 24,
 KFLOPS = {"points": None,
           "eq_jac": 57600 + 5760 + 43200 + 1440,
           "gram": None}
-KNAMES = {"points": "k_points_eq2<Euler P2, fp64>", "eq_jac": "k_eq_fused_pts2<Euler P2, fp64, 2>",
+KNAMES = {"points": "k_phys_points + k_points_eq2<Euler P2, fp64>", "eq_jac": "k_eq_fused_pts2<Euler P2, fp64, 2, 11>",
           "gram": "k_fused_final"}
 # HBM traffic per launch of each kernel from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (KiB per dispatch) on this workload, scaled by what the same
@@ -67,10 +67,10 @@ KNAMES = {"points": "k_points_eq2<Euler P2, fp64>", "eq_jac": "k_eq_fused_pts2<E
 # of profiles/eq_jacobian_euler_p2_819x16.md, taken on the kernels as they
 # now stand; an entry must become None when its kernel changes.
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
-TRAFFIC_KIB = {"points": (4498.8, 80569.2), "eq_jac": (48563.3, 5404.0), "gram": (4286.8, 290.7)}
+TRAFFIC_KIB = {"points": (4504.5, 80570.2), "eq_jac": (48748.0, 6176.0), "gram": (4897.5, 290.7)}
 TRAFFIC_SOURCE = "profiles/eq_jacobian_euler_p2_819x16.md"
 # the full-order kernel (profiles/hdm_assemble_euler_p2_16384.md)
-HDM_TRAFFIC_KIB = (9551.3, 226304.0)
+HDM_TRAFFIC_KIB = (9551.2, 226304.0)
 # Full-order loop with Jacobians: reads U_e, the neighbour traces, x_e, X_e
 # and connectivity; writes R_e, N_e, dR/dU_e, dR/dU_e', dR/dx_e, dN/dx_e.
 HDM_BYTES_PER_ELEM = 8 * (24 + 36 + 12 + 12) + 4 * (6 + 3 + 36) + 8 * (24 + 1 + 24 * 24 + 24 * 36 + 24 * 12 + 12)

@@ -1984,15 +1984,12 @@ IFT_DEV void fused_pts2_body(FusedShared2<D, NT>& sh2, const EqArgs& a, const do
   int nbad[2] = {0, 0}, bor[2] = {0, 0};
   // Block blk takes the same elements at every point pair: the pair's n_s
   // elements split as evenly as the blocks allow, then as evenly over the
-  // four waves.  Where they do not split evenly, the wave that takes one
-  // more element rotates with the block's round of 256 workgroups, so that
-  // two blocks sharing a CU put their longer waves on different SIMDs.
+  // block's four waves.
   const int nb = gridDim.x;
   const int bcnt = a.n_s / nb + (blk < a.n_s % nb ? 1 : 0);
   const int bbeg = blk * (a.n_s / nb) + min(blk, a.n_s % nb);
-  const int wr = (wave - (int)((pp * nb + blk) >> 8)) & 3;   // the wave's rank within its block
-  const int ecnt = bcnt / 4 + (wr < bcnt % 4 ? 1 : 0);
-  const int kbeg = bbeg + wr * (bcnt / 4) + min(wr, bcnt % 4);
+  const int ecnt = bcnt / 4 + (wave < bcnt % 4 ? 1 : 0);
+  const int kbeg = bbeg + wave * (bcnt / 4) + min(wave, bcnt % 4);
   const Pts<D, double>* pb0 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p0 * a.n_s;
   const Pts<D, double>* pb1 = reinterpret_cast<const Pts<D, double>*>(a.pts) + (long long)p1 * a.n_s;
   __syncthreads();   // the table is loaded
