@@ -96,6 +96,25 @@ __global__ __launch_bounds__(64) void k_phys_points(PhysConst base, int pde, dou
   if (p < n_pts) out[p] = phys_from_mu(base, pde, bc_scale, mu + 2 * p);
 }
 
+// The physical constants of point pt in a point kernel: a.pcs[pt] through
+// the constant address space, so that they arrive by scalar loads (as a
+// select of pointers the compiler makes it a flat load), else a.pc.
+IFT_DEV PhysConst point_consts(const EqArgs& a, int pt) {
+  using cpc = const __attribute__((address_space(4))) PhysConst;
+  PhysConst pc = a.pc;
+  if (a.pcs) {
+    cpc* q = (cpc*)a.pcs + pt;
+    pc.gamma = q->gamma;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pc.uinf[c] = q->uinf[c];
+    pc.src_amp = q->src_amp;
+    pc.src_b = q->src_b;
+    pc.all_farfield = q->all_farfield;
+    pc.bc_st = q->bc_st;
+  }
+  return pc;
+}
+
 // Copies one element's point data between LDS (ElemLDS::p, 16-byte aligned)
 // and the point workspace, whose element slots start at multiples of the
 // FP64 point-data size from a 256-byte aligned base: 16-byte words where
@@ -107,6 +126,27 @@ IFT_DEV void copy_pts(Pts<D, R>* dst, const Pts<D, R>* src, int tid) {
 }
 
 // ------------------------------------------------------------------ loaders
+// Direct global-to-LDS loads (gfx950): lane l of the wave moves the 16 bytes
+// at src + 16 l to dst + 16 l, for the lanes below nl; dst is the same LDS
+// address in every lane.  They count in vmcnt like other vector loads and
+// return in order, so "at most N outstanding" means that every load issued
+// before the last N has landed.
+using lds_void_t = __attribute__((address_space(3))) void;
+using gbl_void_t = __attribute__((address_space(1))) void;
+IFT_DEV void dma16_at(const void* lane_src, void* dst, bool on) {
+  if (on) __builtin_amdgcn_global_load_lds((gbl_void_t*)lane_src, (lds_void_t*)dst, 16, 0, 0);
+}
+IFT_DEV void dma16(const void* src, void* dst, int lane, int nl) {
+  dma16_at(static_cast<const char*>(src) + 16 * lane, dst, lane < nl);
+}
+// Waits until at most N vector memory loads of the wave are outstanding (a
+// compiler memory barrier too, so no LDS read moves above it).
+template <int N>
+IFT_DEV void vm_wait() {
+  static_assert(N >= 0 && N < 16, "vmcnt immediate");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
 // acc + sum_j row[j * stride] v[j], accumulated in index order.  The loads
 // of a chunk of CH terms are issued together: summed in a plain loop, each
 // term would wait for its own load (a cache round trip per basis
@@ -429,7 +469,7 @@ IFT_DEV void points_eq_body(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, in
   load_eq<D, R>(s, a, k, pt, tid);
   __syncthreads();
   const PhysConst pc = FROM_MU ? (a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu + 2 * pt) : a.pc)
-                               : (a.pcs ? a.pcs[pt] : a.pc);
+                               : point_consts(a, pt);
   static_assert(n_point_tasks<D, true>() <= NTHR_PTS, "one task per thread");
   phase_points<D, R, true>(s, tid, pc, R(a.kappa), R(a.eps));
   __syncthreads();
@@ -457,7 +497,7 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   const int k = k0 + min(h, a.n_s - 1 - k0);
   load_tab<D, R, NTHR_PTS>(s[h], t);
   load_eq<D, R, sizeof(R) == 8 ? 32 : 16>(s[h], a, k, pt, t);   // ends with a barrier; FP32 takes 16-column chunks (three waves per SIMD)
-  const PhysConst pc = a.pcs ? a.pcs[pt] : a.pc;
+  const PhysConst pc = point_consts(a, pt);
   phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return pc; }, R(a.eps));
   __syncthreads();
   phase_distortion_eq<D, R>(s[h], a, k, t);
@@ -1664,27 +1704,6 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
 // every element and point are those of the one-point kernel in the same
 // order, so each element's M_e and Gram term are the same; only the grouping
 // of elements into waves and blocks differs.
-// Direct global-to-LDS loads (gfx950): lane l of the wave moves the 16 bytes
-// at src + 16 l to dst + 16 l, for the lanes below nl; dst is the same LDS
-// address in every lane.  They count in vmcnt like other vector loads and
-// return in order, so "at most N outstanding" means that every load issued
-// before the last N has landed.
-using lds_void_t = __attribute__((address_space(3))) void;
-using gbl_void_t = __attribute__((address_space(1))) void;
-IFT_DEV void dma16_at(const void* lane_src, void* dst, bool on) {
-  if (on) __builtin_amdgcn_global_load_lds((gbl_void_t*)lane_src, (lds_void_t*)dst, 16, 0, 0);
-}
-IFT_DEV void dma16(const void* src, void* dst, int lane, int nl) {
-  dma16_at(static_cast<const char*>(src) + 16 * lane, dst, lane < nl);
-}
-// Waits until at most N vector memory loads of the wave are outstanding (a
-// compiler memory barrier too, so no LDS read moves above it).
-template <int N>
-IFT_DEV void vm_wait() {
-  static_assert(N >= 0 && N < 16, "vmcnt immediate");
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-
 // LDS of the stacked-point kernel: the fused kernel's, plus a ring per wave
 // of PTS2_RING slots filled PTS2_RING - 1 iterations ahead by direct loads
 // that hold no registers.  Iteration i of the kernel takes w step i and, for
