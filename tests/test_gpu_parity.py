@@ -308,6 +308,40 @@ def test_batched_points_pairs_and_lone_point(P, euler_case):
         assert nb.cpu().numpy()[j] == single["n_bad"]
 
 
+@pytest.mark.parametrize("n,m", [(12, 12), (8, 4), (21, 10)])
+def test_batched_points_column_tiles(n, m, dev):
+    """Multi-point FP64 calls across the stacked-point kernel's column-tile
+    cases: two tiles with n <= 16 (every tile reached), one tile, and
+    n + m = 31, which the one-point kernel takes.  Five points (two pairs and
+    a lone point), each against its single call and the oracle."""
+    import torch
+    case = Case(synth.euler_p2(nx=16, ny=8, n=n, m=m, n_s=64), dev)
+    wl, r, d = case.wl, case.rom, case.dev
+    idx = [3, 0, 11, 5, 8]
+    P = len(idx)
+    _say(f"batched eq assembly n={n} m={m} x{P}")
+    r.reserve(P)
+    mu2 = np.zeros((P, 2))
+    mu2[:, :wl.mus.shape[1]] = wl.mus[idx]
+    MU, W, T = _t(mu2, d), _t(wl.w_eval[idx], d), _t(wl.tau_eval[idx], d)
+    J, G, H = _z(P, d), _z(P * r.D, d), _z(P * r.D * r.D, d)
+    nb = _z(P, d, torch.int32)
+    r.eq_assemble_jacobian_batch(MU, W, T, J, G, H, nb)
+    torch.cuda.synchronize()
+    J, G, H = J.cpu().numpy(), G.cpu().numpy().reshape(P, r.D), H.cpu().numpy().reshape(P, r.D, r.D)
+    for j, k in enumerate(idx):
+        single = _eq_gpu(case, wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
+        oj = case.orom.jacobian(wl.mus[k], wl.w_eval[k], wl.tau_eval[k])
+        assert nb.cpu().numpy()[j] == single["n_bad"]
+        if np.isinf(oj["J"]):   # an invalid lifted state: J~ = +inf, counted
+            assert np.isinf(J[j]) and single["n_bad"] > 0
+            continue
+        assert single["n_bad"] == 0
+        assert rel(G[j], single["g"]) < 1e-14 and rel(H[j], single["H"]) < 1e-14
+        assert rel(G[j], oj["g"]) < 1e-12 and rel(H[j], oj["H"]) < 1e-12
+        assert abs(J[j] - oj["J"]) <= 1e-12 * oj["J"]
+
+
 @pytest.mark.parametrize("which", ["tiny_case", "st_case"])
 def test_gauss_newton_steps_parity(which, request):
     """Twenty steps from the plain start; each GPU step is compared with the
