@@ -167,7 +167,9 @@ __global__ __launch_bounds__(NTHR_PTS, 2) void k_points_batch(const BatchInst* I
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     inst = __builtin_amdgcn_readfirstlane(batch_owner_from(L.off, n_inst, item, inst));
     const int k = item - L.off[inst];
-    points_eq_body<D, R, true>(s, I[inst].a, k, 0, threadIdx.x);
+    int tid_i = threadIdx.x;   // formed again per item (kept live across the loop, the task indices spill)
+    asm volatile("" : "+v"(tid_i));
+    points_eq_body<D, R, true>(s, I[inst].a, k, 0, tid_i);
     __syncthreads();
   }
 }
@@ -182,17 +184,22 @@ __global__ __launch_bounds__(2 * NTHR_PTS, sizeof(R) == 4 ? 3 : 2) void k_points
   __shared__ ElemLDS<D, R> s[2];
   __shared__ PhysConst spc[2];
   const int total = L.cnt[0];
-  const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
+  const int tid = threadIdx.x, h = __builtin_amdgcn_readfirstlane(tid / NTHR_PTS);
   int inst = 0;
-  load_tab<D, R, NTHR_PTS>(s[h], t);   // constant: visible after the first barrier
+  load_tab<D, R, NTHR_PTS>(s[h], tid % NTHR_PTS);   // constant: visible after the first barrier
   for (int i0 = 2 * blockIdx.x; i0 < total; i0 += 2 * gridDim.x) {
+    // The lane's task indices are formed again for each item from an opaque
+    // copy of the thread index: kept live across the loop they spill.
+    int tid_i = tid;
+    asm volatile("" : "+v"(tid_i));
+    const int t = tid_i % NTHR_PTS;
     const int item = i0 + min(h, total - 1 - i0);
     inst = __builtin_amdgcn_readfirstlane(batch_owner_from(L.off, n_inst, item, inst));
     const int k = item - L.off[inst];
     const EqArgs& a = I[inst].a;
     if (t == 0) spc[h] = a.mu ? phys_from_mu(a.pc, D::PDE, a.bc_mu_scale, a.mu) : a.pc;
     load_eq<D, R>(s[h], a, k, 0, t);   // ends with a barrier
-    phase_points_pair<D, R>(s, tid, [&](int e) -> const PhysConst& { return spc[e]; }, R(a.eps));
+    phase_points_pair<D, R>(s, tid_i, [&](int e) -> const PhysConst& { return spc[e]; }, R(a.eps));
     __syncthreads();
     phase_distortion_eq<D, R>(s[h], a, k, t);
     if (item == i0 + h) copy_pts<D, R, NTHR_PTS>(reinterpret_cast<Pts<D, R>*>(a.pts) + k, &s[h].p, t);
