@@ -308,18 +308,19 @@ def test_batched_points_pairs_and_lone_point(P, euler_case):
         assert nb.cpu().numpy()[j] == single["n_bad"]
 
 
-@pytest.mark.parametrize("n,m", [(12, 12), (8, 4), (21, 10)])
-def test_batched_points_column_tiles(n, m, dev):
+@pytest.mark.parametrize("n,m,n_s", [(12, 12, 64), (8, 4, 64), (21, 10, 64), (20, 10, 3)])
+def test_batched_points_column_tiles(n, m, n_s, dev):
     """Multi-point FP64 calls across the stacked-point kernel's column-tile
     cases: two tiles with n <= 16 (every tile reached), one tile, and
-    n + m = 31, which the one-point kernel takes.  Five points (two pairs and
-    a lone point), each against its single call and the oracle."""
+    n + m = 31, which the one-point kernel takes; and three sampled elements,
+    which leave most of its blocks without an element.  Five points (two
+    pairs and a lone point), each against its single call and the oracle."""
     import torch
-    case = Case(synth.euler_p2(nx=16, ny=8, n=n, m=m, n_s=64), dev)
+    case = Case(synth.euler_p2(nx=16, ny=8, n=n, m=m, n_s=n_s), dev)
     wl, r, d = case.wl, case.rom, case.dev
     idx = [3, 0, 11, 5, 8]
     P = len(idx)
-    _say(f"batched eq assembly n={n} m={m} x{P}")
+    _say(f"batched eq assembly n={n} m={m} n_s={n_s} x{P}")
     r.reserve(P)
     mu2 = np.zeros((P, 2))
     mu2[:, :wl.mus.shape[1]] = wl.mus[idx]
