@@ -1700,10 +1700,12 @@ IFT_DEV void fused_body(FusedShared<D, R, NT>& sh, const EqArgs& a, const double
 // residual rows fill the MFMA row tiles (three for Euler P2, where two
 // elements at one point take four, their distortion rows padding a tile
 // each), and the B operands serve both.  A point's distortion row enters its
-// Gram as a k-block of its own after its residual rows: the k-blocks of
-// every element and point are those of the one-point kernel in the same
-// order, so each element's M_e and Gram term are the same; only the grouping
-// of elements into waves and blocks differs.
+// Gram as a k-block of its own after its residual rows.  The x k-blocks run
+// beside the w k-blocks (below), but within a column tile they reach
+// disjoint columns, so every entry of M_e sums its terms in the one-point
+// kernel's order and each element's M_e and Gram term are the same; only
+// the grouping of elements into waves and blocks differs.
+
 // LDS of the stacked-point kernel: the fused kernel's, plus a ring per wave
 // of PTS2_RING slots filled PTS2_RING - 1 iterations ahead by direct loads
 // that hold no registers.  Iteration i of the kernel takes w step i and, for
