@@ -217,9 +217,13 @@ IFT_DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, int nbytes) {
 // <= 64) go through cl, 64 LDS slots of this wave: lane j writes v_j (zero
 // from n on) once the first chunk's loads are issued, and the products read
 // them back as broadcasts (LDS operations of a wave complete in order).
-template <int CH, bool PAIR = false>
+// during() runs once there too, while those loads are in flight.
+struct NoOp {
+  IFT_DEV void operator()() const {}
+};
+template <int CH, bool PAIR = false, class F = NoOp>
 IFT_DEV void lift_col_dot(__amdgpu_buffer_rsrc_t B, bool own, int lane_bytes, int cstride, const double* v, double* cl,
-                          int n, double init, double& acc, double& acc2) {
+                          int n, double init, double& acc, double& acc2, const F& during = F()) {
   static_assert(64 % CH == 0, "chunks tile the 64 coefficient slots");
   const int lane = threadIdx.x & 63;
   acc = 0.0;
@@ -242,7 +246,10 @@ IFT_DEV void lift_col_dot(__amdgpu_buffer_rsrc_t B, bool own, int lane_bytes, in
         }
       }
     }
-    if (j0 == 0) cl[lane] = lane < n ? v[lane] : 0.0;
+    if (j0 == 0) {
+      cl[lane] = lane < n ? v[lane] : 0.0;
+      during();
+    }
     __builtin_amdgcn_sched_barrier(0);   // every load of the chunk issues before the first product
     if (j0 == 0) acc = init;
 #pragma unroll
@@ -257,7 +264,10 @@ IFT_DEV void lift_col_dot(__amdgpu_buffer_rsrc_t B, bool own, int lane_bytes, in
       if constexpr (PAIR) acc2 += r2[u] * cc[u];
     }
   }
-  if (n <= 0) acc = init;
+  if (n <= 0) {   // no chunk: the hook still runs once
+    during();
+    acc = init;
+  }
 }
 
 // Lift U_e = Phi_e w, U_e' = Phi_e' w, x_e = X_e + Psi_e tau for one
@@ -272,8 +282,10 @@ IFT_DEV void lift_col_dot(__amdgpu_buffer_rsrc_t B, bool own, int lane_bytes, in
 // n <= CH (x rows: m <= 16).  k must be uniform across
 // each wave.  Ends with a barrier: everything it wrote is visible to the
 // block.
-template <class D, class R, int CH = 16>
-IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) {
+// during() runs in both waves once the lift's first loads are issued (work
+// whose own loads then wait beside the lift's, such as the table copy).
+template <class D, class R, int CH = 16, class F = NoOp>
+IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid, const F& during = F()) {
   constexpr int RU = D::NUE + D::NUN;
   constexpr bool PAIR = RU % 2 == 0;          // two U rows per lane (16-byte loads)
   constexpr int NU = PAIR ? RU / 2 : RU;      // lanes of the U rows
@@ -285,7 +297,7 @@ IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) 
     const int r0 = PAIR ? 2 * min(lane, NU - 1) : min(lane, NU - 1);
     const auto B = buf_rsrc(a.LiftU + (long long)ku * n * RU, n * RU * 8);
     double acc, acc2;
-    lift_col_dot<CH, PAIR>(B, lane < NU, r0 * 8, RU * 8, a.w + (long long)pt * n, s.cf[0], n, 0.0, acc, acc2);
+    lift_col_dot<CH, PAIR>(B, lane < NU, r0 * 8, RU * 8, a.w + (long long)pt * n, s.cf[0], n, 0.0, acc, acc2, during);
     if (lane < NU) {
       if (r0 < D::NUE) s.U[r0] = R(acc);
       else s.Un[r0 - D::NUE] = R(acc);
@@ -301,7 +313,8 @@ IFT_DEV void load_eq(ElemLDS<D, R>& s, const EqArgs& a, int k, int pt, int tid) 
     const double er = a.eta_ref_s[ku];
     const auto B = buf_rsrc(a.LiftX + (long long)ku * m * D::NXE, m * D::NXE * 8);
     double acc, unused;
-    lift_col_dot<16>(B, lane < D::NXE, q * 8, D::NXE * 8, a.tau + (long long)pt * m, s.cf[1], m, X, acc, unused);
+    lift_col_dot<16>(B, lane < D::NXE, q * 8, D::NXE * 8, a.tau + (long long)pt * m, s.cf[1], m, X, acc, unused,
+                     during);
     if (lane < D::NXE) {
       s.x[q] = R(acc);
       s.X[q] = R(X);
@@ -495,8 +508,9 @@ __global__ __launch_bounds__(2 * NTHR_PTS) void k_points_eq2(EqArgs a) {
   if (k0 >= a.n_s) return;   // padding blocks (whole block)
   const int tid = threadIdx.x, h = tid / NTHR_PTS, t = tid % NTHR_PTS;
   const int k = k0 + min(h, a.n_s - 1 - k0);
-  load_tab<D, R, NTHR_PTS>(s[h], t);
-  load_eq<D, R, sizeof(R) == 8 ? 32 : 16>(s[h], a, k, pt, t);   // ends with a barrier; FP32 takes 16-column chunks (three waves per SIMD)
+  // ends with a barrier; FP32 takes 16-column chunks (three waves per SIMD).  The
+  // reference table is copied once the lift's first loads are in flight.
+  load_eq<D, R, sizeof(R) == 8 ? 32 : 16>(s[h], a, k, pt, t, [&] { load_tab<D, R, NTHR_PTS>(s[h], t); });
   const PhysConst pc = point_consts(a, pt);
   phase_points_pair<D, R>(s, tid, [&](int) -> const PhysConst& { return pc; }, R(a.eps));
   __syncthreads();
